@@ -1,0 +1,347 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check here reaches its expected value by a route that does not use the
+oracle's segment enumeration: values printed in the paper (tests/golden),
+LP solves, scalar maximisation, grid search, closed forms (water-filling,
+knapsack), and invariants of duality (§3).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import brute
+
+LOG, CAPLIN = 0, 1
+
+
+# ---------------------------------------------------------------- §4.1 -----
+
+def test_worked_example_cost_curve(golden_dir):
+    G = json.load(open(os.path.join(golden_dir, "worked_example.json")))
+    a, p = G["a"], G["p"]
+    for t, cv in zip(G["kinks_t"], G["kinks_cost"]):
+        assert oracle.cost(a, p, t) == pytest.approx(cv, abs=1e-12)
+    # affine between kinks, from the kink values alone
+    for t in np.linspace(0, 5, 41):
+        ks, cs = G["kinks_t"], G["kinks_cost"]
+        assert oracle.cost(a, p, t) == pytest.approx(float(np.interp(t, ks, cs)), abs=1e-12)
+    assert math.isinf(oracle.cost(a, p, 5.01))
+
+
+def test_worked_example_supports(golden_dir):
+    """For 0 <= t <= 2 only resource 2 is used, for 2 < t < 5 resources 2 and
+    4, at t = 5 only resource 4; resources 1 and 3 never (1-based)."""
+    G = json.load(open(os.path.join(golden_dir, "worked_example.json")))
+    a, p = G["a"], G["p"]
+    never = {j - 1 for j in G["never_used_1based"]}
+    # sweep the optimum along the whole curve with log utilities of many weights
+    for w in np.geomspace(0.05, 50, 60):
+        J = oracle.subproblem(a, p, LOG, w, 0.0, 0.0)
+        used = {j for j, x in ((J["jlo"], J["xlo"]), (J["jhi"], J["xhi"])) if j >= 0 and x > 0}
+        assert not (used & never)
+        if J["t"] < 2 - 1e-12:
+            assert used == {1}
+        elif 2 + 1e-12 < J["t"] < 5 - 1e-12:
+            assert used == {1, 3}
+    J = oracle.subproblem(a, p, LOG, 1e9, 0.0, 0.0)  # cheap enough: t = 5
+    assert J["t"] == pytest.approx(5.0)
+    assert J["jhi"] == 3 and J["xhi"] == pytest.approx(1.0)
+
+
+def test_worked_example_net_utility(golden_dir):
+    """u = log t: optimum at the vertex t = 2; u = 4 log t: t = 2.4 with
+    x_2 = 13/15, x_4 = 2/15 (the paper's 't about 2.4')."""
+    G = json.load(open(os.path.join(golden_dir, "worked_example.json")))
+    a, p = G["a"], G["p"]
+    J = oracle.subproblem(a, p, LOG, 1.0, 0.0, 0.0)
+    assert J["t"] == pytest.approx(2.0, abs=1e-12)
+    assert J["v"] == pytest.approx(math.log(2.0) - 1.0, abs=1e-12)
+    J = oracle.subproblem(a, p, LOG, 4.0, 0.0, 0.0)
+    assert J["t"] == pytest.approx(G["net_utility_optimum_t_approx"], abs=1e-12)
+    assert (J["jlo"], J["jhi"]) == (1, 3)
+    assert J["xlo"] == pytest.approx(13 / 15, abs=1e-12)
+    assert J["xhi"] == pytest.approx(2 / 15, abs=1e-12)
+    # independent route: golden section on u - c_LP
+    t, v = brute.job_golden(a, p, LOG, 4.0, 0.0, 1e-12)
+    assert t == pytest.approx(2.4, abs=1e-6)
+
+
+def test_cost_matches_lp():
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        m = int(rng.integers(1, 6))
+        a = rng.random(m) * 3
+        p = rng.random(m) * 2
+        for t in rng.random(4) * a.max():
+            assert oracle.cost(a, p, t) == pytest.approx(brute.cost_lp(a, p, t), abs=1e-9)
+
+
+def test_cost_convex_increasing():
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        m = int(rng.integers(2, 7))
+        a = rng.random(m) + 0.05
+        p = rng.random(m)
+        ts = np.linspace(0, a.max(), 201)
+        cs = np.array([oracle.cost(a, p, t) for t in ts])
+        assert cs[0] == 0.0
+        assert np.all(np.diff(cs) >= -1e-12)
+        assert np.all(cs[:-2] + cs[2:] - 2 * cs[1:-1] >= -1e-9)
+
+
+# ---------------------------------------------------------------- §4.2 -----
+
+@pytest.mark.parametrize("kind", [LOG, CAPLIN])
+def test_segment_argmax_vs_scalar(kind):
+    rng = np.random.default_rng(13 + kind)
+    for _ in range(200):
+        g = rng.random() * 2
+        d = g + rng.random() * 2 + 1e-3
+        alpha = rng.random() * 3 + 1e-3
+        w = 0.5 + 1.5 * rng.random()
+        c = rng.random() * 4
+        eps = 1e-3
+        t = oracle.segment_argmax(kind, w, c, eps, alpha, g, d)
+        v = brute.u(kind, w, c, eps, t) - alpha * t
+        tn, vn = brute.segment_scalar(kind, w, c, eps, alpha, 0.0, g, d)
+        assert v >= vn - 1e-9
+        assert g - 1e-15 <= t <= d + 1e-15
+        if kind == LOG:
+            assert t == pytest.approx(tn, abs=1e-6)
+
+
+def test_segment_target_priority_table_cases():
+    """All four cases of the capped-linear maximiser, incl. w > alpha, c < gamma."""
+    f = lambda w, c, al, g, d: oracle.segment_argmax(CAPLIN, w, c, 0.0, al, g, d)
+    assert f(1.0, 1.5, 2.0, 1.0, 2.0) == 1.0  # w <= alpha -> gamma
+    assert f(3.0, 1.5, 2.0, 1.0, 2.0) == 1.5  # target inside
+    assert f(3.0, 2.5, 2.0, 1.0, 2.0) == 2.0  # target beyond delta
+    assert f(3.0, 0.5, 2.0, 1.0, 2.0) == 1.0  # target below gamma (table gap)
+
+
+def test_subproblem_vs_lp_golden():
+    rng = np.random.default_rng(14)
+    for it in range(30):
+        m = int(rng.integers(1, 6))
+        a = rng.random(m) * 2 + 0.01
+        p = rng.random(m) * 2 + 0.01
+        kind = it % 2
+        w = 0.5 + 1.5 * rng.random()
+        c = 0.5 + 1.5 * rng.random()
+        J = oracle.subproblem(a, p, kind, w, c, 1e-3)
+        t, v = brute.job_golden(a, p, kind, w, c, 1e-3)
+        assert J["v"] == pytest.approx(v, abs=1e-7)
+        if kind == LOG:
+            assert J["t"] == pytest.approx(t, abs=1e-5)
+        # the reported allocation realises t and v
+        x = np.zeros(m)
+        if J["jlo"] >= 0:
+            x[J["jlo"]] += J["xlo"]
+        if J["jhi"] >= 0:
+            x[J["jhi"]] += J["xhi"]
+        assert np.all(x >= -1e-15) and x.sum() <= 1 + 1e-12
+        assert float(a @ x) == pytest.approx(J["t"], abs=1e-12)
+        assert brute.u(kind, w, c, 1e-3, J["t"]) - float(p @ x) == pytest.approx(J["v"], abs=1e-12)
+
+
+def test_subproblem_vs_simplex_grid():
+    rng = np.random.default_rng(15)
+    h = 2e-3
+    for it in range(12):
+        m = 1 + it % 3
+        a = rng.random(m) * 2 + 0.05
+        p = rng.random(m) * 2 + 0.05
+        kind = it % 2
+        w, c = 0.5 + 1.5 * rng.random(), 0.5 + 1.5 * rng.random()
+        J = oracle.subproblem(a, p, kind, w, c, 1e-3)
+        vg, _ = brute.job_grid(a, p, kind, w, c, 1e-3, h=h if m < 3 else 1e-2)
+        L = (w * a.max() / 1e-3 if kind == LOG else w * a.max()) + p.max()
+        assert J["v"] >= vg - 1e-12
+        assert J["v"] <= vg + L * m * (h if m < 3 else 1e-2)
+
+
+def test_subproblem_zero_row_and_zero_price():
+    J = oracle.subproblem([0.0, 0.0], [1.0, 1.0], LOG, 2.0, 0.0, 1e-3)
+    assert J["t"] == 0.0 and J["jhi"] == -1 and J["v"] == pytest.approx(2 * math.log(1e-3))
+    J = oracle.subproblem([0.0, 0.0], [1.0, 1.0], CAPLIN, 2.0, 1.0, 1e-3)
+    assert J["t"] == 0.0 and J["v"] == 0.0
+    # a free resource: take all of the best free one
+    J = oracle.subproblem([0.5, 2.0, 1.0], [0.0, 0.0, 3.0], LOG, 1.0, 0.0, 1e-3)
+    assert J["t"] == pytest.approx(2.0) and J["jhi"] == 1 and J["v"] == pytest.approx(math.log(2.001))
+
+
+# ------------------------------------------------------------ §3 duality ---
+
+def _inst(n, m, seed, **kw):
+    return synth.random_small(n, m, seed, **kw)
+
+
+def test_weak_duality_random_prices():
+    I = _inst(300, 4, 1)
+    rng = np.random.default_rng(16)
+    for _ in range(10):
+        p = rng.random(4) * 3
+        d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+        U, du = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, d.r, d.jobs)
+        assert d.g >= U - 1e-9
+        # the scaled allocation is feasible
+        X = oracle.dense_allocation(I.n, I.m, d.jobs)
+        s = np.where(d.r > I.R, I.R / np.maximum(d.r, 1e-300), 1.0)
+        Xs = X * s[None, :]
+        assert np.all(Xs.sum(0) <= I.R * (1 + 1e-12))
+        assert np.all(Xs.sum(1) <= 1 + 1e-12)
+        # better-conditioned form of the gap agrees
+        assert d.g - U == pytest.approx(float(p @ (I.R - d.r)) + du, rel=1e-9, abs=1e-9)
+
+
+def test_dual_convex_along_segments():
+    I = _inst(200, 3, 2)
+    rng = np.random.default_rng(17)
+    for _ in range(10):
+        p1, p2 = rng.random(3) * 3, rng.random(3) * 3
+        g = lambda p: oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p).g
+        for th in (0.25, 0.5, 0.75):
+            assert g(th * p1 + (1 - th) * p2) <= th * g(p1) + (1 - th) * g(p2) + 1e-9
+
+
+def test_danskin_gradient_finite_difference():
+    """q = R - r is the gradient of g where g is differentiable (§3)."""
+    I = _inst(60, 3, 3, log_frac=1.0)
+    rng = np.random.default_rng(18)
+    for _ in range(5):
+        p = 0.5 + rng.random(3) * 2
+        d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p)
+        for j in range(3):
+            h = 1e-6
+            e = np.zeros(3)
+            e[j] = h
+            gp = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p + e).g
+            gm = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p - e).g
+            assert (gp - gm) / (2 * h) == pytest.approx(I.R[j] - d.r[j], rel=1e-6, abs=1e-6)
+
+
+def test_upper_bound_max_throughput():
+    """U* <= sum_i u_i(max_j a_ij) (§2.4) and g(p*) >= U*."""
+    I = _inst(200, 4, 4)
+    p, info = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=1e-9, max_iter=200)
+    ub = sum(brute.u(I.kind[i], I.w[i], I.c[i], I.eps, I.T[i].max()) for i in range(I.n))
+    assert info["U"] <= ub + 1e-9
+    assert info["g"] >= info["U"] - 1e-9
+
+
+# ----------------------------------------------------- whole problem pins ---
+
+def test_problem_grid_tiny():
+    rng = np.random.default_rng(19)
+    for it in range(3):
+        n, m = 2, 2
+        T = rng.random((n, m)) + 0.1
+        kind = np.array([it % 2, (it + 1) % 2], np.uint8)
+        w = 0.5 + 1.5 * rng.random(n)
+        c = 0.5 + 1.5 * rng.random(n)
+        R = np.array([0.6, 0.5])
+        eps = 0.05
+        h = 0.02
+        Ug = brute.problem_grid(T, kind, w, c, eps, R, h=h)
+        p, info = oracle.solve(T, w, c, kind, eps, R, tol_rel=1e-10, max_iter=400)
+        Lip = float(np.max(w[:, None] * T) / eps) * 2
+        # strong duality: the dual optimum equals U*; grid is within L*h below it
+        assert Ug <= info["g"] + 1e-7
+        assert info["g"] <= Ug + Lip * h * m
+
+
+def test_waterfilling_single_resource():
+    rng = np.random.default_rng(20)
+    n = 2000
+    a = 0.1 + 0.9 * rng.random(n)
+    w = 0.5 + 1.5 * rng.random(n)
+    R = 300.0
+    ps, Us = brute.waterfill_m1(a, w, 1e-3, R)
+    T = a[:, None]
+    p, info = oracle.solve(T, w, np.zeros(n), np.zeros(n, np.uint8), 1e-3, np.array([R]),
+                           tol_rel=1e-12, max_iter=300)
+    assert p[0] == pytest.approx(ps, rel=1e-7)
+    assert info["g"] == pytest.approx(Us, rel=1e-9)
+    assert info["U"] == pytest.approx(Us, rel=1e-9)
+
+
+def test_identical_jobs_knapsack():
+    a = np.array([0.3, 0.9, 0.6])
+    n = 500
+    R = np.array([200.0, 100.0, 120.0])
+    T = np.tile(a, (n, 1))
+    w = np.ones(n)
+    tau = brute.knapsack_identical(a, R, n)
+    Ustar = n * math.log(tau + 1e-3)
+    p, info = oracle.solve(T, w, np.zeros(n), np.zeros(n, np.uint8), 1e-3, R, tol_rel=1e-12,
+                           max_iter=400)
+    # the dual optimum is U* (strong duality); the scaled recovery can lose
+    # whole jobs at the massive tie, so only the upper bound is tight here
+    assert info["g"] == pytest.approx(Ustar, rel=1e-7)
+    assert info["U"] <= Ustar + 1e-9
+
+
+def test_linear_utility_lp():
+    """Capped-linear with c >= max_j a_ij is linear utility: U* is an LP."""
+    I = _inst(80, 3, 5)
+    c = np.full(I.n, 10.0)
+    kind = np.ones(I.n, np.uint8)
+    Ulp = brute.lp_linear(I.T, I.w, I.R)
+    p, info = oracle.solve(I.T, I.w, c, kind, I.eps, I.R, tol_rel=1e-10, max_iter=400)
+    assert info["g"] == pytest.approx(Ulp, rel=1e-7)
+
+
+def test_price_is_sensitivity_of_optimum():
+    """p* = grad_R U*(R) (§3, eq. e-pstar-grad), by central differences of the
+    dual optimum g(p*) = U* in R."""
+    I = _inst(400, 3, 6, log_frac=1.0)
+    p, info = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=1e-12, max_iter=300)
+    for j in range(3):
+        h = 2.0
+        e = np.zeros(3)
+        e[j] = h
+        _, ip = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R + e, p0=p, tol_rel=1e-12,
+                             max_iter=300)
+        _, im = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R - e, p0=p, tol_rel=1e-12,
+                             max_iter=300)
+        assert (ip["g"] - im["g"]) / (2 * h) == pytest.approx(p[j], rel=2e-2)
+
+
+def test_kkt_at_convergence():
+    I = _inst(20000, 4, 7, log_frac=1.0)
+    p, info = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=1e-6, max_iter=200)
+    # the column-scaling recovery leaves a floor of order 1/n at ties
+    assert info["rel_gap"] <= 5e-5
+    d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+    X = oracle.dense_allocation(I.n, I.m, d.jobs)
+    assert np.all((X > 0).sum(1) <= 2)
+    s = np.where(d.r > I.R, I.R / d.r, 1.0)
+    rt = (X * s).sum(0)
+    assert np.all(rt <= I.R * (1 + 1e-12))
+    # complementary slackness: priced resources are (nearly) used up
+    gap = info["g"] - info["U"]
+    assert np.all(p * (I.R - rt) <= gap + 1e-9)
+    assert np.all(p >= 0)
+
+
+def test_trace_example_gap_definition(golden_dir):
+    """The printed gap is dual value per job minus utility per job (§6.1)."""
+    G = json.load(open(os.path.join(golden_dir, "trace_example.json")))
+    for L in G["lines"]:
+        assert "%.2e" % (L["dual_value"] - L["utility"]) == L["gap_printed"]
+    assert G["final_residual"] < G["tolerance_per_job"]
+
+
+def test_generator_determinism():
+    a = synth.mixed_16(n=70000, m=16)
+    b = synth.mixed_16(n=70000, m=16)
+    assert a.T.tobytes() == b.T.tobytes() and a.w.tobytes() == b.w.tobytes()
+    rows = synth.roofline_rows(65530, 65600, n=200000, m=8)
+    full = synth.roofline_64(n=200000, m=8)
+    assert rows[0].tobytes() == full.T[65530:65600].tobytes()
+    assert rows[1].tobytes() == full.kind[65530:65600].tobytes()
