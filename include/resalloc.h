@@ -1,0 +1,181 @@
+/*
+ * resalloc.h -- C ABI of the MI355X (gfx950) price-discovery library.
+ *
+ * The library solves the fungible resource allocation problem of Agrawal,
+ * Boyd, Narayanan, Kazhamiaka and Zaharia, "Allocation of Fungible Resources
+ * via a Fast, Scalable Price Discovery Method" (§2.4, eq. e-res-alloc):
+ *
+ *     maximise   sum_i u_i(t_i)
+ *     subject to x_i >= 0,  1^T x_i <= 1,  t_i = a_i^T x_i,   i = 1..n
+ *                sum_i x_i <= R
+ *
+ * by price discovery (§5, Algorithm 2): for prices p >= 0 it evaluates the
+ * dual function g(p) = p^T R + sum_i max_x (u_i(a_i^T x) - p^T x) (§3,
+ * eq. e-subprob) and its subgradient q = R - r, r = sum_i x_i (§3,
+ * eq. e-g-subgrad), recovers a feasible allocation by scaling over-used
+ * columns (§5), and updates p with projected L-BFGS (§5).
+ *
+ * Conventions for every call:
+ *   - every function returns ra_status; nothing aborts or throws;
+ *   - "device" pointers are HIP device memory on the context's device (for
+ *     example torch tensor data pointers); "host" pointers are ordinary
+ *     host memory;
+ *   - inputs are BORROWED: the caller keeps them alive and unchanged until
+ *     the object that uses them is destroyed; outputs are caller-allocated;
+ *     scratch space is owned by the context or the problem;
+ *   - calls are ordered on the context's stream and are synchronous: results
+ *     are valid when the call returns;
+ *   - one context per host thread; a context is not thread-safe;
+ *   - on error, outputs are left untouched and ra_last_error(ctx) describes
+ *     the failure; RA_EINVAL is returned before any device work is queued.
+ *
+ * Utility functions (§2.2), one per job:
+ *   RA_UTIL_LOG     u(t) = w * log(t + eps)                    (w > 0)
+ *   RA_UTIL_CAPLIN  u(t) = w * min(t, c)   (capped linear; the target-priority
+ *                   utility w*min(t - c, 0) of §2.2 shifted by w*c; c >= 0)
+ */
+#ifndef RESALLOC_H
+#define RESALLOC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RA_OK = 0,
+    RA_EINVAL = 1,       /* invalid argument (checked before any device work)   */
+    RA_ENOMEM = 2,       /* device or pinned host allocation failed             */
+    RA_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed          */
+    RA_ENUMERIC = 4,     /* non-finite dual value or gradient                   */
+    RA_ENOTCONV = 5,     /* solver stopped at max_iter above the tolerance      */
+    RA_EUNSUPPORTED = 6  /* valid request this build does not implement        */
+} ra_status;
+
+typedef enum { RA_F32 = 0, RA_F64 = 1 } ra_dtype;
+
+typedef enum { RA_UTIL_LOG = 0, RA_UTIL_CAPLIN = 1 } ra_util_kind;
+
+typedef struct ra_ctx ra_ctx;         /* device, stream, scratch, pinned staging   */
+typedef struct ra_problem ra_problem; /* borrowed T + packed per-job utilities      */
+
+/* Largest number of resources a problem may have. */
+#define RA_MAX_RESOURCES 256
+
+/* Create a context on HIP device `device_ordinal`. `hip_stream` is a
+ * hipStream_t to order work on, or NULL for a context-owned stream (default
+ * priority). Errors: RA_EINVAL (bad ordinal, out NULL), RA_EDEVICE, RA_ENOMEM. */
+ra_status ra_create(ra_ctx **out, int device_ordinal, void *hip_stream);
+
+/* Destroy a context (waits for its stream). NULL is accepted. Problems
+ * created on it stay usable until they are destroyed; the context's stream
+ * and memory are released with the last of them. */
+ra_status ra_destroy(ra_ctx *ctx);
+
+/* Static string naming a status code. */
+const char *ra_status_string(ra_status s);
+
+/* Human-readable detail of the last failure on `ctx` ("" if none). */
+const char *ra_last_error(const ra_ctx *ctx);
+
+/* Describe a problem instance (§2.4, eq. e-res-alloc).
+ *   n, m      jobs and resources: n >= 1, 1 <= m <= RA_MAX_RESOURCES
+ *   dt        element type of T, w and c (RA_F32 or RA_F64)
+ *   T         device, n x m row-major efficiency matrix; row i is the job's
+ *             efficiency vector a_i of §2.1 (entries >= 0, finite)
+ *   w, c      device, n values each: utility weight (> 0) and, for capped
+ *             linear jobs, the cap c (>= 0; ignored for log jobs)
+ *   kind      device, n bytes of ra_util_kind, or NULL for all RA_UTIL_LOG
+ *   R         host, m resource limits R_j (> 0, finite); copied
+ *   eps       log offset (>= 0; eps = 0 requires every optimum t_i > 0)
+ *   validate  1: check T, w, c and kind on the device (one pass) and return
+ *             RA_EINVAL on a bad value; 0: trust the caller
+ * T stays borrowed. w, c and kind are read once, here, into a problem-owned
+ * packed copy (8 bytes per job in FP32, 16 in FP64). */
+ra_status ra_problem_create(ra_ctx *ctx, ra_problem **out, int64_t n, int32_t m, ra_dtype dt,
+                            const void *T, const void *w, const void *c, const uint8_t *kind,
+                            const double *R, double eps, int validate);
+
+/* Release a problem and its packed copy. NULL is accepted. */
+ra_status ra_problem_destroy(ra_problem *prob);
+
+/* One evaluation of the dual function at prices p (§3, eq. e-subprob and
+ * eq. e-g-subgrad; per job, Algorithm 1 of §4.2).
+ *   p            host, m prices (>= 0, finite); the kernel evaluates at p
+ *                rounded to the problem's element type
+ *   g            host, 1: g(p) = p^T R + sum_i v_i (v_i = the job's net utility)
+ *   grad         host, m: q = R - r (a subgradient; the gradient where g is
+ *                differentiable)
+ *   lower_bound  host, 1 or NULL: utility U(X~) of the feasible allocation
+ *                obtained by scaling each over-used column j of X by R_j/r_j
+ *                (§5); g(p) - U(X~) is the duality gap
+ *   j_pair       device, n x 2 int16 or NULL: the job's support (j_lo, j_hi),
+ *                -1 where unused; j_lo = -1 means the slack end of §4.1
+ *   x_pair       device, n x 2 of dt or NULL: the allocation on (j_lo, j_hi)
+ *                (eq. e-xixj); written only together with j_pair
+ *   j1           device, n int16 or NULL: argmax_j a_ij / p_j, the first
+ *                vertex of the job's cost curve (lowest j on exact ties;
+ *                -1 for an all-zero row)
+ * Errors: RA_EINVAL, RA_EDEVICE, RA_ENUMERIC (non-finite g or grad). */
+ra_status ra_dual_eval(ra_ctx *ctx, const ra_problem *prob, const double *p, double *g,
+                       double *grad, double *lower_bound, int16_t *j_pair, void *x_pair,
+                       int16_t *j1);
+
+/* Options of the price-discovery loop (§5, Algorithm 2). */
+typedef struct {
+    double tol_rel;          /* stop when (g - U(X~)) / max(|g|, |U(X~)|) <= tol_rel */
+    int32_t max_iter;        /* price updates (Algorithm 2, K^max)                   */
+    int32_t lbfgs_mem;       /* L-BFGS memory (the paper's default is 10)            */
+    int32_t method;          /* 0 = projected L-BFGS, 1 = projected subgradient     */
+    int32_t init;            /* 0 = p = 1, 1 = use p_inout as given                 */
+    int32_t use_graph;       /* 1 = replay one captured HIP graph per evaluation    */
+    int32_t verbose;         /* 1 = one line per iteration on stderr                */
+    int32_t max_evals;       /* > 0: stop after exactly this many dual evaluations  */
+} ra_solve_opts;
+
+/* Outcome of a solve. */
+typedef struct {
+    int32_t iters;           /* price updates taken                                  */
+    int32_t dual_evals;      /* dual evaluations (line-search trials included)       */
+    int32_t fell_back;       /* projected-subgradient steps taken                     */
+    int32_t converged;       /* 1 if rel_gap <= tol_rel                               */
+    double g;                /* dual value at the returned prices (upper bound)      */
+    double U_lb;             /* U(X~) at the returned prices (lower bound)           */
+    double rel_gap;          /* (g - U_lb) / max(|g|, |U_lb|)                         */
+    double seconds;          /* wall time of the call                                */
+} ra_solve_info;
+
+/* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
+ * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit). */
+void ra_solve_opts_default(ra_solve_opts *opts);
+
+/* Price discovery (§5, Algorithm 2). p_inout: host, m doubles; read when
+ * opts->init == 1, and on return holds the prices with the smallest relative
+ * gap seen (the reported certificate). info: host, may be NULL.
+ * Returns RA_OK when the tolerance was met, RA_ENOTCONV when max_iter ended
+ * the loop (p_inout and info are still filled), or an error. */
+ra_status ra_solve(ra_ctx *ctx, const ra_problem *prob, const ra_solve_opts *opts,
+                   double *p_inout, ra_solve_info *info);
+
+/* Dense feasible allocation X~ at prices p (§5): device, n x m of the
+ * problem's element type, row-major. X~ = X diag(min(1, R_j / r_j)) with X
+ * the subproblem solutions at p (at most two nonzeros per row, §4.1). */
+ra_status ra_get_allocation(ra_ctx *ctx, const ra_problem *prob, const double *p, void *X);
+
+/* Kernel timing on the context's stream (for benchmarks and profiling).
+ * enable = 1 brackets every launch of the dual kernel with a pair of HIP
+ * events on the context's stream and accumulates the elapsed times; while it
+ * is on, evaluations launch kernels directly instead of replaying a graph.
+ * enable = 0 stops timing; the totals are kept until the next enable = 1. */
+ra_status ra_set_kernel_timing(ra_ctx *ctx, int enable);
+
+/* Totals of the timed dual-kernel launches: milliseconds and launch count
+ * (host outputs, either may be NULL). */
+ra_status ra_get_kernel_timing(const ra_ctx *ctx, double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RESALLOC_H */

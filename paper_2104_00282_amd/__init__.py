@@ -1,0 +1,167 @@
+"""MI355X price discovery for fungible resource allocation.
+
+Python face of the C ABI in include/resalloc.h.  PyTorch supplies device
+memory only; every step of the method runs in libresalloc.so (gfx950 HIP).
+``_capi`` holds the ctypes declarations under the C names; ``Context`` and
+``Problem`` below are conveniences that marshal torch tensors into them.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import weakref
+
+import numpy as np
+
+from . import _capi
+from ._capi import (RA_EDEVICE, RA_EINVAL, RA_ENOMEM, RA_ENOTCONV, RA_ENUMERIC, RA_EUNSUPPORTED,
+                    RA_F32, RA_F64, RA_OK, RA_UTIL_CAPLIN, RA_UTIL_LOG, RAError, ra_create,
+                    ra_destroy, ra_dual_eval, ra_get_allocation, ra_last_error, ra_problem_create,
+                    ra_problem_destroy, ra_solve, ra_solve_info, ra_solve_opts,
+                    ra_solve_opts_default, ra_status_string, ra_set_kernel_timing,
+                    ra_get_kernel_timing)
+
+__all__ = [
+    "Context", "Problem", "RAError", "ra_create", "ra_destroy", "ra_status_string",
+    "ra_last_error", "ra_problem_create", "ra_problem_destroy", "ra_dual_eval",
+    "ra_solve_opts_default", "ra_solve", "ra_get_allocation", "ra_solve_opts", "ra_solve_info",
+    "ra_set_kernel_timing", "ra_get_kernel_timing",
+]
+
+
+# Handles still open at interpreter exit are closed before torch and the HIP
+# runtime are torn down (problems first, then contexts).
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    objs = list(_LIVE)
+    for o in objs:
+        if isinstance(o, Problem):
+            o.close()
+    for o in objs:
+        o.close()
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _hbuf(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Context:
+    """A library context on one HIP device with its own stream."""
+
+    def __init__(self, device=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        self.device = device
+        self.handle = ra_create(device, None)
+        _LIVE.add(self)
+
+    def close(self):
+        if self.handle:
+            ra_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """A resource allocation problem on the device (tensors are kept alive).
+
+    T: (n, m) float32/float64 CUDA tensor; w, c: (n,) of T's dtype; kind:
+    (n,) uint8 (0 = log, 1 = capped linear) or None; R: m limits.
+    """
+
+    def __init__(self, ctx, T, w, c=None, kind=None, R=None, eps=1e-3, validate=True):
+        import torch
+        if T.dim() != 2 or not T.is_cuda:
+            raise ValueError("T must be a 2-D device tensor")
+        if T.dtype not in (torch.float32, torch.float64):
+            raise TypeError("T must be float32 or float64")
+        self.ctx = ctx
+        self.T = T.contiguous()
+        self.n, self.m = self.T.shape
+        self.dtype = self.T.dtype
+        self.w = w.to(self.dtype).contiguous()
+        self.c = None if c is None else c.to(self.dtype).contiguous()
+        self.kind = None if kind is None else kind.to(torch.uint8).contiguous()
+        self.R = np.ascontiguousarray(np.asarray(R, dtype=np.float64))
+        self.eps = float(eps)
+        torch.cuda.synchronize(self.T.device)
+        self.handle = ra_problem_create(
+            ctx.handle, self.n, self.m, RA_F32 if self.dtype == torch.float32 else RA_F64,
+            _dptr(self.T), _dptr(self.w), _dptr(self.c), _dptr(self.kind), _hbuf(self.R),
+            self.eps, 1 if validate else 0)
+        _LIVE.add(self)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ra_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dual_eval(self, p, lower_bound=False, support=False, j1=False):
+        """g(p), grad = R - r, and optionally U(X~), the per-job support
+        (j_pair int16 (n, 2), x_pair (n, 2)) and the first vertex j1 (n,)."""
+        import torch
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+        g = ctypes.c_double()
+        grad = np.zeros(self.m)
+        lb = ctypes.c_double() if lower_bound else None
+        dev = self.T.device
+        jp = torch.empty((self.n, 2), dtype=torch.int16, device=dev) if support else None
+        xp = torch.empty((self.n, 2), dtype=self.dtype, device=dev) if support else None
+        jv = torch.empty(self.n, dtype=torch.int16, device=dev) if j1 else None
+        ra_dual_eval(self.ctx.handle, self.handle, _hbuf(p), ctypes.byref(g), _hbuf(grad),
+                     ctypes.byref(lb) if lb is not None else None, _dptr(jp), _dptr(xp),
+                     _dptr(jv))
+        out = {"g": g.value, "grad": grad, "r": self.R - grad}
+        if lb is not None:
+            out["lower_bound"] = lb.value
+        if support:
+            out["j_pair"], out["x_pair"] = jp, xp
+        if j1:
+            out["j1"] = jv
+        return out
+
+    def solve(self, p0=None, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, method=0, use_graph=True,
+              verbose=False, max_evals=0):
+        """Price discovery; returns (p, info dict, status)."""
+        o = ra_solve_opts_default()
+        o.max_evals = max_evals
+        o.tol_rel = tol_rel
+        o.max_iter = max_iter
+        o.lbfgs_mem = lbfgs_mem
+        o.method = method
+        o.use_graph = 1 if use_graph else 0
+        o.verbose = 1 if verbose else 0
+        p = np.ones(self.m)
+        if p0 is not None:
+            p = np.ascontiguousarray(np.asarray(p0, dtype=np.float64)).copy()
+            o.init = 1
+        info = ra_solve_info()
+        st = ra_solve(self.ctx.handle, self.handle, o, _hbuf(p), info)
+        return p, {f: getattr(info, f) for f, _ in ra_solve_info._fields_}, st
+
+    def allocation(self, p):
+        """Dense feasible allocation X~ (n, m) at prices p."""
+        import torch
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float64))
+        X = torch.empty((self.n, self.m), dtype=self.dtype, device=self.T.device)
+        ra_get_allocation(self.ctx.handle, self.handle, _hbuf(p), _dptr(X))
+        return X

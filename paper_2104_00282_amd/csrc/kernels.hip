@@ -1,0 +1,669 @@
+// gfx950 kernels of the price-discovery hot path.
+//
+// Per job i (row a = a_i of the efficiency matrix T, prices p), the kernels
+// solve the subproblem of §3 (eq. e-subprob): maximise u(t) - p^T x over
+// x >= 0, 1^T x <= 1, t = a^T x.  §4.1 shows the cost c(t) of reaching
+// throughput t is the lower convex envelope of the points (0, 0) and
+// (a_j, p_j); §4.2 maximises u(t) - c(t) one envelope segment at a time with
+// the closed forms eq. e-opt-t-log (log utility) and eq. e-opt-t-target
+// (capped-linear utility), and the allocation on a segment is eq. e-xixj.
+//
+// Instead of building all m(m+1)/2 segments (Algorithm 1), a job walks the
+// envelope from the origin: the first vertex is the resource with the
+// largest a_j / p_j, each further vertex the one with the smallest slope
+// (p_j - p_c) / (a_j - a_c) among a_j > a_c.  Since u - c is concave, the
+// walk stops at the first segment whose maximiser lies before its right end.
+// It visits only the segments up to the optimum and costs one pass over the
+// row per visited vertex.
+//
+// Layout: T is n x m row-major in HBM.  A wavefront owns a tile of 64
+// consecutive jobs (64 m contiguous elements) and loads it with 16-byte
+// loads that each cover 1 KiB of consecutive bytes, stages it in LDS with a
+// padded row stride (conflict-free 16-byte row reads), and each lane then
+// solves one job from its own row.  The next tile is prefetched into
+// registers while the current one is solved.  Resource usage r_j is summed
+// per tile in a per-wave LDS histogram, folded into per-lane FP64
+// accumulators after every tile, reduced across the block in a fixed order
+// and written as one row of block partials; no global atomics are used, so
+// results are reproducible bit for bit.
+#include "ra_kernels.h"
+
+#include <math.h>
+
+namespace ra {
+
+template <typename F> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <typename F> using V2 = typename Vec2<F>::type;
+
+__device__ __forceinline__ float dlog(float x) { return logf(x); }
+__device__ __forceinline__ double dlog(double x) { return log(x); }
+
+// u(t) of §2.2: log utility w log(t + eps) or capped linear w min(t, c).
+template <typename F>
+__device__ __forceinline__ F utility(bool caplin, F w, F c, F eps, F t)
+{
+    return caplin ? w * (t < c ? t : c) : w * dlog(t + eps);
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename F>
+struct Job {
+    int jlo, jhi, j1;  // support (-1 = none) and first envelope vertex
+    F xlo, xhi;        // allocation on jlo / jhi
+    F tlo, thi;        // a_jlo x_lo and a_jhi x_hi
+    F v;               // net utility u(t) - p^T x
+};
+
+// First envelope vertex: largest key a_j * (1/p_j); lowest j on exact ties;
+// a_j = 0 never wins (key 0, or NaN when p_j = 0).
+template <typename F, int M, class Row>
+__device__ __forceinline__ int scan_first(const Row& a, int mm, const F* __restrict__ IP)
+{
+    F best = F(0);
+    int j1 = -1;
+    if constexpr (M > 0) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const F key = a.get(j) * IP[j];
+            const bool b = key > best;
+            best = b ? key : best;
+            j1 = b ? j : j1;
+        }
+    } else {
+        for (int j = 0; j < mm; ++j) {
+            const F key = a.get(j) * IP[j];
+            const bool b = key > best;
+            best = b ? key : best;
+            j1 = b ? j : j1;
+        }
+    }
+    return j1;
+}
+
+// Next envelope vertex after (ac, pc): smallest slope (p_j - pc)/(a_j - ac)
+// over a_j > ac, compared by cross-multiplication; lowest j on ties; -1 if
+// no resource is more efficient than the current vertex.
+template <typename F, int M, class Row>
+__device__ __forceinline__ int scan_next(const Row& a, int mm, const F* __restrict__ P, F ac,
+                                         F pc)
+{
+    F bn = F(1), bd = F(0);
+    int jn = -1;
+    if constexpr (M > 0) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const F d = a.get(j) - ac;
+            const F nm = P[j] - pc;
+            const bool b = (d > F(0)) & (nm * bd < bn * d);
+            bn = b ? nm : bn;
+            bd = b ? d : bd;
+            jn = b ? j : jn;
+        }
+    } else {
+        for (int j = 0; j < mm; ++j) {
+            const F d = a.get(j) - ac;
+            const F nm = P[j] - pc;
+            const bool b = (d > F(0)) & (nm * bd < bn * d);
+            bn = b ? nm : bn;
+            bd = b ? d : bd;
+            jn = b ? j : jn;
+        }
+    }
+    return jn;
+}
+
+// One job's subproblem (Algorithm 1 of §4.2 as an envelope walk).
+// a.get(j): entry j in an unrolled scan; a.at(j): entry j for a per-lane j;
+// P, IP: prices and reciprocals (wave-uniform); Pdyn: prices for a per-lane
+// index.
+template <typename F, int M, class Row>
+__device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restrict__ P,
+                                          const F* __restrict__ IP, const F* Pdyn, F w, F c,
+                                          bool caplin, F eps, Job<F>& J)
+{
+    const int j1 = scan_first<F, M>(a, mm, IP);
+    J.j1 = j1;
+    if (j1 < 0) {  // all-zero row: nothing can be bought, t = 0
+        J.jlo = J.jhi = -1;
+        J.xlo = J.xhi = J.tlo = J.thi = F(0);
+        J.v = utility(caplin, w, c, eps, F(0));
+        return;
+    }
+    int lo = -1, hi = j1;
+    F alo = F(0), plo = F(0);
+    F ahi = a.at(j1), phi = Pdyn[j1];
+    F t;
+    for (;;) {
+        // segment [alo, ahi] of slope alpha = num / den (den > 0, num >= 0)
+        const F num = phi - plo, den = ahi - alo;
+        bool walk;
+        if (!caplin) {
+            // eq. e-opt-t-log: t = clip((u')^{-1}(alpha), alo, ahi),
+            // (u')^{-1}(alpha) = w / alpha - eps (+inf for alpha = 0)
+            const F tu = w * den / num - eps;
+            t = fmin(fmax(tu, alo), ahi);
+            walk = tu >= ahi;
+        } else if (w * den <= num) {  // eq. e-opt-t-target, w <= alpha
+            t = alo;
+            walk = false;
+        } else {  // w > alpha: the cap clipped to the segment
+            t = fmin(fmax(c, alo), ahi);
+            walk = c >= ahi;
+        }
+        if (!walk) break;
+        const int jn = scan_next<F, M>(a, mm, P, ahi, phi);
+        if (jn < 0) {  // right end of the curve, t = max_j a_j
+            t = ahi;
+            break;
+        }
+        lo = hi;
+        alo = ahi;
+        plo = phi;
+        hi = jn;
+        ahi = a.at(jn);
+        phi = Pdyn[jn];
+    }
+    // eq. e-xixj on the final segment (lo = -1: the origin, x_hi = t / a_hi)
+    const F den = ahi - alo;
+    F xhi = (t - alo) / den;
+    F xlo = (lo >= 0) ? (ahi - t) / den : F(0);
+    J.v = utility(caplin, w, c, eps, t) - (plo * xlo + phi * xhi);
+    if (xhi == F(0)) {  // at the left end: a single resource (or none)
+        hi = lo;
+        ahi = alo;
+        xhi = xlo;
+        lo = -1;
+        xlo = F(0);
+    } else if (xlo == F(0)) {
+        lo = -1;
+    }
+    J.jlo = lo;
+    J.jhi = hi;
+    J.xlo = xlo;
+    J.xhi = xhi;
+    J.tlo = (lo >= 0) ? alo * xlo : F(0);
+    J.thi = (hi >= 0) ? ahi * xhi : F(0);
+}
+
+template <int M>
+struct RegRow {
+    float v[M];
+    const float* lds;
+    __device__ __forceinline__ float get(int j) const { return v[j]; }
+    __device__ __forceinline__ float at(int j) const { return lds[j]; }
+};
+
+template <typename F>
+struct GlobalRow {
+    const F* __restrict__ r;
+    __device__ __forceinline__ F get(int j) const { return r[j]; }
+    __device__ __forceinline__ F at(int j) const { return r[j]; }
+};
+
+// ------------------------------------------------------------------------
+// Dual kernel, FP32, m = M in {4, 8, 16, 32, 64}, T 16-byte aligned.
+// ------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(256) k_dual_vec(
+    const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
+    const PriceBlock<float>* __restrict__ pb, float eps, double* __restrict__ partial,
+    int* __restrict__ jpair, float2* __restrict__ xpair, float2* __restrict__ tpair,
+    int16_t* __restrict__ j1out)
+{
+    constexpr int Q = M / 4;                    // 16-byte chunks per row
+    constexpr int S = M + ((Q & 1) ? 0 : 4);    // LDS row stride in words
+    constexpr int TR = 64;                      // rows per wave tile
+    __shared__ __attribute__((aligned(16))) float tile[4][TR * S];
+    __shared__ float hist[4][M];
+    __shared__ float ptab[M];
+
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const float* __restrict__ P = pb->p;
+    const float* __restrict__ IP = pb->invp;
+    if (threadIdx.x < M) ptab[threadIdx.x] = P[threadIdx.x];
+    if (lane < M) hist[wv][lane] = 0.f;
+    __syncthreads();
+
+    double racc = 0.0, vacc = 0.0;
+    const int64_t ntiles = (n + TR - 1) / TR;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    int64_t ti = (int64_t)blockIdx.x * 4 + wv;
+    float* tl = tile[wv];
+    float4 pre[Q];
+    float2 wcn = make_float2(0.f, 0.f);
+
+    auto load_tile = [&](int64_t tix) {
+        const int64_t row0 = tix * TR;
+        const int64_t rows = (n - row0) < TR ? (n - row0) : TR;
+        const int valid = (int)rows * Q;
+        const float4* src = reinterpret_cast<const float4*>(T + row0 * M);
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int ch = lane + 64 * k;
+            pre[k] = (ch < valid) ? src[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        wcn = (lane < rows) ? prm[row0 + lane] : make_float2(1.f, -1.f);
+    };
+
+    if (ti < ntiles) load_tile(ti);
+    for (; ti < ntiles; ti += nw) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int ch = lane + 64 * k;
+            const int r = ch / Q, q = ch % Q;
+            *reinterpret_cast<float4*>(tl + r * S + 4 * q) = pre[k];
+        }
+        const float2 wc = wcn;
+        wave_sync();
+        if (ti + nw < ntiles) load_tile(ti + nw);
+
+        const int64_t i = ti * TR + lane;
+        if (i < n) {
+            RegRow<M> row;
+            row.lds = tl + lane * S;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
+                row.v[4 * q + 0] = v.x;
+                row.v[4 * q + 1] = v.y;
+                row.v[4 * q + 2] = v.z;
+                row.v[4 * q + 3] = v.w;
+            }
+            Job<float> J;
+            solve_job<float, M>(row, M, P, IP, ptab, wc.x, wc.y, wc.y >= 0.f, eps, J);
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], J.xhi);
+            vacc += (double)J.v;
+            if (jpair) jpair[i] = (J.jlo & 0xffff) | (J.jhi << 16);
+            if (xpair) xpair[i] = make_float2(J.xlo, J.xhi);
+            if (tpair) tpair[i] = make_float2(J.tlo, J.thi);
+            if (j1out) j1out[i] = (int16_t)J.j1;
+        }
+        wave_sync();
+        if (lane < M) {
+            racc += (double)hist[wv][lane];
+            hist[wv][lane] = 0.f;
+        }
+        wave_sync();
+    }
+
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) vacc += __shfl_xor(vacc, off);
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(&tile[0][0]);
+    if (lane < M) red[wv * (M + 1) + lane] = racc;
+    if (lane == 0) red[wv * (M + 1) + M] = vacc;
+    __syncthreads();
+    if (threadIdx.x < M + 1) {
+        const int t = threadIdx.x;
+        const double s = ((red[t] + red[(M + 1) + t]) + red[2 * (M + 1) + t]) + red[3 * (M + 1) + t];
+        partial[(int64_t)blockIdx.x * (M + 1) + t] = s;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Dual kernel, any m <= 256, FP32 or FP64: one lane per job reading its row
+// straight from global memory (used for FP64 and for m outside the
+// vectorised classes).
+// ------------------------------------------------------------------------
+template <typename F>
+__global__ void __launch_bounds__(256) k_dual_gen(
+    const F* __restrict__ T, const V2<F>* __restrict__ prm, int64_t n, int m,
+    const PriceBlock<F>* __restrict__ pb, F eps, double* __restrict__ partial,
+    int* __restrict__ jpair, V2<F>* __restrict__ xpair, V2<F>* __restrict__ tpair,
+    int16_t* __restrict__ j1out)
+{
+    constexpr int TR = 64;
+    __shared__ F hist[4][256];
+    __shared__ double red[4][257];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const F* __restrict__ P = pb->p;
+    const F* __restrict__ IP = pb->invp;
+    for (int j = lane; j < m; j += 64) hist[wv][j] = F(0);
+    __syncthreads();
+
+    double racc[4] = {0.0, 0.0, 0.0, 0.0};
+    double vacc = 0.0;
+    const int64_t ntiles = (n + TR - 1) / TR;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t ti = (int64_t)blockIdx.x * 4 + wv; ti < ntiles; ti += nw) {
+        const int64_t i = ti * TR + lane;
+        if (i < n) {
+            GlobalRow<F> row{T + i * m};
+            const V2<F> wc = prm[i];
+            Job<F> J;
+            solve_job<F, 0>(row, m, P, IP, P, wc.x, wc.y, wc.y >= F(0), eps, J);
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], J.xhi);
+            vacc += (double)J.v;
+            if (jpair) jpair[i] = (J.jlo & 0xffff) | (J.jhi << 16);
+            if (xpair) xpair[i] = V2<F>{J.xlo, J.xhi};
+            if (tpair) tpair[i] = V2<F>{J.tlo, J.thi};
+            if (j1out) j1out[i] = (int16_t)J.j1;
+        }
+        wave_sync();
+        for (int k = 0; k < 4; ++k) {
+            const int j = lane + 64 * k;
+            if (j < m) {
+                racc[k] += (double)hist[wv][j];
+                hist[wv][j] = F(0);
+            }
+        }
+        wave_sync();
+    }
+    for (int off = 32; off > 0; off >>= 1) vacc += __shfl_xor(vacc, off);
+    for (int k = 0; k < 4; ++k) {
+        const int j = lane + 64 * k;
+        if (j < m) red[wv][j] = racc[k];
+    }
+    if (lane == 0) red[wv][m] = vacc;
+    __syncthreads();
+    for (int t = threadIdx.x; t < m + 1; t += 256) {
+        const double s = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+        partial[(int64_t)blockIdx.x * (m + 1) + t] = s;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Column reduction of block partials: one block per column, fixed order.
+// ------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_reduce_cols(const double* __restrict__ partial, int nb,
+                                                     int ncols, double* __restrict__ out)
+{
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += partial[(int64_t)b * ncols + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// ------------------------------------------------------------------------
+// Lower bound (§5): column scales s_j = min(1, R_j / r_j), scaled throughput
+// t~_i = s_lo a_lo x_lo + s_hi a_hi x_hi, sums of u(t~_i) and of the utility
+// lost by scaling, u(t_i) - u(t~_i).  The loss is formed from
+// t_i - t~_i = (1 - s_lo) a_lo x_lo + (1 - s_hi) a_hi x_hi, with 1 - s_j
+// computed in FP64, so it keeps its relative accuracy when s_j is close to 1.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ float dlog1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double dlog1p(double x) { return log1p(x); }
+
+template <typename F>
+__global__ void __launch_bounds__(256) k_lower(const int* __restrict__ jpair,
+                                               const V2<F>* __restrict__ tpair,
+                                               const V2<F>* __restrict__ prm, int64_t n, int m,
+                                               const double* __restrict__ R,
+                                               const double* __restrict__ r, F eps,
+                                               double* __restrict__ partial2)
+{
+    __shared__ F s[256];
+    __shared__ F sc[256];
+    __shared__ double red[2][4];
+    for (int j = threadIdx.x; j < m; j += 256) {
+        const bool over = r[j] > R[j];
+        s[j] = over ? F(R[j] / r[j]) : F(1);
+        sc[j] = over ? F((r[j] - R[j]) / r[j]) : F(0);
+    }
+    __syncthreads();
+    double U = 0.0, du = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const int jp = jpair[i];
+        const int jlo = (int)(int16_t)(jp & 0xffff);
+        const int jhi = jp >> 16;
+        const V2<F> tp = tpair[i];
+        const V2<F> wc = prm[i];
+        const F tt = (jlo >= 0 ? s[jlo] * tp.x : F(0)) + (jhi >= 0 ? s[jhi] * tp.y : F(0));
+        const F dt = (jlo >= 0 ? sc[jlo] * tp.x : F(0)) + (jhi >= 0 ? sc[jhi] * tp.y : F(0));
+        const bool caplin = wc.y >= F(0);
+        const F w = wc.x, c = wc.y;
+        U += (double)utility(caplin, w, c, eps, tt);
+        F loss;
+        if (!caplin) {
+            loss = w * dlog1p(dt / (tt + eps));
+        } else {
+            const F t = tp.x + tp.y;
+            loss = (tt >= c) ? F(0) : (t <= c ? w * dt : w * (c - tt));
+        }
+        du += (double)loss;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        U += __shfl_xor(U, off);
+        du += __shfl_xor(du, off);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = U;
+        red[1][wv] = du;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const int k = threadIdx.x;
+        partial2[(int64_t)blockIdx.x * 2 + k] = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+    }
+}
+
+// ------------------------------------------------------------------------
+// Input packing and validation.
+// ------------------------------------------------------------------------
+template <typename F>
+__global__ void k_pack(const F* __restrict__ w, const F* __restrict__ c,
+                       const uint8_t* __restrict__ kind, int64_t n, V2<F>* __restrict__ prm,
+                       int* __restrict__ bad)
+{
+    int flags = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint8_t k = kind ? kind[i] : (uint8_t)0;
+        const F wi = w[i];
+        F ci = F(-1);
+        if (!(wi > F(0)) || !isfinite(wi)) flags |= 1;
+        if (k == 1) {
+            ci = c[i];
+            if (!(ci >= F(0)) || !isfinite(ci)) flags |= 2;
+        } else if (k > 1) {
+            flags |= 4;
+        }
+        prm[i] = V2<F>{wi, ci};
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+template <typename F>
+__global__ void k_validate_T(const F* __restrict__ T, int64_t count, int* __restrict__ bad)
+{
+    int flags = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
+        const F v = T[e];
+        if (!(v >= F(0)) || !isfinite(v)) flags |= 8;
+    }
+    if (flags) atomicOr(bad, flags);
+}
+
+template <typename F>
+__global__ void k_materialize(const int* __restrict__ jpair, const V2<F>* __restrict__ xpair,
+                              int64_t n, int m, const double* __restrict__ R,
+                              const double* __restrict__ r, F* __restrict__ X)
+{
+    __shared__ F s[256];
+    for (int j = threadIdx.x; j < m; j += blockDim.x) s[j] = (r[j] > R[j]) ? F(R[j] / r[j]) : F(1);
+    __syncthreads();
+    const int64_t total = n * m;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t i = e / m;
+        const int j = (int)(e - i * m);
+        const int jp = jpair[i];
+        const int jlo = (int)(int16_t)(jp & 0xffff);
+        const int jhi = jp >> 16;
+        const V2<F> xp = xpair[i];
+        F x = F(0);
+        if (jlo == j) x += s[j] * xp.x;
+        if (jhi == j) x += s[j] * xp.y;
+        X[e] = x;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Host-side launchers.
+// ------------------------------------------------------------------------
+template <typename K>
+static int occupancy_blocks(K kernel)
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 256, 0) != hipSuccess || nb < 1)
+        nb = 1;
+    return nb;
+}
+
+static bool vec_class(int m) { return m == 4 || m == 8 || m == 16 || m == 32 || m == 64; }
+
+int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok)
+{
+    static int occ[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int slot;
+    if (dtype == 0 && vec_ok && vec_class(m)) {
+        slot = m == 4 ? 0 : m == 8 ? 1 : m == 16 ? 2 : m == 32 ? 3 : 4;
+    } else {
+        slot = dtype == 0 ? 5 : 6;
+    }
+    if (occ[slot] == 0) {
+        switch (slot) {
+        case 0: occ[slot] = occupancy_blocks(k_dual_vec<4>); break;
+        case 1: occ[slot] = occupancy_blocks(k_dual_vec<8>); break;
+        case 2: occ[slot] = occupancy_blocks(k_dual_vec<16>); break;
+        case 3: occ[slot] = occupancy_blocks(k_dual_vec<32>); break;
+        case 4: occ[slot] = occupancy_blocks(k_dual_vec<64>); break;
+        case 5: occ[slot] = occupancy_blocks(k_dual_gen<float>); break;
+        default: occ[slot] = occupancy_blocks(k_dual_gen<double>); break;
+        }
+    }
+    const int64_t ntiles = (n + 63) / 64;
+    const int64_t want = (ntiles + 3) / 4;
+    const int64_t cap = (int64_t)dev_cus * occ[slot];
+    int64_t g = want < cap ? want : cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
+                       const void* prm, int64_t n, const void* prices, double eps,
+                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1)
+{
+    int* jp = reinterpret_cast<int*>(jpair);
+    if (dtype == 0) {
+        const float* Tf = static_cast<const float*>(T);
+        const float2* pr = static_cast<const float2*>(prm);
+        const auto* pb = static_cast<const PriceBlock<float>*>(prices);
+        float2* xp = static_cast<float2*>(xpair);
+        float2* tp = static_cast<float2*>(tpair);
+        const float e = (float)eps;
+        if (vec_ok && vec_class(m)) {
+            switch (m) {
+            case 4: k_dual_vec<4><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
+            case 8: k_dual_vec<8><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
+            case 16: k_dual_vec<16><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
+            case 32: k_dual_vec<32><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
+            default: k_dual_vec<64><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
+            }
+        } else {
+            k_dual_gen<float><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp, tp, j1);
+        }
+    } else {
+        k_dual_gen<double><<<grid, 256, 0, st>>>(
+            static_cast<const double*>(T), static_cast<const double2*>(prm), n, m,
+            static_cast<const PriceBlock<double>*>(prices), eps, partial, jp,
+            static_cast<double2*>(xpair), static_cast<double2*>(tpair), j1);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_cols(hipStream_t st, const double* partial, int nb, int ncols,
+                              double* out)
+{
+    k_reduce_cols<<<ncols, 256, 0, st>>>(partial, nb, ncols, out);
+    return hipGetLastError();
+}
+
+int lower_grid(int dev_cus, int64_t n)
+{
+    const int64_t want = (n + 255) / 256;
+    const int64_t cap = (int64_t)dev_cus * 8;
+    int64_t g = want < cap ? want : cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_lower(int dtype, int grid, hipStream_t st, const int16_t* jpair,
+                        const void* tpair, const void* prm, int64_t n, int m, const double* R,
+                        const double* r, double eps, double* partial2)
+{
+    const int* jp = reinterpret_cast<const int*>(jpair);
+    if (dtype == 0)
+        k_lower<float><<<grid, 256, 0, st>>>(jp, static_cast<const float2*>(tpair),
+                                             static_cast<const float2*>(prm), n, m, R, r,
+                                             (float)eps, partial2);
+    else
+        k_lower<double><<<grid, 256, 0, st>>>(jp, static_cast<const double2*>(tpair),
+                                              static_cast<const double2*>(prm), n, m, R, r, eps,
+                                              partial2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(int dtype, hipStream_t st, const void* w, const void* c,
+                       const uint8_t* kind, int64_t n, void* prm, int* bad)
+{
+    const int64_t want = (n + 255) / 256;
+    const int grid = (int)(want < 4096 ? (want < 1 ? 1 : want) : 4096);
+    if (dtype == 0)
+        k_pack<float><<<grid, 256, 0, st>>>(static_cast<const float*>(w),
+                                            static_cast<const float*>(c), kind, n,
+                                            static_cast<float2*>(prm), bad);
+    else
+        k_pack<double><<<grid, 256, 0, st>>>(static_cast<const double*>(w),
+                                             static_cast<const double*>(c), kind, n,
+                                             static_cast<double2*>(prm), bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_T(int dtype, hipStream_t st, const void* T, int64_t count, int* bad)
+{
+    const int64_t want = (count + 255) / 256;
+    const int grid = (int)(want < 8192 ? (want < 1 ? 1 : want) : 8192);
+    if (dtype == 0)
+        k_validate_T<float><<<grid, 256, 0, st>>>(static_cast<const float*>(T), count, bad);
+    else
+        k_validate_T<double><<<grid, 256, 0, st>>>(static_cast<const double*>(T), count, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_materialize(int dtype, hipStream_t st, const int16_t* jpair, const void* xpair,
+                              int64_t n, int m, const double* R, const double* r, void* X)
+{
+    const int64_t want = (n * m + 255) / 256;
+    const int grid = (int)(want < 8192 ? (want < 1 ? 1 : want) : 8192);
+    const int* jp = reinterpret_cast<const int*>(jpair);
+    if (dtype == 0)
+        k_materialize<float><<<grid, 256, 0, st>>>(jp, static_cast<const float2*>(xpair), n, m, R,
+                                                   r, static_cast<float*>(X));
+    else
+        k_materialize<double><<<grid, 256, 0, st>>>(jp, static_cast<const double2*>(xpair), n, m,
+                                                    R, r, static_cast<double*>(X));
+    return hipGetLastError();
+}
+
+}  // namespace ra

@@ -1,0 +1,52 @@
+// Internal launch interface between the host runtime and the gfx950 kernels.
+// Not part of the public C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ra {
+
+// Device block of prices for one evaluation, written by the host before the
+// dual kernel runs. F is the problem's element type.
+template <typename F>
+struct PriceBlock {
+    F p[256];     // prices rounded to F
+    F invp[256];  // 1 / p_j (+inf where p_j = 0)
+};
+
+// Number of blocks one dual-kernel launch uses for n jobs with m resources.
+int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);
+
+// Dual evaluation (Algorithm 1 per job, sums into block partials).
+// partial: [grid][m + 1] doubles (r_j partials, then the net-utility sum).
+// Optional outputs may be null: jpair (n x 2 int16), xpair (n x 2 F),
+// tpair (n x 2 F, a_lo x_lo and a_hi x_hi), j1 (n int16).
+hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
+                       const void* prm, int64_t n, const void* prices, double eps,
+                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1);
+
+// out[j] = sum_b partial[b * ncols + j], j < ncols (fixed order).
+hipError_t launch_reduce_cols(hipStream_t st, const double* partial, int nb, int ncols,
+                              double* out);
+
+// Lower bound of the column-scaled allocation (§5): partial2 [grid][2] gets
+// sum_i u_i(t~_i) and sum_i u_i(t_i) - u_i(t~_i); r and R are device m-vectors.
+int lower_grid(int dev_cus, int64_t n);
+hipError_t launch_lower(int dtype, int grid, hipStream_t st, const int16_t* jpair,
+                        const void* tpair, const void* prm, int64_t n, int m, const double* R,
+                        const double* r, double eps, double* partial2);
+
+// Pack (w, c, kind) into one 2-vector per job: (w, c) for capped-linear jobs,
+// (w, -1) for log jobs. bad gets bit 1 for w <= 0 / non-finite, bit 2 for a
+// bad cap, bit 4 for an unknown kind.
+hipError_t launch_pack(int dtype, hipStream_t st, const void* w, const void* c,
+                       const uint8_t* kind, int64_t n, void* prm, int* bad);
+
+// bad gets bit 8 if any T entry is negative or non-finite.
+hipError_t launch_validate_T(int dtype, hipStream_t st, const void* T, int64_t count, int* bad);
+
+// Dense X~ (n x m, element type F) from the support and column scales.
+hipError_t launch_materialize(int dtype, hipStream_t st, const int16_t* jpair, const void* xpair,
+                              int64_t n, int m, const double* R, const double* r, void* X);
+
+}  // namespace ra

@@ -1,0 +1,105 @@
+"""GPU price discovery (C ABI ra_solve, ra_get_allocation) against the oracle.
+
+The solver loop reports prices and a certificate (g, U(X~)); the oracle
+re-evaluates both at the returned prices in FP64.  The dual optimum is also
+compared with the oracle's own solve.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2104_00282_amd as ra
+    c = ra.Context(0)
+    yield c
+    c.close()
+
+
+def _problem(ctx, torch, I):
+    import paper_2104_00282_amd as ra
+    T, w, c, kind = to_device(I, torch)
+    return ra.Problem(ctx, T, w, c, kind, I.R, I.eps)
+
+
+def _certificate(I, p):
+    d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+    U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, d.r, d.jobs)
+    return d.g, U
+
+
+def test_small_log_fp64(ctx, torch):
+    print("solve small-log", flush=True)
+    I = synth.small_log()
+    prob = _problem(ctx, torch, I)
+    p, info, st = prob.solve(tol_rel=1e-8, max_iter=300)
+    g, U = _certificate(I, p)
+    assert info["g"] == pytest.approx(g, rel=1e-11)
+    assert info["U_lb"] == pytest.approx(U, rel=1e-11)
+    po, io = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=1e-8, max_iter=300)
+    # both reach the dual optimum g(p*) = U*
+    assert info["g"] == pytest.approx(io["g"], rel=1e-6)
+    assert info["rel_gap"] <= 3 * max(io["rel_gap"], 1e-8)
+    assert np.allclose(p, po, rtol=1e-3)
+
+
+def test_mixed_fp32_certificate(ctx, torch):
+    print("solve mixed fp32", flush=True)
+    I = synth.random_small(50000, 8, seed=42, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    p, info, st = prob.solve(tol_rel=1e-5, max_iter=200)
+    assert info["rel_gap"] <= 1e-4
+    g, U = _certificate(I, p)
+    scale = abs(g) + abs(U)
+    assert abs(info["g"] - g) <= 1e-5 * scale
+    assert abs(info["U_lb"] - U) <= 1e-5 * scale
+    assert U <= g
+
+
+def test_graph_matches_direct(ctx, torch):
+    I = synth.random_small(20000, 16, seed=43, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    pa, ia, _ = prob.solve(tol_rel=1e-6, max_iter=40, use_graph=True)
+    pb, ib, _ = prob.solve(tol_rel=1e-6, max_iter=40, use_graph=False)
+    assert np.array_equal(pa, pb)
+    assert ia["g"] == ib["g"] and ia["iters"] == ib["iters"]
+
+
+def test_warm_start_and_subgradient(ctx, torch):
+    I = synth.random_small(20000, 4, seed=44, dtype=np.float32, log_frac=1.0)
+    prob = _problem(ctx, torch, I)
+    p, info, st = prob.solve(tol_rel=1e-5, max_iter=200)
+    assert info["converged"] == 1
+    p2, info2, _ = prob.solve(p0=p, tol_rel=1e-5, max_iter=5)
+    assert info2["converged"] == 1 and info2["iters"] == 0
+    p3, info3, _ = prob.solve(tol_rel=1e-5, max_iter=30, method=1)
+    d0 = prob.dual_eval(np.ones(4), lower_bound=True)
+    gap0 = (d0["g"] - d0["lower_bound"]) / abs(d0["g"])
+    assert info3["rel_gap"] < gap0 and info3["fell_back"] == info3["iters"]
+
+
+def test_allocation_matches_certificate(ctx, torch):
+    I = synth.random_small(30000, 8, seed=45, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    p, info, _ = prob.solve(tol_rel=1e-5, max_iter=100)
+    X = prob.allocation(p).double().cpu().numpy()
+    assert np.all(X >= 0)
+    assert np.all(X.sum(1) <= 1 + 1e-5)
+    assert np.all(X.sum(0) <= I.R * (1 + 1e-5))
+    assert np.all((X > 0).sum(1) <= 2)
+    t = np.einsum("ij,ij->i", I.T.astype(np.float64), X)
+    u = np.where(I.kind == 0, I.w * np.log(t + I.eps), I.w * np.minimum(t, I.c))
+    assert u.sum() == pytest.approx(info["U_lb"], rel=1e-5)
