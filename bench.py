@@ -15,6 +15,7 @@ timed on a bounded sample of rows on the host cores (CPU baseline).
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +25,10 @@ import numpy as np
 
 METRIC = "job·resource entries/s in ∇g (%HBM peak); time to 1e-6 gap, warm vs cold"
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SRC = os.path.join(ROOT, "paper_2104_00282_amd", "csrc", "kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "dual_eval_roofline64_counters.json")
+COPY_BYTES = 2_560_000_000  # bytes read (and written) by one calibration copy
 
 
 def log(msg):
@@ -31,16 +36,48 @@ def log(msg):
     sys.stderr.flush()
 
 
-def cpu_baseline(p, target_s=15.0, max_rows=2_000_000):
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def traffic_from_counters():
+    """HBM bytes per dual-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or
+    None when the kernel source changed after the counters were taken."""
+    try:
+        with open(COUNTERS) as f:
+            C = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if C.get("kernels_hip_sha256") != kernel_source_hash():
+        return None
+    return C.get("traffic_bytes_per_launch")
+
+
+def calibrate_copy(reps=5):
+    """A plain device copy of known size (for scaling rocprofv3's FETCH_SIZE and
+    WRITE_SIZE counters): COPY_BYTES read and COPY_BYTES written per copy."""
+    import torch
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": reps}))
+
+
+def cpu_baseline(p, target_s=12.0, max_rows=4_000_000):
     """The FP64 oracle's dual evaluation on rows [0, S) of the same instance."""
     import oracle
     import synth
-    T, kind, w, c = synth.roofline_rows(0, 4096)
+    cal = 65536
+    T, kind, w, c = synth.roofline_rows(0, cal)
     R = np.full(64, 0.1 * 1e7 / 64)
     t0 = time.perf_counter()
     oracle.dual_eval(T, w, c, kind, 1e-3, R, p)
-    per_row = (time.perf_counter() - t0) / 4096
-    rows = int(min(max_rows, max(4096, target_s / max(per_row, 1e-9))))
+    per_row = (time.perf_counter() - t0) / cal
+    rows = int(min(max_rows, max(cal, target_s / max(per_row, 1e-9))))
     rows = (rows // 4096) * 4096
     T, kind, w, c = synth.roofline_rows(0, rows)
     t0 = time.perf_counter()
@@ -55,11 +92,16 @@ def cpu_baseline(p, target_s=15.0, max_rows=2_000_000):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the plain copy used to scale the HBM counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
@@ -127,7 +169,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic_from_counters(),
             "kernel": "dual evaluation (k_dual_vec<64>)",
             "bytes_per_launch": bytes_per_launch,
             "launches": launches,

@@ -131,7 +131,7 @@ typedef struct {
     int32_t init;            /* 0 = p = 1, 1 = use p_inout as given                 */
     int32_t use_graph;       /* 1 = replay one captured HIP graph per evaluation    */
     int32_t verbose;         /* 1 = one line per iteration on stderr                */
-    int32_t max_evals;       /* > 0: stop after exactly this many dual evaluations  */
+    int32_t max_evals;       /* > 0: stop after at most this many passes over T      */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
@@ -150,9 +150,15 @@ typedef struct {
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit). */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
-/* Price discovery (§5, Algorithm 2). p_inout: host, m doubles; read when
- * opts->init == 1, and on return holds the prices with the smallest relative
- * gap seen (the reported certificate). info: host, may be NULL.
+/* Price discovery (§5, Algorithm 2). Every pass over T evaluates g and its
+ * gradient at the new prices and, in the same pass, the lower bound U(X~) of
+ * the previously evaluated prices, so a point's certificate (its duality
+ * gap) is known one pass after the point itself; a final pass certifies the
+ * last point when the evaluation budget allows.
+ * p_inout: host, m doubles; read when opts->init == 1, and on return holds
+ * the certified prices with the smallest relative gap (the reported
+ * certificate; U_lb is NaN and rel_gap +inf if no point could be certified
+ * within max_evals). info: host, may be NULL.
  * Returns RA_OK when the tolerance was met, RA_ENOTCONV when max_iter ended
  * the loop (p_inout and info are still filled), or an error. */
 ra_status ra_solve(ra_ctx *ctx, const ra_problem *prob, const ra_solve_opts *opts,

@@ -21,7 +21,7 @@
 // loads that each cover 1 KiB of consecutive bytes, stages it in LDS with a
 // padded row stride (conflict-free 16-byte row reads), and each lane then
 // solves one job from its own row.  The next tile is prefetched into
-// registers while the current one is solved.  Resource usage r_j is summed
+// registers (non-temporal loads) while the current one is solved.  Resource usage r_j is summed
 // per tile in a per-wave LDS histogram, folded into per-lane FP64
 // accumulators after every tile, reduced across the block in a fixed order
 // and written as one row of block partials; no global atomics are used, so
@@ -130,21 +130,17 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
                                           bool caplin, F eps, Job<F>& J)
 {
     const int j1 = scan_first<F, M>(a, mm, IP);
-    J.j1 = j1;
-    if (j1 < 0) {  // all-zero row: nothing can be bought, t = 0
-        J.jlo = J.jhi = -1;
-        J.xlo = J.xhi = J.tlo = J.thi = F(0);
-        J.v = utility(caplin, w, c, eps, F(0));
-        return;
-    }
-    int lo = -1, hi = j1;
+    // An all-zero row (j1 < 0) buys nothing: t = 0.  It runs through the same
+    // code with an empty segment so that every result has one definition.
+    const bool any = j1 >= 0;
+    int lo = -1, hi = any ? j1 : -1;
     F alo = F(0), plo = F(0);
-    F ahi = a.at(j1), phi = Pdyn[j1];
-    F t;
-    for (;;) {
+    F ahi = any ? a.at(j1) : F(1), phi = any ? Pdyn[j1] : F(0);
+    F t = F(0);
+    bool walk = any;
+    while (walk) {
         // segment [alo, ahi] of slope alpha = num / den (den > 0, num >= 0)
         const F num = phi - plo, den = ahi - alo;
-        bool walk;
         if (!caplin) {
             // eq. e-opt-t-log: t = clip((u')^{-1}(alpha), alo, ahi),
             // (u')^{-1}(alpha) = w / alpha - eps (+inf for alpha = 0)
@@ -158,39 +154,72 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
             t = fmin(fmax(c, alo), ahi);
             walk = c >= ahi;
         }
-        if (!walk) break;
-        const int jn = scan_next<F, M>(a, mm, P, ahi, phi);
-        if (jn < 0) {  // right end of the curve, t = max_j a_j
-            t = ahi;
-            break;
+        if (walk) {
+            const int jn = scan_next<F, M>(a, mm, P, ahi, phi);
+            if (jn < 0) {  // right end of the curve, t = max_j a_j
+                t = ahi;
+                walk = false;
+            } else {
+                lo = hi;
+                alo = ahi;
+                plo = phi;
+                hi = jn;
+                ahi = a.at(jn);
+                phi = Pdyn[jn];
+            }
         }
-        lo = hi;
-        alo = ahi;
-        plo = phi;
-        hi = jn;
-        ahi = a.at(jn);
-        phi = Pdyn[jn];
     }
     // eq. e-xixj on the final segment (lo = -1: the origin, x_hi = t / a_hi)
     const F den = ahi - alo;
-    F xhi = (t - alo) / den;
-    F xlo = (lo >= 0) ? (ahi - t) / den : F(0);
-    J.v = utility(caplin, w, c, eps, t) - (plo * xlo + phi * xhi);
-    if (xhi == F(0)) {  // at the left end: a single resource (or none)
-        hi = lo;
-        ahi = alo;
-        xhi = xlo;
-        lo = -1;
-        xlo = F(0);
-    } else if (xlo == F(0)) {
-        lo = -1;
+    const F xh = (t - alo) / den;
+    const F xl = (lo >= 0) ? (ahi - t) / den : F(0);
+    J.j1 = j1;
+    J.v = utility(caplin, w, c, eps, t) - (plo * xl + phi * xh);
+    // a zero share is not part of the support; a single resource is
+    // reported as (j_lo, j_hi) = (-1, j).  Written with selects only, so the
+    // result stays in registers.
+    const bool left = xh == F(0);   // t at the left end: only `lo` (or nothing)
+    const bool right = xl == F(0);  // only `hi`
+    J.jhi = left ? lo : hi;
+    J.jlo = (left | right) ? -1 : lo;
+    J.xhi = left ? xl : xh;
+    J.xlo = (left | right) ? F(0) : xl;
+    J.thi = left ? alo * xl : ahi * xh;
+    J.tlo = (left | right) ? F(0) : alo * xl;
+}
+
+__device__ __forceinline__ float dlog1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double dlog1p(double x) { return log1p(x); }
+
+// Lower-bound contribution of one job (§5): its allocation on (lo, hi) with
+// throughput parts tlo = a_lo x_lo, thi = a_hi x_hi is scaled per column by
+// s_j = min(1, R_j / r_j).  U = u(t~) with t~ = s_lo tlo + s_hi thi, and the
+// utility lost, du = u(t) - u(t~), is formed from t - t~ = (1 - s_lo) tlo +
+// (1 - s_hi) thi (1 - s_j given in FP64-rounded form) so that it keeps its
+// relative accuracy when the scales are close to 1.
+template <typename F>
+__device__ __forceinline__ void scaled_utility(bool caplin, F w, F c, F eps, int jlo, int jhi,
+                                               F tlo, F thi, const F* S, const F* SC, F& U,
+                                               F& du)
+{
+    const F tt = (jlo >= 0 ? S[jlo] * tlo : F(0)) + (jhi >= 0 ? S[jhi] * thi : F(0));
+    const F dt = (jlo >= 0 ? SC[jlo] * tlo : F(0)) + (jhi >= 0 ? SC[jhi] * thi : F(0));
+    U = utility(caplin, w, c, eps, tt);
+    if (!caplin) {
+        du = w * dlog1p(dt / (tt + eps));
+    } else {
+        const F t = tlo + thi;
+        du = (tt >= c) ? F(0) : (t <= c ? w * dt : w * (c - tt));
     }
-    J.jlo = lo;
-    J.jhi = hi;
-    J.xlo = xlo;
-    J.xhi = xhi;
-    J.tlo = (lo >= 0) ? alo * xlo : F(0);
-    J.thi = (hi >= 0) ? ahi * xhi : F(0);
+}
+
+// 16-byte streaming load with the non-temporal hint: every byte of T is read
+// once per evaluation, so it should not displace reusable lines in the caches.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 stream_load(const float4* p)
+{
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
 }
 
 template <int M>
@@ -223,17 +252,25 @@ __global__ void __launch_bounds__(256) k_dual_vec(
     constexpr int TR = 64;                      // rows per wave tile
     __shared__ __attribute__((aligned(16))) float tile[4][TR * S];
     __shared__ float hist[4][M];
-    __shared__ float ptab[M];
+    __shared__ float ptab[M], qtab[M], stab[M], sctab[M];
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const float* __restrict__ P = pb->p;
     const float* __restrict__ IP = pb->invp;
-    if (threadIdx.x < M) ptab[threadIdx.x] = P[threadIdx.x];
+    const float* __restrict__ Qp = pb->q;
+    const float* __restrict__ IQ = pb->invq;
+    const bool prev = pb->has_prev != 0;
+    if (threadIdx.x < M) {
+        ptab[threadIdx.x] = P[threadIdx.x];
+        qtab[threadIdx.x] = Qp[threadIdx.x];
+        stab[threadIdx.x] = pb->s[threadIdx.x];
+        sctab[threadIdx.x] = pb->sc[threadIdx.x];
+    }
     if (lane < M) hist[wv][lane] = 0.f;
     __syncthreads();
 
-    double racc = 0.0, vacc = 0.0;
+    double racc = 0.0, vacc = 0.0, uacc = 0.0, duacc = 0.0;
     const int64_t ntiles = (n + TR - 1) / TR;
     const int64_t nw = (int64_t)gridDim.x * 4;
     int64_t ti = (int64_t)blockIdx.x * 4 + wv;
@@ -244,14 +281,37 @@ __global__ void __launch_bounds__(256) k_dual_vec(
     auto load_tile = [&](int64_t tix) {
         const int64_t row0 = tix * TR;
         const int64_t rows = (n - row0) < TR ? (n - row0) : TR;
-        const int valid = (int)rows * Q;
         const float4* src = reinterpret_cast<const float4*>(T + row0 * M);
+        if (rows == TR) {
 #pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const int ch = lane + 64 * k;
-            pre[k] = (ch < valid) ? src[ch] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int k = 0; k < Q; ++k) pre[k] = stream_load(src + lane + 64 * k);
+            wcn = prm[row0 + lane];
+        } else {
+            const int valid = (int)rows * Q;
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const int ch = lane + 64 * k;
+                pre[k] = (ch < valid) ? stream_load(src + ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            wcn = (lane < rows) ? prm[row0 + lane] : make_float2(1.f, -1.f);
         }
-        wcn = (lane < rows) ? prm[row0 + lane] : make_float2(1.f, -1.f);
+    };
+
+    // Per-job outputs of a tile are kept in registers and stored at the start
+    // of the next iteration, before the following tile's loads are issued:
+    // the vector-memory counter retires in order, so waiting for a tile's
+    // loads then never waits for stores issued after them.
+    int64_t pend_i = -1;
+    int pend_jp = 0;
+    int16_t pend_j1 = 0;
+    float2 pend_x = make_float2(0.f, 0.f), pend_t = make_float2(0.f, 0.f);
+    auto flush_outputs = [&]() {
+        if (pend_i >= 0) {
+            if (jpair) jpair[pend_i] = pend_jp;
+            if (xpair) xpair[pend_i] = pend_x;
+            if (tpair) tpair[pend_i] = pend_t;
+            if (j1out) j1out[pend_i] = pend_j1;
+        }
     };
 
     if (ti < ntiles) load_tile(ti);
@@ -264,9 +324,11 @@ __global__ void __launch_bounds__(256) k_dual_vec(
         }
         const float2 wc = wcn;
         wave_sync();
+        flush_outputs();
         if (ti + nw < ntiles) load_tile(ti + nw);
 
         const int64_t i = ti * TR + lane;
+        pend_i = -1;
         if (i < n) {
             RegRow<M> row;
             row.lds = tl + lane * S;
@@ -279,14 +341,25 @@ __global__ void __launch_bounds__(256) k_dual_vec(
                 row.v[4 * q + 3] = v.w;
             }
             Job<float> J;
-            solve_job<float, M>(row, M, P, IP, ptab, wc.x, wc.y, wc.y >= 0.f, eps, J);
+            const bool caplin = wc.y >= 0.f;
+            solve_job<float, M>(row, M, P, IP, ptab, wc.x, wc.y, caplin, eps, J);
             if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], J.xhi);
             vacc += (double)J.v;
-            if (jpair) jpair[i] = (J.jlo & 0xffff) | (J.jhi << 16);
-            if (xpair) xpair[i] = make_float2(J.xlo, J.xhi);
-            if (tpair) tpair[i] = make_float2(J.tlo, J.thi);
-            if (j1out) j1out[i] = (int16_t)J.j1;
+            if (prev) {  // lower bound of the previous prices, same row
+                Job<float> K;
+                solve_job<float, M>(row, M, Qp, IQ, qtab, wc.x, wc.y, caplin, eps, K);
+                float u, loss;
+                scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab,
+                               u, loss);
+                uacc += (double)u;
+                duacc += (double)loss;
+            }
+            pend_i = i;
+            pend_jp = (J.jlo & 0xffff) | (J.jhi << 16);
+            pend_x = make_float2(J.xlo, J.xhi);
+            pend_t = make_float2(J.tlo, J.thi);
+            pend_j1 = (int16_t)J.j1;
         }
         wave_sync();
         if (lane < M) {
@@ -295,18 +368,28 @@ __global__ void __launch_bounds__(256) k_dual_vec(
         }
         wave_sync();
     }
+    flush_outputs();
 
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) vacc += __shfl_xor(vacc, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        vacc += __shfl_xor(vacc, off);
+        uacc += __shfl_xor(uacc, off);
+        duacc += __shfl_xor(duacc, off);
+    }
+    constexpr int NC = M + 3;
     __syncthreads();
     double* red = reinterpret_cast<double*>(&tile[0][0]);
-    if (lane < M) red[wv * (M + 1) + lane] = racc;
-    if (lane == 0) red[wv * (M + 1) + M] = vacc;
+    if (lane < M) red[wv * NC + lane] = racc;
+    if (lane == 0) {
+        red[wv * NC + M] = vacc;
+        red[wv * NC + M + 1] = uacc;
+        red[wv * NC + M + 2] = duacc;
+    }
     __syncthreads();
-    if (threadIdx.x < M + 1) {
+    if (threadIdx.x < NC) {
         const int t = threadIdx.x;
-        const double s = ((red[t] + red[(M + 1) + t]) + red[2 * (M + 1) + t]) + red[3 * (M + 1) + t];
-        partial[(int64_t)blockIdx.x * (M + 1) + t] = s;
+        const double s = ((red[t] + red[NC + t]) + red[2 * NC + t]) + red[3 * NC + t];
+        partial[(int64_t)blockIdx.x * NC + t] = s;
     }
 }
 
@@ -324,16 +407,17 @@ __global__ void __launch_bounds__(256) k_dual_gen(
 {
     constexpr int TR = 64;
     __shared__ F hist[4][256];
-    __shared__ double red[4][257];
+    __shared__ double red[4][259];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const F* __restrict__ P = pb->p;
     const F* __restrict__ IP = pb->invp;
+    const bool prev = pb->has_prev != 0;
     for (int j = lane; j < m; j += 64) hist[wv][j] = F(0);
     __syncthreads();
 
     double racc[4] = {0.0, 0.0, 0.0, 0.0};
-    double vacc = 0.0;
+    double vacc = 0.0, uacc = 0.0, duacc = 0.0;
     const int64_t ntiles = (n + TR - 1) / TR;
     const int64_t nw = (int64_t)gridDim.x * 4;
     for (int64_t ti = (int64_t)blockIdx.x * 4 + wv; ti < ntiles; ti += nw) {
@@ -342,10 +426,20 @@ __global__ void __launch_bounds__(256) k_dual_gen(
             GlobalRow<F> row{T + i * m};
             const V2<F> wc = prm[i];
             Job<F> J;
-            solve_job<F, 0>(row, m, P, IP, P, wc.x, wc.y, wc.y >= F(0), eps, J);
+            const bool caplin = wc.y >= F(0);
+            solve_job<F, 0>(row, m, P, IP, P, wc.x, wc.y, caplin, eps, J);
             if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], J.xhi);
             vacc += (double)J.v;
+            if (prev) {  // lower bound of the previous prices, same row
+                Job<F> K;
+                solve_job<F, 0>(row, m, pb->q, pb->invq, pb->q, wc.x, wc.y, caplin, eps, K);
+                F u, loss;
+                scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, pb->s, pb->sc,
+                               u, loss);
+                uacc += (double)u;
+                duacc += (double)loss;
+            }
             if (jpair) jpair[i] = (J.jlo & 0xffff) | (J.jhi << 16);
             if (xpair) xpair[i] = V2<F>{J.xlo, J.xhi};
             if (tpair) tpair[i] = V2<F>{J.tlo, J.thi};
@@ -361,16 +455,25 @@ __global__ void __launch_bounds__(256) k_dual_gen(
         }
         wave_sync();
     }
-    for (int off = 32; off > 0; off >>= 1) vacc += __shfl_xor(vacc, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        vacc += __shfl_xor(vacc, off);
+        uacc += __shfl_xor(uacc, off);
+        duacc += __shfl_xor(duacc, off);
+    }
     for (int k = 0; k < 4; ++k) {
         const int j = lane + 64 * k;
         if (j < m) red[wv][j] = racc[k];
     }
-    if (lane == 0) red[wv][m] = vacc;
+    if (lane == 0) {
+        red[wv][m] = vacc;
+        red[wv][m + 1] = uacc;
+        red[wv][m + 2] = duacc;
+    }
     __syncthreads();
-    for (int t = threadIdx.x; t < m + 1; t += 256) {
+    const int nc = m + 3;
+    for (int t = threadIdx.x; t < nc; t += 256) {
         const double s = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
-        partial[(int64_t)blockIdx.x * (m + 1) + t] = s;
+        partial[(int64_t)blockIdx.x * nc + t] = s;
     }
 }
 
@@ -400,9 +503,6 @@ __global__ void __launch_bounds__(256) k_reduce_cols(const double* __restrict__ 
 // t_i - t~_i = (1 - s_lo) a_lo x_lo + (1 - s_hi) a_hi x_hi, with 1 - s_j
 // computed in FP64, so it keeps its relative accuracy when s_j is close to 1.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ float dlog1p(float x) { return log1pf(x); }
-__device__ __forceinline__ double dlog1p(double x) { return log1p(x); }
-
 template <typename F>
 __global__ void __launch_bounds__(256) k_lower(const int* __restrict__ jpair,
                                                const V2<F>* __restrict__ tpair,
@@ -428,18 +528,9 @@ __global__ void __launch_bounds__(256) k_lower(const int* __restrict__ jpair,
         const int jhi = jp >> 16;
         const V2<F> tp = tpair[i];
         const V2<F> wc = prm[i];
-        const F tt = (jlo >= 0 ? s[jlo] * tp.x : F(0)) + (jhi >= 0 ? s[jhi] * tp.y : F(0));
-        const F dt = (jlo >= 0 ? sc[jlo] * tp.x : F(0)) + (jhi >= 0 ? sc[jhi] * tp.y : F(0));
-        const bool caplin = wc.y >= F(0);
-        const F w = wc.x, c = wc.y;
-        U += (double)utility(caplin, w, c, eps, tt);
-        F loss;
-        if (!caplin) {
-            loss = w * dlog1p(dt / (tt + eps));
-        } else {
-            const F t = tp.x + tp.y;
-            loss = (tt >= c) ? F(0) : (t <= c ? w * dt : w * (c - tt));
-        }
+        F u, loss;
+        scaled_utility(wc.y >= F(0), wc.x, wc.y, eps, jlo, jhi, tp.x, tp.y, s, sc, u, loss);
+        U += (double)u;
         du += (double)loss;
     }
     for (int off = 32; off > 0; off >>= 1) {

@@ -7,18 +7,30 @@
 namespace ra {
 
 // Device block of prices for one evaluation, written by the host before the
-// dual kernel runs. F is the problem's element type.
+// dual kernel runs. F is the problem's element type.  With has_prev set, the
+// same pass also returns the lower bound of the previously evaluated prices q:
+// the jobs are solved again at q, the used columns are scaled by s (the
+// column scales min(1, R_j / r_j) of r(q)) and the scaled utility is summed.
 template <typename F>
 struct PriceBlock {
     F p[256];     // prices rounded to F
     F invp[256];  // 1 / p_j (+inf where p_j = 0)
+    F q[256];     // previous prices
+    F invq[256];  // 1 / q_j
+    F s[256];     // column scales of r(q)
+    F sc[256];    // 1 - s_j, formed in FP64
+    int has_prev;
 };
+
+// Columns of one row of dual-kernel block partials: r_j (m), then the sums of
+// net utilities, of scaled utilities U(X~) and of utility lost by scaling.
+inline int partial_cols(int m) { return m + 3; }
 
 // Number of blocks one dual-kernel launch uses for n jobs with m resources.
 int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);
 
 // Dual evaluation (Algorithm 1 per job, sums into block partials).
-// partial: [grid][m + 1] doubles (r_j partials, then the net-utility sum).
+// partial: [grid][partial_cols(m)] doubles.
 // Optional outputs may be null: jpair (n x 2 int16), xpair (n x 2 F),
 // tpair (n x 2 F, a_lo x_lo and a_hi x_hi), j1 (n int16).
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,

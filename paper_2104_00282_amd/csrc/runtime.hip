@@ -96,7 +96,8 @@ size_t price_block_bytes(int dt)
 }
 
 // Fill the pinned price block from host prices; returns p^T R with the
-// rounded prices (the point the kernel actually evaluates).
+// rounded prices (the point the kernel actually evaluates).  The block asks
+// for no lower bound of a previous point (see fill_prev).
 double fill_prices(ra_problem* P, const double* p, std::vector<double>* prounded)
 {
     double pR = 0.0;
@@ -109,6 +110,7 @@ double fill_prices(ra_problem* P, const double* p, std::vector<double>* prounded
             pR += (double)pf * P->R[j];
             if (prounded) (*prounded)[j] = (double)pf;
         }
+        b->has_prev = 0;
     } else {
         auto* b = static_cast<ra::PriceBlock<double>*>(P->h_pblock);
         for (int j = 0; j < P->m; ++j) {
@@ -117,8 +119,34 @@ double fill_prices(ra_problem* P, const double* p, std::vector<double>* prounded
             pR += p[j] * P->R[j];
             if (prounded) (*prounded)[j] = p[j];
         }
+        b->has_prev = 0;
     }
     return pR;
+}
+
+// Ask the next pass for the lower bound of a previously evaluated point:
+// its (already rounded) prices q and the column scales of its usage r (§5).
+template <typename F>
+void fill_prev_t(ra_problem* P, const std::vector<double>& q, const std::vector<double>& r)
+{
+    auto* b = static_cast<ra::PriceBlock<F>*>(P->h_pblock);
+    for (int j = 0; j < P->m; ++j) {
+        const F qf = (F)q[j];
+        b->q[j] = qf;
+        b->invq[j] = qf > F(0) ? F(1) / qf : F(INFINITY);
+        const bool over = r[j] > P->R[j];
+        b->s[j] = over ? (F)(P->R[j] / r[j]) : F(1);
+        b->sc[j] = over ? (F)((r[j] - P->R[j]) / r[j]) : F(0);
+    }
+    b->has_prev = 1;
+}
+
+void fill_prev(ra_problem* P, const std::vector<double>& q, const std::vector<double>& r)
+{
+    if (P->dt == 0)
+        fill_prev_t<float>(P, q, r);
+    else
+        fill_prev_t<double>(P, q, r);
 }
 
 ra_status ensure_support_ws(ra_problem* P)
@@ -147,7 +175,7 @@ ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_
         RA_HIP(ctx, hipEventRecord(ctx->ev1, st));
         ctx->timed_pending = true;
     }
-    RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial, P->grid, P->m + 1, P->dout));
+    RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial, P->grid, ra::partial_cols(P->m), P->dout));
     if (lb) {
         RA_HIP(ctx, ra::launch_lower(P->dt, P->lgrid, st, jp, tp, P->prm, P->n, P->m, P->Rdev,
                                      P->dout, P->eps, P->partial2));
@@ -171,39 +199,52 @@ ra_status collect_timing(ra_ctx* ctx)
 }
 
 struct Eval {
-    double g = 0, U = 0, gap = 0, rel = 0, f = 0;
+    double g = 0, f = 0;
     std::vector<double> grad;  // gradient of f = g / n
     std::vector<double> p;     // the (rounded) prices evaluated
+    std::vector<double> r;     // usage r(p)
+    double pR = 0;
+    // certificate (§5): lower bound U(X~) of the column-scaled allocation,
+    // gap = g - U(X~) and the relative gap; valid when certified
+    bool certified = false;
+    double U = 0, gap = 0, rel = INFINITY;
 };
 
-// Results of the last evaluation from the pinned buffer.
-void read_eval(const ra_problem* P, double pR, Eval& E)
+// Dual value, gradient and usage of the last pass from the pinned buffer.
+void read_dual(const ra_problem* P, double pR, Eval& E)
 {
     const int m = P->m;
     const double* o = P->h_out;
+    E.pR = pR;
     E.g = pR + o[m];
-    double pq = 0.0;
+    E.f = E.g / (double)P->n;
     E.grad.resize(m);
-    for (int j = 0; j < m; ++j) {
-        const double q = P->R[j] - o[j];
-        pq += E.p[j] * q;
-        E.grad[j] = q / (double)P->n;
-    }
-    // gap = g - U(X~) = p^T (R - r) + sum_i [u(t_i) - u(t~_i)]
-    E.gap = pq + o[m + 2];
+    E.r.assign(o, o + m);
+    for (int j = 0; j < m; ++j) E.grad[j] = (P->R[j] - o[j]) / (double)P->n;
+    E.certified = false;
+}
+
+// Certificate of E from the scaled-utility sums su (sum of u(t~)) and sdu
+// (sum of u(t) - u(t~)) of its own allocation:
+// gap = g - U(X~) = p^T (R - r) + sum_i [u(t_i) - u(t~_i)].
+void certify(const ra_problem* P, double su, double sdu, Eval& E)
+{
+    (void)su;
+    double pq = 0.0;
+    for (int j = 0; j < P->m; ++j) pq += E.p[j] * (P->R[j] - E.r[j]);
+    E.gap = pq + sdu;
     E.U = E.g - E.gap;
     const double den = std::max(std::fabs(E.g), std::fabs(E.U));
     E.rel = E.gap / (den > 0 ? den : 1.0);
-    E.f = E.g / (double)P->n;
+    E.certified = true;
 }
 
 ra_status capture_graph(ra_problem* P)
 {
     ra_ctx* ctx = P->ctx;
     if (P->gexec) return RA_OK;
-    if (ensure_support_ws(P) != RA_OK) return RA_ENOMEM;
     RA_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    ra_status st = enqueue_eval(P, true, nullptr, nullptr, nullptr);
+    ra_status st = enqueue_eval(P, false, nullptr, nullptr, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->stream, &g);
     if (st != RA_OK) {
@@ -220,28 +261,32 @@ ra_status capture_graph(ra_problem* P)
     return RA_OK;
 }
 
-// One full evaluation at p (dual value, gradient, lower bound).
-ra_status evaluate(ra_problem* P, const double* p, bool use_graph, Eval& E)
+// One pass at p: dual value, gradient and usage at p, and -- when prev is
+// given -- the certificate of prev, computed in the same pass over T.
+ra_status evaluate(ra_problem* P, const double* p, Eval* prev, bool use_graph, Eval& E)
 {
     ra_ctx* ctx = P->ctx;
     E.p.resize(P->m);
     const double pR = fill_prices(P, p, &E.p);
+    if (prev) fill_prev(P, prev->p, prev->r);
     if (use_graph && !ctx->timing) {
         ra_status st = capture_graph(P);
         if (st != RA_OK) return st;
         RA_HIP(ctx, hipGraphLaunch(P->gexec, ctx->stream));
     } else {
-        if (ensure_support_ws(P) != RA_OK) return RA_ENOMEM;
-        ra_status st = enqueue_eval(P, true, nullptr, nullptr, nullptr);
+        ra_status st = enqueue_eval(P, false, nullptr, nullptr, nullptr);
         if (st != RA_OK) return st;
     }
     RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (collect_timing(ctx) != RA_OK) return RA_EDEVICE;
-    read_eval(P, pR, E);
-    if (!std::isfinite(E.g) || !std::isfinite(E.gap))
-        return fail(ctx, RA_ENUMERIC, "non-finite dual value or gap");
+    read_dual(P, pR, E);
+    if (!std::isfinite(E.g)) return fail(ctx, RA_ENUMERIC, "non-finite dual value");
     for (double q : E.grad)
         if (!std::isfinite(q)) return fail(ctx, RA_ENUMERIC, "non-finite gradient");
+    if (prev) {
+        certify(P, P->h_out[P->m + 1], P->h_out[P->m + 2], *prev);
+        if (!std::isfinite(prev->gap)) return fail(ctx, RA_ENUMERIC, "non-finite duality gap");
+    }
     return RA_OK;
 }
 
@@ -403,7 +448,7 @@ ra_status ra_problem_create(ra_ctx* ctx, ra_problem** out, int64_t n, int32_t m,
     } while (0)
     RA_ALLOC(hipMalloc(&P->prm, (size_t)n * 2 * elt(P->dt)));
     RA_ALLOC(hipMalloc(&P->Rdev, sizeof(double) * m));
-    RA_ALLOC(hipMalloc(&P->partial, sizeof(double) * (size_t)P->grid * (m + 1)));
+    RA_ALLOC(hipMalloc(&P->partial, sizeof(double) * (size_t)P->grid * ra::partial_cols(m)));
     RA_ALLOC(hipMalloc(&P->partial2, sizeof(double) * (size_t)P->lgrid * 2));
     RA_ALLOC(hipMalloc(&P->dout, sizeof(double) * (m + 3)));
     RA_ALLOC(hipMalloc(&P->pblock, price_block_bytes(P->dt)));
@@ -458,13 +503,17 @@ ra_status ra_dual_eval(ra_ctx* ctx, const ra_problem* prob, const double* p, dou
     if (st != RA_OK) return st;
     RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (collect_timing(ctx) != RA_OK) return RA_EDEVICE;
-    read_eval(P, pR, E);
+    read_dual(P, pR, E);
     if (!std::isfinite(E.g)) return fail(ctx, RA_ENUMERIC, "non-finite dual value");
     for (int j = 0; j < P->m; ++j)
         if (!std::isfinite(P->h_out[j])) return fail(ctx, RA_ENUMERIC, "non-finite usage");
+    if (lb) {
+        certify(P, P->h_out[P->m + 1], P->h_out[P->m + 2], E);
+        if (!std::isfinite(E.U)) return fail(ctx, RA_ENUMERIC, "non-finite lower bound");
+        *lower_bound = E.U;
+    }
     *g = E.g;
     for (int j = 0; j < P->m; ++j) grad[j] = P->R[j] - P->h_out[j];
-    if (lb) *lower_bound = E.U;
     return RA_OK;
 }
 
@@ -509,35 +558,48 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
     // the NULL stream cannot be captured
     const bool graph = o.use_graph && ctx->stream != nullptr;
 
-    Eval E, En, best;
+    // cur: current iterate; trial: line-search point; pend: the last point
+    // evaluated, whose certificate arrives with the next pass; best: the
+    // certified point with the smallest relative gap
+    Eval cur, trial, pend, best;
     int evals = 0, iters = 0, fallbacks = 0, sg_steps = 0;
-    ra_status st = evaluate(P, p.data(), graph, E);
+    bool have_pend = false, done = false;
+    auto budget_left = [&]() { return o.max_evals == 0 || evals < o.max_evals; };
+
+    // One pass over T at x: evaluates x and certifies the pending point.
+    auto pass = [&](const std::vector<double>& x, Eval& out) -> ra_status {
+        ra_status s = evaluate(P, x.data(), have_pend ? &pend : nullptr, graph, out);
+        if (s != RA_OK) return s;
+        if (have_pend) {
+            if (o.verbose)
+                fprintf(stderr, "iteration %02d | utility=%.6f | dual_value=%.6f | gap=%.2e\n",
+                        evals - 1, pend.U / (double)P->n, pend.g / (double)P->n,
+                        pend.gap / (double)P->n);
+            if (!best.certified || pend.rel < best.rel) best = pend;
+            if (pend.rel <= o.tol_rel) done = true;
+        }
+        ++evals;
+        pend = out;
+        have_pend = true;
+        return RA_OK;
+    };
+
+    ra_status st = pass(p, cur);
     if (st != RA_OK) return st;
-    ++evals;
-    best = E;
 
     // L-BFGS memory: ring of (s, y, 1/s^T y)
     const int M = o.lbfgs_mem;
     std::vector<std::vector<double>> S(M, std::vector<double>(m)), Y(M, std::vector<double>(m));
-    std::vector<double> rho(M), alpha(M), d(m), q(m), pn(m), step(m);
+    std::vector<double> rho(M), alpha(M), d(m), q(m), pn(m), step(m), yv(m);
     int npairs = 0, head = 0;
-    auto log_line = [&](int k, const Eval& e) {
-        if (o.verbose)
-            fprintf(stderr, "iteration %02d | utility=%.6f | dual_value=%.6f | gap=%.2e\n", k,
-                    e.U / (double)P->n, e.g / (double)P->n, e.gap / (double)P->n);
-    };
-    log_line(0, E);
-    // evaluation budget (max_evals > 0): the loop ends after exactly that many
-    auto budget_left = [&]() { return o.max_evals == 0 || evals < o.max_evals; };
     bool out_of_budget = false;
 
-    for (; iters < o.max_iter; ++iters) {
-        if (E.rel <= o.tol_rel) break;
+    for (; iters < o.max_iter && !done; ++iters) {
         if (!budget_left()) break;
         bool took = false;
         if (o.method == 0) {
             // two-loop recursion: q = H grad
-            q = E.grad;
+            q = cur.grad;
             for (int h = 0; h < npairs; ++h) {
                 const int s = (head - 1 - h + M) % M;
                 alpha[h] = rho[s] * dotv(S[s], q);
@@ -554,17 +616,17 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
                 for (int j = 0; j < m; ++j) q[j] += S[s][j] * (alpha[h] - b);
             }
             // keep prices at zero that the direction would push negative
-            for (int j = 0; j < m; ++j) d[j] = (E.p[j] <= 0.0 && q[j] > 0.0) ? 0.0 : -q[j];
-            if (dotv(d, E.grad) >= 0.0) {
+            for (int j = 0; j < m; ++j) d[j] = (cur.p[j] <= 0.0 && q[j] > 0.0) ? 0.0 : -q[j];
+            if (dotv(d, cur.grad) >= 0.0) {
                 npairs = 0;
                 for (int j = 0; j < m; ++j)
-                    d[j] = (E.p[j] <= 0.0 && E.grad[j] > 0.0) ? 0.0 : -E.grad[j];
+                    d[j] = (cur.p[j] <= 0.0 && cur.grad[j] > 0.0) ? 0.0 : -cur.grad[j];
             }
             const double dn = inf_norm(d);
             if (dn == 0.0) break;
             double lam = 1.0;
             if (npairs == 0) {
-                const double pi = inf_norm(E.p);
+                const double pi = inf_norm(cur.p);
                 lam = 0.1 * (pi > 0.0 ? pi : 1.0) / dn;
             }
             for (int ls = 0; ls < 20; ++ls) {
@@ -572,21 +634,20 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
                     out_of_budget = true;
                     break;
                 }
-                for (int j = 0; j < m; ++j) pn[j] = std::max(E.p[j] + lam * d[j], 0.0);
-                st = evaluate(P, pn.data(), graph, En);
+                for (int j = 0; j < m; ++j) pn[j] = std::max(cur.p[j] + lam * d[j], 0.0);
+                st = pass(pn, trial);
                 if (st != RA_OK) return st;
-                ++evals;
-                if (En.rel < best.rel) best = En;
-                for (int j = 0; j < m; ++j) step[j] = En.p[j] - E.p[j];
-                if (En.rel <= o.tol_rel || En.f <= E.f + 1e-4 * dotv(E.grad, step)) {
+                if (done) break;
+                for (int j = 0; j < m; ++j) step[j] = trial.p[j] - cur.p[j];
+                if (trial.f <= cur.f + 1e-4 * dotv(cur.grad, step)) {  // Armijo
                     took = true;
                     break;
                 }
                 lam *= 0.5;
             }
+            if (done || out_of_budget) break;
             if (took) {
-                std::vector<double> yv(m);
-                for (int j = 0; j < m; ++j) yv[j] = En.grad[j] - E.grad[j];
+                for (int j = 0; j < m; ++j) yv[j] = trial.grad[j] - cur.grad[j];
                 const double sy = dotv(step, yv);
                 if (sy > 1e-12 * std::sqrt(dotv(step, step) * dotv(yv, yv))) {
                     S[head] = step;
@@ -598,39 +659,42 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
             } else {
                 npairs = 0;
             }
-            if (out_of_budget) break;
         }
         if (!took) {
-            if (!budget_left()) break;
             // projected subgradient step p - a_k q with a_k = a0 / sqrt(k)
+            if (!budget_left()) break;
             ++sg_steps;
             ++fallbacks;
-            const double gi = inf_norm(E.grad), pi = inf_norm(E.p);
+            const double gi = inf_norm(cur.grad), pi = inf_norm(cur.p);
             const double a0 = gi > 0.0 ? 0.1 * (pi > 0.0 ? pi : 1.0) / gi : 0.0;
             const double ak = a0 / std::sqrt((double)sg_steps);
-            for (int j = 0; j < m; ++j) pn[j] = std::max(E.p[j] - ak * E.grad[j], 0.0);
-            st = evaluate(P, pn.data(), graph, En);
+            for (int j = 0; j < m; ++j) pn[j] = std::max(cur.p[j] - ak * cur.grad[j], 0.0);
+            st = pass(pn, trial);
             if (st != RA_OK) return st;
-            ++evals;
-            if (En.rel < best.rel) best = En;
+            if (done) break;
         }
-        std::swap(E, En);
-        log_line(iters + 1, E);
+        cur = trial;
     }
-    if (E.rel < best.rel) best = E;
-    const bool conv = best.rel <= o.tol_rel;
+    // the last point evaluated still awaits its certificate
+    if (!done && have_pend && budget_left()) {
+        Eval tail;
+        st = pass(pend.p, tail);
+        if (st != RA_OK) return st;
+    }
+    const bool conv = best.certified && best.rel <= o.tol_rel;
+    const Eval& ret = best.certified ? best : pend;
     if (o.verbose)
         fprintf(stderr, "%s in %03d iterations, with residual %g\n",
-                conv ? "Converged" : "Stopped", iters, best.gap / (double)P->n);
-    for (int j = 0; j < m; ++j) p_inout[j] = best.p[j];
+                conv ? "Converged" : "Stopped", iters, ret.gap / (double)P->n);
+    for (int j = 0; j < m; ++j) p_inout[j] = ret.p[j];
     if (info) {
         info->iters = iters;
         info->dual_evals = evals;
         info->fell_back = fallbacks;
         info->converged = conv ? 1 : 0;
-        info->g = best.g;
-        info->U_lb = best.U;
-        info->rel_gap = best.rel;
+        info->g = ret.g;
+        info->U_lb = ret.certified ? ret.U : NAN;
+        info->rel_gap = ret.certified ? ret.rel : INFINITY;
         info->seconds =
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }

@@ -1,0 +1,81 @@
+"""CPU checks of the C ABI: the built library loads and exports every function
+include/resalloc.h declares; calls that need no device behave as documented."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "resalloc.h")
+LIB = os.path.join(ROOT, "paper_2104_00282_amd", "libresalloc.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ra_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libresalloc.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for fn in ("ra_create", "ra_destroy", "ra_problem_create", "ra_dual_eval", "ra_solve",
+               "ra_get_allocation", "ra_status_string", "ra_last_error"):
+        assert fn in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, missing
+    for f in declared_functions():
+        getattr(lib, f)
+
+
+def test_binding_names_match_header():
+    from paper_2104_00282_amd import _capi
+    assert set(_capi.PROTOTYPES) == set(declared_functions())
+
+
+def test_status_strings_and_defaults(lib):
+    import paper_2104_00282_amd as ra
+    assert ra.ra_status_string(ra.RA_OK) == "ok"
+    assert ra.ra_status_string(ra.RA_ENOTCONV) == "not converged"
+    assert ra.ra_status_string(99) == "unknown status"
+    o = ra.ra_solve_opts_default()
+    assert (o.tol_rel, o.max_iter, o.lbfgs_mem, o.method, o.init, o.use_graph, o.max_evals) == \
+        (1e-6, 500, 10, 0, 0, 1, 0)
+
+
+def test_null_arguments_rejected_without_device(lib):
+    import paper_2104_00282_amd as ra
+    L = ra._capi.lib()
+    assert L.ra_create(None, 0, None) == ra.RA_EINVAL
+    assert L.ra_destroy(None) == ra.RA_OK
+    assert L.ra_problem_destroy(None) == ra.RA_OK
+    assert L.ra_dual_eval(None, None, None, None, None, None, None, None, None) == ra.RA_EINVAL
+    assert L.ra_solve(None, None, None, None, None) == ra.RA_EINVAL
+    assert L.ra_get_allocation(None, None, None, None) == ra.RA_EINVAL
+    assert L.ra_set_kernel_timing(None, 1) == ra.RA_EINVAL
+    assert L.ra_last_error(None) == b""
+
+
+def test_create_without_gpu_reports_device_error():
+    """In a container without a GPU, ra_create fails cleanly (no crash)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    import paper_2104_00282_amd as ra
+    with pytest.raises(ra.RAError) as e:
+        ra.ra_create(0)
+    assert e.value.status == ra.RA_EDEVICE
