@@ -169,6 +169,29 @@ ra_status ra_solve(ra_ctx *ctx, const ra_problem *prob, const ra_solve_opts *opt
  * the subproblem solutions at p (at most two nonzeros per row, §4.1). */
 ra_status ra_get_allocation(ra_ctx *ctx, const ra_problem *prob, const double *p, void *X);
 
+/* Batched price discovery: B problems of one context solved together.
+ * Each problem runs its own price loop (as ra_solve, same options); every
+ * round evaluates all problems still running in one persistent kernel launch
+ * (problems laid end to end, each wavefront streaming a byte-balanced
+ * contiguous share), replayed from one captured HIP graph per round.  The
+ * launch's grid size is chosen by timing candidates on the first round of a
+ * new batch shape (cached in the context, and in the text file named by the
+ * environment variable RESALLOC_TUNE_CACHE when it is set).
+ *   B         number of problems (>= 1)
+ *   probs     host, B problem handles created on ctx; each FP32 with m in
+ *             {4, 8, 16, 32} and T 16-byte aligned, else RA_EUNSUPPORTED
+ *   opts      shared options (init = 1 reads p_inout); NULL = defaults
+ *   tol_each  host, B per-problem tolerances replacing opts->tol_rel, or NULL
+ *   p_inout   host, sum of the problems' m doubles, problem b's prices at
+ *             offset m_0 + ... + m_{b-1}; on return each problem's certified
+ *             prices with the smallest relative gap
+ *   infos     host, B results, or NULL (seconds = wall time of the batch)
+ * Returns RA_OK when every problem met its tolerance, RA_ENOTCONV otherwise
+ * (outputs filled), or an error. */
+ra_status ra_batch_solve(ra_ctx *ctx, int32_t B, ra_problem *const *probs,
+                         const ra_solve_opts *opts, const double *tol_each, double *p_inout,
+                         ra_solve_info *infos);
+
 /* Kernel timing on the context's stream (for benchmarks and profiling).
  * enable = 1 brackets every launch of the dual kernel with a pair of HIP
  * events on the context's stream and accumulates the elapsed times; while it

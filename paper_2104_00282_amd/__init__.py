@@ -19,13 +19,13 @@ from ._capi import (RA_EDEVICE, RA_EINVAL, RA_ENOMEM, RA_ENOTCONV, RA_ENUMERIC, 
                     ra_destroy, ra_dual_eval, ra_get_allocation, ra_last_error, ra_problem_create,
                     ra_problem_destroy, ra_solve, ra_solve_info, ra_solve_opts,
                     ra_solve_opts_default, ra_status_string, ra_set_kernel_timing,
-                    ra_get_kernel_timing)
+                    ra_get_kernel_timing, ra_batch_solve)
 
 __all__ = [
     "Context", "Problem", "RAError", "ra_create", "ra_destroy", "ra_status_string",
     "ra_last_error", "ra_problem_create", "ra_problem_destroy", "ra_dual_eval",
     "ra_solve_opts_default", "ra_solve", "ra_get_allocation", "ra_solve_opts", "ra_solve_info",
-    "ra_set_kernel_timing", "ra_get_kernel_timing",
+    "ra_set_kernel_timing", "ra_get_kernel_timing", "ra_batch_solve", "batch_solve",
 ]
 
 
@@ -165,3 +165,37 @@ class Problem:
         X = torch.empty((self.n, self.m), dtype=self.dtype, device=self.T.device)
         ra_get_allocation(self.ctx.handle, self.handle, _hbuf(p), _dptr(X))
         return X
+
+
+def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lbfgs_mem=10,
+                method=0, use_graph=True, max_evals=0):
+    """Solve several Problems of one Context together (ra_batch_solve).
+    Returns (list of price arrays, list of info dicts, status)."""
+    if not problems:
+        raise ValueError("no problems")
+    ctx = problems[0].ctx
+    B = len(problems)
+    o = ra_solve_opts_default()
+    o.tol_rel = tol_rel
+    o.max_iter = max_iter
+    o.lbfgs_mem = lbfgs_mem
+    o.method = method
+    o.use_graph = 1 if use_graph else 0
+    o.max_evals = max_evals
+    ms = [pr.m for pr in problems]
+    offs = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+    p = np.ones(int(offs[-1]))
+    if p0 is not None:
+        for b, pb in enumerate(p0):
+            p[offs[b]:offs[b + 1]] = np.asarray(pb, dtype=np.float64)
+        o.init = 1
+    handles = (ctypes.c_void_p * B)(*[pr.handle for pr in problems])
+    infos = (ra_solve_info * B)()
+    tol = None
+    if tol_each is not None:
+        tol = np.ascontiguousarray(np.asarray(tol_each, dtype=np.float64))
+    st = ra_batch_solve(ctx.handle, B, handles, o, _hbuf(tol) if tol is not None else None,
+                        _hbuf(p), infos)
+    out_p = [p[offs[b]:offs[b + 1]].copy() for b in range(B)]
+    out_i = [{f: getattr(infos[b], f) for f, _ in ra_solve_info._fields_} for b in range(B)]
+    return out_p, out_i, st

@@ -57,6 +57,8 @@ PROTOTYPES = {
     "ra_solve": (_st, [_vp, _vp, ctypes.POINTER(ra_solve_opts), _vp,
                        ctypes.POINTER(ra_solve_info)]),
     "ra_get_allocation": (_st, [_vp, _vp, _vp, _vp]),
+    "ra_batch_solve": (_st, [_vp, _i32, _vp, ctypes.POINTER(ra_solve_opts), _vp, _vp,
+                             _vp]),
     "ra_set_kernel_timing": (_st, [_vp, _int]),
     "ra_get_kernel_timing": (_st, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
 }
@@ -163,3 +165,13 @@ def ra_get_kernel_timing(ctx):
     if st != RA_OK:
         raise RAError(st, ra_last_error(ctx))
     return ms.value, k.value
+
+
+def ra_batch_solve(ctx, B, probs, opts, tol_each, p_inout, infos):
+    """probs: ctypes array of problem handles; infos: ctypes array of
+    ra_solve_info (or None)."""
+    st = lib().ra_batch_solve(ctx, B, probs, ctypes.byref(opts) if opts is not None else None,
+                              tol_each, p_inout, infos)
+    if st not in (RA_OK, RA_ENOTCONV):
+        raise RAError(st, ra_last_error(ctx))
+    return st

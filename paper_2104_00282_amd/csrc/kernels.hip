@@ -478,6 +478,184 @@ __global__ void __launch_bounds__(256) k_dual_gen(
 }
 
 // ------------------------------------------------------------------------
+// Batched dual kernel: many FP32 problems with m in {4, 8, 16, 32} evaluated
+// in one persistent launch per price iteration.  The host lays the active
+// problems' 64-job tiles end to end and gives each wavefront a contiguous
+// chunk of that tile space, balanced by bytes.  A wave keeps FP64
+// accumulators for the problem it is in and writes them to its next partial
+// slot whenever it crosses into another problem, so the slots of one problem
+// are contiguous and are summed in a fixed order by k_batch_reduce.
+// ------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void batch_tile(const BatchItem& it, int64_t tile, float* tl,
+                                           float* hist, const float* __restrict__ P,
+                                           const float* __restrict__ IP,
+                                           const float* __restrict__ Qp,
+                                           const float* __restrict__ IQ, const float* ptab,
+                                           const float* qtab, const float* stab,
+                                           const float* sctab, bool prev, int lane,
+                                           double& racc, double& vacc, double& uacc,
+                                           double& duacc)
+{
+    constexpr int Q = M / 4;
+    constexpr int S = M + ((Q & 1) ? 0 : 4);
+    const int64_t row0 = tile * 64;
+    const int rows = (int)((it.n - row0) < 64 ? (it.n - row0) : 64);
+    const float4* src = reinterpret_cast<const float4*>(it.T + row0 * M);
+    const int valid = rows * Q;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int ch = lane + 64 * k;
+        if (ch < valid) {
+            const int r = ch / Q, q = ch % Q;
+            *reinterpret_cast<float4*>(tl + r * S + 4 * q) = stream_load(src + ch);
+        }
+    }
+    const float2 wc = (lane < rows) ? it.prm[row0 + lane] : make_float2(1.f, -1.f);
+    wave_sync();
+    if (lane < rows) {
+        RegRow<M> row;
+        row.lds = tl + lane * S;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
+            row.v[4 * q + 0] = v.x;
+            row.v[4 * q + 1] = v.y;
+            row.v[4 * q + 2] = v.z;
+            row.v[4 * q + 3] = v.w;
+        }
+        const bool caplin = wc.y >= 0.f;
+        const float eps = it.eps;
+        Job<float> J;
+        solve_job<float, M>(row, M, P, IP, ptab, wc.x, wc.y, caplin, eps, J);
+        if (J.jlo >= 0) atomicAdd(&hist[J.jlo], J.xlo);
+        if (J.jhi >= 0) atomicAdd(&hist[J.jhi], J.xhi);
+        vacc += (double)J.v;
+        if (prev) {
+            Job<float> K;
+            solve_job<float, M>(row, M, Qp, IQ, qtab, wc.x, wc.y, caplin, eps, K);
+            float u, loss;
+            scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab, u,
+                           loss);
+            uacc += (double)u;
+            duacc += (double)loss;
+        }
+    }
+    wave_sync();
+    if (lane < M) {
+        racc += (double)hist[lane];
+        hist[lane] = 0.f;
+    }
+    wave_sync();
+}
+
+__global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict__ items,
+                                                    const float* __restrict__ prices,
+                                                    const int* __restrict__ chunk,
+                                                    const int* __restrict__ segbase,
+                                                    double* __restrict__ partial)
+{
+    constexpr int SMAX = BATCH_MAX_M + 4;
+    __shared__ __attribute__((aligned(16))) float tile[4][64 * SMAX];
+    __shared__ float hist[4][BATCH_MAX_M];
+    __shared__ float tabs[4][4][BATCH_MAX_M];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int w = blockIdx.x * 4 + wv;
+    const int t0 = chunk[w], t1 = chunk[w + 1];
+    float* tl = tile[wv];
+    float* hs = hist[wv];
+    if (lane < BATCH_MAX_M) hs[lane] = 0.f;
+    wave_sync();
+    if (t0 >= t1) return;
+
+    // problem of the first tile: the last item with tile0 <= t0
+    int a = 0;
+    while (items[a + 1].tile0 <= t0) ++a;  // items[n_active].tile0 = total tiles
+    int slot = segbase[w];
+    int cur = -1;
+    BatchItem it;
+    const float *P = nullptr, *IP = nullptr, *Qp = nullptr, *IQ = nullptr;
+    double racc = 0.0, vacc = 0.0, uacc = 0.0, duacc = 0.0;
+    auto flush = [&]() {
+        for (int off = 32; off > 0; off >>= 1) {
+            vacc += __shfl_xor(vacc, off);
+            uacc += __shfl_xor(uacc, off);
+            duacc += __shfl_xor(duacc, off);
+        }
+        double* out = partial + (int64_t)slot * BATCH_COLS;
+        if (lane < BATCH_MAX_M) out[lane] = (lane < it.m) ? racc : 0.0;
+        if (lane == 0) {
+            out[BATCH_MAX_M] = vacc;
+            out[BATCH_MAX_M + 1] = uacc;
+            out[BATCH_MAX_M + 2] = duacc;
+        }
+        ++slot;
+        racc = vacc = uacc = duacc = 0.0;
+    };
+    for (int t = t0; t < t1; ++t) {
+        while (items[a + 1].tile0 <= t) ++a;
+        if (a != cur) {
+            if (cur >= 0) flush();
+            cur = a;
+            it = items[a];
+            const float* pr = prices + (int64_t)a * 6 * BATCH_MAX_M;
+            P = pr;
+            IP = pr + BATCH_MAX_M;
+            Qp = pr + 2 * BATCH_MAX_M;
+            IQ = pr + 3 * BATCH_MAX_M;
+            if (lane < it.m) {
+                tabs[wv][0][lane] = pr[lane];
+                tabs[wv][1][lane] = pr[2 * BATCH_MAX_M + lane];
+                tabs[wv][2][lane] = pr[4 * BATCH_MAX_M + lane];
+                tabs[wv][3][lane] = pr[5 * BATCH_MAX_M + lane];
+            }
+            wave_sync();
+        }
+        const int64_t lt = t - it.tile0;
+        const bool prev = it.has_prev != 0;
+        const float* pt = tabs[wv][0];
+        const float* qt = tabs[wv][1];
+        const float* st = tabs[wv][2];
+        const float* sct = tabs[wv][3];
+        switch (it.m) {
+        case 4:
+            batch_tile<4>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
+                          uacc, duacc);
+            break;
+        case 8:
+            batch_tile<8>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
+                          uacc, duacc);
+            break;
+        case 16:
+            batch_tile<16>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
+                           uacc, duacc);
+            break;
+        default:
+            batch_tile<32>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
+                           uacc, duacc);
+            break;
+        }
+    }
+    flush();
+}
+
+// out[a][c] = sum of partial slots [seg[2a], seg[2a+1]] of column c.
+__global__ void __launch_bounds__(64) k_batch_reduce(const double* __restrict__ partial,
+                                                     const int* __restrict__ seg,
+                                                     const int* __restrict__ header,
+                                                     double* __restrict__ out)
+{
+    const int a = blockIdx.x;
+    if (a >= header[0]) return;
+    const int c = threadIdx.x;
+    if (c >= BATCH_COLS) return;
+    double s = 0.0;
+    for (int k = seg[2 * a]; k <= seg[2 * a + 1]; ++k) s += partial[(int64_t)k * BATCH_COLS + c];
+    out[(int64_t)a * BATCH_COLS + c] = s;
+}
+
+// ------------------------------------------------------------------------
 // Column reduction of block partials: one block per column, fixed order.
 // ------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_reduce_cols(const double* __restrict__ partial, int nb,
@@ -681,6 +859,22 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
             static_cast<const PriceBlock<double>*>(prices), eps, partial, jp,
             static_cast<double2*>(xpair), static_cast<double2*>(tpair), j1);
     }
+    return hipGetLastError();
+}
+
+int batch_blocks_per_cu()
+{
+    static int occ = 0;
+    if (occ == 0) occ = occupancy_blocks(k_dual_batch);
+    return occ;
+}
+
+hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
+                        const float* prices, const int* chunk, const int* segbase,
+                        const int* seg, const int* header, double* partial, double* out)
+{
+    k_dual_batch<<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+    k_batch_reduce<<<max_items, 64, 0, st>>>(partial, seg, header, out);
     return hipGetLastError();
 }
 

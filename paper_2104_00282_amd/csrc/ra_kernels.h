@@ -26,6 +26,30 @@ struct PriceBlock {
 // net utilities, of scaled utilities U(X~) and of utility lost by scaling.
 inline int partial_cols(int m) { return m + 3; }
 
+// One active problem of a batched evaluation (FP32, m in {4, 8, 16, 32}).
+// items[n_active] is a sentinel whose tile0 is the total tile count.
+constexpr int BATCH_MAX_M = 32;
+constexpr int BATCH_COLS = BATCH_MAX_M + 3;  // r_j (padded), net utility, U(X~), loss
+struct BatchItem {
+    const float* T;      // n x m row-major, 16-byte aligned
+    const float2* prm;   // packed (w, c) per job
+    int64_t n;
+    int m;
+    int tile0;           // first tile of this problem in the batch's tile space
+    float eps;
+    int has_prev;        // the pass also certifies the problem's previous prices
+};
+
+// Batched evaluation: k_dual_batch (grid blocks of 4 waves; wave w covers
+// tiles [chunk[w], chunk[w+1]) and writes partial slots from segbase[w]) and
+// k_batch_reduce (problem a sums slots seg[2a]..seg[2a+1] into out[a][*]).
+// prices: per item 6 x BATCH_MAX_M floats (p, 1/p, q, 1/q, s, 1 - s);
+// header[0] = number of active items.
+int batch_blocks_per_cu();
+hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
+                        const float* prices, const int* chunk, const int* segbase,
+                        const int* seg, const int* header, double* partial, double* out);
+
 // Number of blocks one dual-kernel launch uses for n jobs with m resources.
 int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);
 

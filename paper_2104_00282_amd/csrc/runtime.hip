@@ -11,6 +11,7 @@
 // of net utilities), lower-bound kernel (feasible allocation by column
 // scaling) and its reduction, copy results out.  The price update (step 3)
 // is a projected L-BFGS on the host over m doubles.
+#include "price_loop.hpp"
 #include "ra_kernels.h"
 #include "resalloc.h"
 
@@ -18,6 +19,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -38,6 +41,7 @@ struct ra_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
+    std::map<std::string, int> batch_tuned;  // batch shape -> blocks per CU
 };
 
 struct ra_problem {
@@ -198,47 +202,6 @@ ra_status collect_timing(ra_ctx* ctx)
     return RA_OK;
 }
 
-struct Eval {
-    double g = 0, f = 0;
-    std::vector<double> grad;  // gradient of f = g / n
-    std::vector<double> p;     // the (rounded) prices evaluated
-    std::vector<double> r;     // usage r(p)
-    double pR = 0;
-    // certificate (§5): lower bound U(X~) of the column-scaled allocation,
-    // gap = g - U(X~) and the relative gap; valid when certified
-    bool certified = false;
-    double U = 0, gap = 0, rel = INFINITY;
-};
-
-// Dual value, gradient and usage of the last pass from the pinned buffer.
-void read_dual(const ra_problem* P, double pR, Eval& E)
-{
-    const int m = P->m;
-    const double* o = P->h_out;
-    E.pR = pR;
-    E.g = pR + o[m];
-    E.f = E.g / (double)P->n;
-    E.grad.resize(m);
-    E.r.assign(o, o + m);
-    for (int j = 0; j < m; ++j) E.grad[j] = (P->R[j] - o[j]) / (double)P->n;
-    E.certified = false;
-}
-
-// Certificate of E from the scaled-utility sums su (sum of u(t~)) and sdu
-// (sum of u(t) - u(t~)) of its own allocation:
-// gap = g - U(X~) = p^T (R - r) + sum_i [u(t_i) - u(t~_i)].
-void certify(const ra_problem* P, double su, double sdu, Eval& E)
-{
-    (void)su;
-    double pq = 0.0;
-    for (int j = 0; j < P->m; ++j) pq += E.p[j] * (P->R[j] - E.r[j]);
-    E.gap = pq + sdu;
-    E.U = E.g - E.gap;
-    const double den = std::max(std::fabs(E.g), std::fabs(E.U));
-    E.rel = E.gap / (den > 0 ? den : 1.0);
-    E.certified = true;
-}
-
 ra_status capture_graph(ra_problem* P)
 {
     ra_ctx* ctx = P->ctx;
@@ -261,13 +224,16 @@ ra_status capture_graph(ra_problem* P)
     return RA_OK;
 }
 
-// One pass at p: dual value, gradient and usage at p, and -- when prev is
-// given -- the certificate of prev, computed in the same pass over T.
-ra_status evaluate(ra_problem* P, const double* p, Eval* prev, bool use_graph, Eval& E)
+// One pass over T at p: dual value and usage at p (p_eval = p as rounded for
+// the kernel) and, when prev is given, the utility lost by scaling prev's
+// allocation (sdu), all from one launch of the dual kernel.
+ra_status run_pass(ra_problem* P, const std::vector<double>& p, const ra::Point* prev,
+                   bool use_graph, std::vector<double>& p_eval, double& g, std::vector<double>& r,
+                   double& sdu)
 {
     ra_ctx* ctx = P->ctx;
-    E.p.resize(P->m);
-    const double pR = fill_prices(P, p, &E.p);
+    p_eval.resize(P->m);
+    const double pR = fill_prices(P, p.data(), &p_eval);
     if (prev) fill_prev(P, prev->p, prev->r);
     if (use_graph && !ctx->timing) {
         ra_status st = capture_graph(P);
@@ -279,29 +245,15 @@ ra_status evaluate(ra_problem* P, const double* p, Eval* prev, bool use_graph, E
     }
     RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (collect_timing(ctx) != RA_OK) return RA_EDEVICE;
-    read_dual(P, pR, E);
-    if (!std::isfinite(E.g)) return fail(ctx, RA_ENUMERIC, "non-finite dual value");
-    for (double q : E.grad)
-        if (!std::isfinite(q)) return fail(ctx, RA_ENUMERIC, "non-finite gradient");
-    if (prev) {
-        certify(P, P->h_out[P->m + 1], P->h_out[P->m + 2], *prev);
-        if (!std::isfinite(prev->gap)) return fail(ctx, RA_ENUMERIC, "non-finite duality gap");
-    }
+    const double* o = P->h_out;
+    g = pR + o[P->m];
+    r.assign(o, o + P->m);
+    sdu = o[P->m + 2];
+    if (!std::isfinite(g)) return fail(ctx, RA_ENUMERIC, "non-finite dual value");
+    for (double v : r)
+        if (!std::isfinite(v)) return fail(ctx, RA_ENUMERIC, "non-finite usage");
+    if (prev && !std::isfinite(sdu)) return fail(ctx, RA_ENUMERIC, "non-finite duality gap");
     return RA_OK;
-}
-
-double dotv(const std::vector<double>& a, const std::vector<double>& b)
-{
-    double s = 0.0;
-    for (size_t j = 0; j < a.size(); ++j) s += a[j] * b[j];
-    return s;
-}
-
-double inf_norm(const std::vector<double>& a)
-{
-    double s = 0.0;
-    for (double v : a) s = std::max(s, std::fabs(v));
-    return s;
 }
 
 }  // namespace
@@ -496,24 +448,27 @@ ra_status ra_dual_eval(ra_ctx* ctx, const ra_problem* prob, const double* p, dou
     RA_HIP(ctx, hipSetDevice(ctx->dev));
     const bool lb = lower_bound != nullptr;
     if (lb && ensure_support_ws(P) != RA_OK) return RA_ENOMEM;
-    Eval E;
-    E.p.resize(P->m);
-    const double pR = fill_prices(P, p, &E.p);
+    std::vector<double> pe(P->m);
+    const double pR = fill_prices(P, p, &pe);
     ra_status st = enqueue_eval(P, lb, j_pair, x_pair, j1);
     if (st != RA_OK) return st;
     RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (collect_timing(ctx) != RA_OK) return RA_EDEVICE;
-    read_dual(P, pR, E);
-    if (!std::isfinite(E.g)) return fail(ctx, RA_ENUMERIC, "non-finite dual value");
+    const double* o = P->h_out;
+    const double gv = pR + o[P->m];
+    if (!std::isfinite(gv)) return fail(ctx, RA_ENUMERIC, "non-finite dual value");
     for (int j = 0; j < P->m; ++j)
-        if (!std::isfinite(P->h_out[j])) return fail(ctx, RA_ENUMERIC, "non-finite usage");
+        if (!std::isfinite(o[j])) return fail(ctx, RA_ENUMERIC, "non-finite usage");
     if (lb) {
-        certify(P, P->h_out[P->m + 1], P->h_out[P->m + 2], E);
-        if (!std::isfinite(E.U)) return fail(ctx, RA_ENUMERIC, "non-finite lower bound");
-        *lower_bound = E.U;
+        // U(X~) = g - [p^T (R - r) + sum_i (u(t_i) - u(t~_i))]
+        double pq = 0.0;
+        for (int j = 0; j < P->m; ++j) pq += pe[j] * (P->R[j] - o[j]);
+        const double U = gv - (pq + o[P->m + 2]);
+        if (!std::isfinite(U)) return fail(ctx, RA_ENUMERIC, "non-finite lower bound");
+        *lower_bound = U;
     }
-    *g = E.g;
-    for (int j = 0; j < P->m; ++j) grad[j] = P->R[j] - P->h_out[j];
+    *g = gv;
+    for (int j = 0; j < P->m; ++j) grad[j] = P->R[j] - o[j];
     return RA_OK;
 }
 
@@ -558,139 +513,31 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
     // the NULL stream cannot be captured
     const bool graph = o.use_graph && ctx->stream != nullptr;
 
-    // cur: current iterate; trial: line-search point; pend: the last point
-    // evaluated, whose certificate arrives with the next pass; best: the
-    // certified point with the smallest relative gap
-    Eval cur, trial, pend, best;
-    int evals = 0, iters = 0, fallbacks = 0, sg_steps = 0;
-    bool have_pend = false, done = false;
-    auto budget_left = [&]() { return o.max_evals == 0 || evals < o.max_evals; };
-
-    // One pass over T at x: evaluates x and certifies the pending point.
-    auto pass = [&](const std::vector<double>& x, Eval& out) -> ra_status {
-        ra_status s = evaluate(P, x.data(), have_pend ? &pend : nullptr, graph, out);
-        if (s != RA_OK) return s;
-        if (have_pend) {
-            if (o.verbose)
-                fprintf(stderr, "iteration %02d | utility=%.6f | dual_value=%.6f | gap=%.2e\n",
-                        evals - 1, pend.U / (double)P->n, pend.g / (double)P->n,
-                        pend.gap / (double)P->n);
-            if (!best.certified || pend.rel < best.rel) best = pend;
-            if (pend.rel <= o.tol_rel) done = true;
-        }
-        ++evals;
-        pend = out;
-        have_pend = true;
-        return RA_OK;
-    };
-
-    ra_status st = pass(p, cur);
-    if (st != RA_OK) return st;
-
-    // L-BFGS memory: ring of (s, y, 1/s^T y)
-    const int M = o.lbfgs_mem;
-    std::vector<std::vector<double>> S(M, std::vector<double>(m)), Y(M, std::vector<double>(m));
-    std::vector<double> rho(M), alpha(M), d(m), q(m), pn(m), step(m), yv(m);
-    int npairs = 0, head = 0;
-    bool out_of_budget = false;
-
-    for (; iters < o.max_iter && !done; ++iters) {
-        if (!budget_left()) break;
-        bool took = false;
-        if (o.method == 0) {
-            // two-loop recursion: q = H grad
-            q = cur.grad;
-            for (int h = 0; h < npairs; ++h) {
-                const int s = (head - 1 - h + M) % M;
-                alpha[h] = rho[s] * dotv(S[s], q);
-                for (int j = 0; j < m; ++j) q[j] -= alpha[h] * Y[s][j];
-            }
-            if (npairs > 0) {
-                const int s = (head - 1 + M) % M;
-                const double gam = dotv(S[s], Y[s]) / dotv(Y[s], Y[s]);
-                for (int j = 0; j < m; ++j) q[j] *= gam;
-            }
-            for (int h = npairs - 1; h >= 0; --h) {
-                const int s = (head - 1 - h + M) % M;
-                const double b = rho[s] * dotv(Y[s], q);
-                for (int j = 0; j < m; ++j) q[j] += S[s][j] * (alpha[h] - b);
-            }
-            // keep prices at zero that the direction would push negative
-            for (int j = 0; j < m; ++j) d[j] = (cur.p[j] <= 0.0 && q[j] > 0.0) ? 0.0 : -q[j];
-            if (dotv(d, cur.grad) >= 0.0) {
-                npairs = 0;
-                for (int j = 0; j < m; ++j)
-                    d[j] = (cur.p[j] <= 0.0 && cur.grad[j] > 0.0) ? 0.0 : -cur.grad[j];
-            }
-            const double dn = inf_norm(d);
-            if (dn == 0.0) break;
-            double lam = 1.0;
-            if (npairs == 0) {
-                const double pi = inf_norm(cur.p);
-                lam = 0.1 * (pi > 0.0 ? pi : 1.0) / dn;
-            }
-            for (int ls = 0; ls < 20; ++ls) {
-                if (!budget_left()) {
-                    out_of_budget = true;
-                    break;
-                }
-                for (int j = 0; j < m; ++j) pn[j] = std::max(cur.p[j] + lam * d[j], 0.0);
-                st = pass(pn, trial);
-                if (st != RA_OK) return st;
-                if (done) break;
-                for (int j = 0; j < m; ++j) step[j] = trial.p[j] - cur.p[j];
-                if (trial.f <= cur.f + 1e-4 * dotv(cur.grad, step)) {  // Armijo
-                    took = true;
-                    break;
-                }
-                lam *= 0.5;
-            }
-            if (done || out_of_budget) break;
-            if (took) {
-                for (int j = 0; j < m; ++j) yv[j] = trial.grad[j] - cur.grad[j];
-                const double sy = dotv(step, yv);
-                if (sy > 1e-12 * std::sqrt(dotv(step, step) * dotv(yv, yv))) {
-                    S[head] = step;
-                    Y[head] = yv;
-                    rho[head] = 1.0 / sy;
-                    head = (head + 1) % M;
-                    npairs = std::min(npairs + 1, M);
-                }
-            } else {
-                npairs = 0;
-            }
-        }
-        if (!took) {
-            // projected subgradient step p - a_k q with a_k = a0 / sqrt(k)
-            if (!budget_left()) break;
-            ++sg_steps;
-            ++fallbacks;
-            const double gi = inf_norm(cur.grad), pi = inf_norm(cur.p);
-            const double a0 = gi > 0.0 ? 0.1 * (pi > 0.0 ? pi : 1.0) / gi : 0.0;
-            const double ak = a0 / std::sqrt((double)sg_steps);
-            for (int j = 0; j < m; ++j) pn[j] = std::max(cur.p[j] - ak * cur.grad[j], 0.0);
-            st = pass(pn, trial);
-            if (st != RA_OK) return st;
-            if (done) break;
-        }
-        cur = trial;
-    }
-    // the last point evaluated still awaits its certificate
-    if (!done && have_pend && budget_left()) {
-        Eval tail;
-        st = pass(pend.p, tail);
+    ra::PriceLoop L(m, P->n, P->R.data(), o, p.data());
+    std::vector<double> pe, rr;
+    double gv = 0.0, sdu = 0.0;
+    while (!L.done()) {
+        const int nc = L.ncertified();
+        ra_status st = run_pass(P, L.next(), L.pending(), graph, pe, gv, rr, sdu);
         if (st != RA_OK) return st;
+        L.feed(pe, gv, rr.data(), sdu);
+        if (o.verbose && L.ncertified() > nc) {
+            const ra::Point& c = L.last_certified();
+            fprintf(stderr, "iteration %02d | utility=%.6f | dual_value=%.6f | gap=%.2e\n",
+                    L.ncertified() - 1, c.U / (double)P->n, c.g / (double)P->n,
+                    c.gap / (double)P->n);
+        }
     }
-    const bool conv = best.certified && best.rel <= o.tol_rel;
-    const Eval& ret = best.certified ? best : pend;
+    const ra::Point& ret = L.result();
+    const bool conv = L.converged();
     if (o.verbose)
         fprintf(stderr, "%s in %03d iterations, with residual %g\n",
-                conv ? "Converged" : "Stopped", iters, ret.gap / (double)P->n);
+                conv ? "Converged" : "Stopped", L.iters(), ret.gap / (double)P->n);
     for (int j = 0; j < m; ++j) p_inout[j] = ret.p[j];
     if (info) {
-        info->iters = iters;
-        info->dual_evals = evals;
-        info->fell_back = fallbacks;
+        info->iters = L.iters();
+        info->dual_evals = L.evals();
+        info->fell_back = L.fallbacks();
         info->converged = conv ? 1 : 0;
         info->g = ret.g;
         info->U_lb = ret.certified ? ret.U : NAN;
@@ -746,3 +593,389 @@ ra_status ra_get_kernel_timing(const ra_ctx* ctx, double* ms_total, int64_t* lau
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched price discovery.
+// ---------------------------------------------------------------------------
+namespace {
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct BatchWs {
+    int B = 0, Wmax = 0;
+    size_t off_items = 0, off_prices = 0, off_chunk = 0, off_segbase = 0, off_seg = 0,
+           off_header = 0, tab_bytes = 0;
+    char* dtab = nullptr;
+    char* htab = nullptr;
+    double* partial = nullptr;
+    double* dout = nullptr;
+    double* hout = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_grid = 0;
+    ~BatchWs()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipFree(dtab);
+        (void)hipFree(partial);
+        (void)hipFree(dout);
+        if (htab) (void)hipHostFree(htab);
+        if (hout) (void)hipHostFree(hout);
+    }
+    ra::BatchItem* items() { return reinterpret_cast<ra::BatchItem*>(htab + off_items); }
+    float* prices() { return reinterpret_cast<float*>(htab + off_prices); }
+    int* chunk() { return reinterpret_cast<int*>(htab + off_chunk); }
+    int* segbase() { return reinterpret_cast<int*>(htab + off_segbase); }
+    int* seg() { return reinterpret_cast<int*>(htab + off_seg); }
+    int* header() { return reinterpret_cast<int*>(htab + off_header); }
+};
+
+ra_status batch_alloc(ra_ctx* ctx, BatchWs& ws, int B, int Wmax)
+{
+    ws.B = B;
+    ws.Wmax = Wmax;
+    size_t o = 0;
+    ws.off_items = o;
+    o = align16(o + sizeof(ra::BatchItem) * (size_t)(B + 1));
+    ws.off_prices = o;
+    o = align16(o + sizeof(float) * 6 * ra::BATCH_MAX_M * (size_t)B);
+    ws.off_chunk = o;
+    o = align16(o + sizeof(int) * (size_t)(Wmax + 1));
+    ws.off_segbase = o;
+    o = align16(o + sizeof(int) * (size_t)(Wmax + 1));
+    ws.off_seg = o;
+    o = align16(o + sizeof(int) * 2 * (size_t)B);
+    ws.off_header = o;
+    o = align16(o + sizeof(int) * 4);
+    ws.tab_bytes = o;
+    RA_HIP(ctx, hipMalloc(&ws.dtab, ws.tab_bytes));
+    RA_HIP(ctx, hipHostMalloc((void**)&ws.htab, ws.tab_bytes, hipHostMallocDefault));
+    std::memset(ws.htab, 0, ws.tab_bytes);
+    RA_HIP(ctx, hipMalloc(&ws.partial,
+                          sizeof(double) * ra::BATCH_COLS * (size_t)(Wmax + B)));
+    RA_HIP(ctx, hipMalloc(&ws.dout, sizeof(double) * ra::BATCH_COLS * (size_t)B));
+    RA_HIP(ctx, hipHostMalloc((void**)&ws.hout, sizeof(double) * ra::BATCH_COLS * (size_t)B,
+                              hipHostMallocDefault));
+    return RA_OK;
+}
+
+// Fill the tables of one round for the active problems `act` (ascending) with
+// W waves: items, prices (next point and, if any, the point to certify),
+// byte-balanced per-wave tile chunks, partial slots.  Returns the tile count.
+int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
+                   const std::vector<ra::PriceLoop>& loops, const std::vector<int>& act, int W,
+                   std::vector<std::vector<double>>& p_eval)
+{
+    const int A = (int)act.size();
+    ra::BatchItem* it = ws.items();
+    float* pr = ws.prices();
+    std::vector<int64_t> tiles(A), cost(A);
+    int64_t tt = 0, C = 0;
+    for (int a = 0; a < A; ++a) {
+        const ra_problem* P = probs[act[a]];
+        const ra::PriceLoop& L = loops[act[a]];
+        tiles[a] = (P->n + 63) / 64;
+        cost[a] = 4 * P->m + 8;  // bytes per job
+        it[a].T = static_cast<const float*>(P->T);
+        it[a].prm = static_cast<const float2*>(P->prm);
+        it[a].n = P->n;
+        it[a].m = P->m;
+        it[a].tile0 = (int)tt;
+        it[a].eps = (float)P->eps;
+        const ra::Point* prev = L.pending();
+        it[a].has_prev = prev ? 1 : 0;
+        float* row = pr + (size_t)a * 6 * ra::BATCH_MAX_M;
+        const std::vector<double>& nx = L.next();
+        p_eval[a].resize(P->m);
+        for (int j = 0; j < P->m; ++j) {
+            const float pf = (float)nx[j];
+            p_eval[a][j] = pf;
+            row[j] = pf;
+            row[ra::BATCH_MAX_M + j] = pf > 0.f ? 1.0f / pf : INFINITY;
+            if (prev) {
+                const float qf = (float)prev->p[j];
+                row[2 * ra::BATCH_MAX_M + j] = qf;
+                row[3 * ra::BATCH_MAX_M + j] = qf > 0.f ? 1.0f / qf : INFINITY;
+                const bool over = prev->r[j] > P->R[j];
+                row[4 * ra::BATCH_MAX_M + j] = over ? (float)(P->R[j] / prev->r[j]) : 1.0f;
+                row[5 * ra::BATCH_MAX_M + j] =
+                    over ? (float)((prev->r[j] - P->R[j]) / prev->r[j]) : 0.0f;
+            }
+        }
+        tt += tiles[a];
+        C += tiles[a] * cost[a];
+    }
+    it[A].tile0 = (int)tt;
+    // wave w starts at the first tile whose cumulative cost reaches w C / W
+    int* ch = ws.chunk();
+    {
+        int a = 0;
+        int64_t cc = 0;  // cost before problem a
+        for (int w = 0; w <= W; ++w) {
+            const double target = (double)C * (double)w / (double)W;
+            while (a < A && (double)(cc + tiles[a] * cost[a]) <= target) {
+                cc += tiles[a] * cost[a];
+                ++a;
+            }
+            if (a >= A || w == W) {
+                ch[w] = (int)tt;
+            } else {
+                int64_t k = (int64_t)std::ceil((target - (double)cc) / (double)cost[a]);
+                k = std::min<int64_t>(std::max<int64_t>(k, 0), tiles[a]);
+                ch[w] = it[a].tile0 + (int)k;
+            }
+        }
+        for (int w = 1; w <= W; ++w) ch[w] = std::max(ch[w], ch[w - 1]);
+        ch[W] = (int)tt;
+    }
+    // partial slots: one per (wave, problem it touches), contiguous per problem
+    int* sb = ws.segbase();
+    int* sg = ws.seg();
+    for (int a = 0; a < A; ++a) sg[2 * a] = -1;
+    int slot = 0, a = 0;
+    for (int w = 0; w < W; ++w) {
+        sb[w] = slot;
+        if (ch[w] >= ch[w + 1]) continue;
+        while (it[a + 1].tile0 <= ch[w]) ++a;
+        int b = a;
+        while (it[b + 1].tile0 < ch[w + 1]) ++b;
+        for (int k = a; k <= b; ++k, ++slot) {
+            if (sg[2 * k] < 0) sg[2 * k] = slot;
+            sg[2 * k + 1] = slot;
+        }
+    }
+    sb[W] = slot;
+    ws.header()[0] = A;
+    return tt;
+}
+
+ra_status batch_enqueue(ra_ctx* ctx, BatchWs& ws, int grid)
+{
+    hipStream_t st = ctx->stream;
+    RA_HIP(ctx, hipMemcpyAsync(ws.dtab, ws.htab, ws.tab_bytes, hipMemcpyHostToDevice, st));
+    RA_HIP(ctx, ra::launch_batch(grid, ws.B, st,
+                                 reinterpret_cast<const ra::BatchItem*>(ws.dtab + ws.off_items),
+                                 reinterpret_cast<const float*>(ws.dtab + ws.off_prices),
+                                 reinterpret_cast<const int*>(ws.dtab + ws.off_chunk),
+                                 reinterpret_cast<const int*>(ws.dtab + ws.off_segbase),
+                                 reinterpret_cast<const int*>(ws.dtab + ws.off_seg),
+                                 reinterpret_cast<const int*>(ws.dtab + ws.off_header), ws.partial,
+                                 ws.dout));
+    RA_HIP(ctx, hipMemcpyAsync(ws.hout, ws.dout, sizeof(double) * ra::BATCH_COLS * (size_t)ws.B,
+                               hipMemcpyDeviceToHost, st));
+    return RA_OK;
+}
+
+ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
+{
+    if (use_graph && !ctx->timing) {
+        if (!ws.gexec || ws.graph_grid != grid) {
+            if (ws.gexec) (void)hipGraphExecDestroy(ws.gexec);
+            if (ws.graph) (void)hipGraphDestroy(ws.graph);
+            ws.gexec = nullptr;
+            ws.graph = nullptr;
+            RA_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+            ra_status s = batch_enqueue(ctx, ws, grid);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+            if (s != RA_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            if (e != hipSuccess)
+                return fail(ctx, RA_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&ws.gexec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(ctx, RA_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            }
+            ws.graph = g;
+            ws.graph_grid = grid;
+        }
+        RA_HIP(ctx, hipGraphLaunch(ws.gexec, ctx->stream));
+    } else {
+        ra_status s = batch_enqueue(ctx, ws, grid);
+        if (s != RA_OK) return s;
+    }
+    RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return RA_OK;
+}
+
+std::string batch_signature(const std::vector<ra_problem*>& probs)
+{
+    // number of problems, total MiB of T (rounded), and the m histogram
+    int64_t bytes = 0;
+    int hist[4] = {0, 0, 0, 0};
+    for (const ra_problem* P : probs) {
+        bytes += P->n * (int64_t)P->m * 4;
+        hist[P->m == 4 ? 0 : P->m == 8 ? 1 : P->m == 16 ? 2 : 3]++;
+    }
+    char buf[128];
+    snprintf(buf, sizeof(buf), "B%zu_MiB%lld_m%d.%d.%d.%d", probs.size(),
+             (long long)(bytes >> 20), hist[0], hist[1], hist[2], hist[3]);
+    return buf;
+}
+
+void tune_cache_load(ra_ctx* ctx)
+{
+    const char* path = std::getenv("RESALLOC_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[160];
+    int v = 0;
+    while (std::fscanf(f, "%159s %d", key, &v) == 2)
+        if (v > 0) ctx->batch_tuned.emplace(key, v);
+    std::fclose(f);
+}
+
+void tune_cache_store(const ra_ctx* ctx)
+{
+    const char* path = std::getenv("RESALLOC_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return;
+    for (const auto& kv : ctx->batch_tuned) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    std::fclose(f);
+}
+
+}  // namespace
+
+extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* probs,
+                                    const ra_solve_opts* opts, const double* tol_each,
+                                    double* p_inout, ra_solve_info* infos)
+{
+    if (!ctx || ctx->closed) return RA_EINVAL;
+    if (B < 1 || !probs || !p_inout) return fail(ctx, RA_EINVAL, "B >= 1, probs and p_inout are required");
+    ra_solve_opts o;
+    ra_solve_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.lbfgs_mem < 1 ||
+        o.lbfgs_mem > 64 || (o.method != 0 && o.method != 1) || (o.init != 0 && o.init != 1))
+        return fail(ctx, RA_EINVAL, "invalid solve options");
+    std::vector<ra_problem*> P(probs, probs + B);
+    std::vector<size_t> off(B + 1, 0);
+    for (int b = 0; b < B; ++b) {
+        if (!P[b] || P[b]->ctx != ctx)
+            return fail(ctx, RA_EINVAL, "problem %d is NULL or from another context", b);
+        const int m = P[b]->m;
+        if (P[b]->dt != 0 || !P[b]->vec_ok || !(m == 4 || m == 8 || m == 16 || m == 32))
+            return fail(ctx, RA_EUNSUPPORTED,
+                        "problem %d: the batched kernel takes FP32, 16-byte aligned T with m in "
+                        "{4, 8, 16, 32}", b);
+        if (P[b]->n > ((int64_t)1 << 36))
+            return fail(ctx, RA_EUNSUPPORTED, "problem %d too large for the batched kernel", b);
+        if (tol_each && !(tol_each[b] >= 0.0))
+            return fail(ctx, RA_EINVAL, "tol_each[%d] must be >= 0", b);
+        off[b + 1] = off[b] + m;
+    }
+    int64_t total_tiles = 0;
+    for (int b = 0; b < B; ++b) total_tiles += (P[b]->n + 63) / 64;
+    if (total_tiles >= ((int64_t)1 << 31))
+        return fail(ctx, RA_EUNSUPPORTED, "batch has too many tiles");
+    RA_HIP(ctx, hipSetDevice(ctx->dev));
+    const auto t0 = std::chrono::steady_clock::now();
+
+    std::vector<ra::PriceLoop> loops;
+    loops.reserve(B);
+    for (int b = 0; b < B; ++b) {
+        ra_solve_opts ob = o;
+        if (tol_each) ob.tol_rel = tol_each[b];
+        std::vector<double> p0(P[b]->m, 1.0);
+        if (o.init == 1)
+            for (int j = 0; j < P[b]->m; ++j) {
+                const double v = p_inout[off[b] + j];
+                if (!std::isfinite(v) || v < 0.0)
+                    return fail(ctx, RA_EINVAL, "p_inout of problem %d must be >= 0 and finite", b);
+                p0[j] = v;
+            }
+        loops.emplace_back(P[b]->m, P[b]->n, P[b]->R.data(), ob, p0.data());
+    }
+
+    const int occ = std::max(1, ra::batch_blocks_per_cu());
+    const int Wmax = ctx->cus * occ * 4;
+    BatchWs ws;
+    if (batch_alloc(ctx, ws, B, Wmax) != RA_OK) return RA_ENOMEM;
+    const bool graph = o.use_graph && ctx->stream != nullptr;
+
+    // grid: tuned per batch shape (timing one round per candidate)
+    if (ctx->batch_tuned.empty()) tune_cache_load(ctx);
+    const std::string sig = batch_signature(P);
+    int bpc = 0;
+    auto found = ctx->batch_tuned.find(sig);
+    if (found != ctx->batch_tuned.end()) bpc = std::min(found->second, occ);
+
+    std::vector<int> act;
+    std::vector<std::vector<double>> p_eval(B);
+    std::vector<double> r(ra::BATCH_MAX_M);
+    if (bpc == 0) {
+        act.resize(B);
+        for (int b = 0; b < B; ++b) act[b] = b;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        RA_HIP(ctx, hipEventCreate(&e0));
+        RA_HIP(ctx, hipEventCreate(&e1));
+        float best_ms = INFINITY;
+        for (int c = 1; c <= occ; ++c) {
+            const int grid = ctx->cus * c;
+            batch_fill(ws, P, loops, act, grid * 4, p_eval);
+            for (int rep = 0; rep < 2; ++rep) {  // first run warms up
+                RA_HIP(ctx, hipEventRecord(e0, ctx->stream));
+                ra_status s = batch_enqueue(ctx, ws, grid);
+                if (s != RA_OK) return s;
+                RA_HIP(ctx, hipEventRecord(e1, ctx->stream));
+                RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            }
+            float ms = 0.f;
+            RA_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                bpc = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->batch_tuned[sig] = bpc;
+        tune_cache_store(ctx);
+    }
+    const int grid = ctx->cus * bpc;
+
+    for (;;) {
+        act.clear();
+        for (int b = 0; b < B; ++b)
+            if (!loops[b].done()) act.push_back(b);
+        if (act.empty()) break;
+        batch_fill(ws, P, loops, act, grid * 4, p_eval);
+        ra_status s = batch_run(ctx, ws, grid, graph);
+        if (s != RA_OK) return s;
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int b = act[a];
+            const ra_problem* Pb = P[b];
+            const double* row = ws.hout + a * ra::BATCH_COLS;
+            double pR = 0.0;
+            for (int j = 0; j < Pb->m; ++j) pR += p_eval[a][j] * Pb->R[j];
+            const double gv = pR + row[ra::BATCH_MAX_M];
+            if (!std::isfinite(gv)) return fail(ctx, RA_ENUMERIC, "problem %d: non-finite dual value", b);
+            for (int j = 0; j < Pb->m; ++j) r[j] = row[j];
+            loops[b].feed(p_eval[a], gv, r.data(), row[ra::BATCH_MAX_M + 2]);
+        }
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool all = true;
+    for (int b = 0; b < B; ++b) {
+        const ra::Point& ret = loops[b].result();
+        for (int j = 0; j < P[b]->m; ++j) p_inout[off[b] + j] = ret.p[j];
+        all = all && loops[b].converged();
+        if (infos) {
+            infos[b].iters = loops[b].iters();
+            infos[b].dual_evals = loops[b].evals();
+            infos[b].fell_back = loops[b].fallbacks();
+            infos[b].converged = loops[b].converged() ? 1 : 0;
+            infos[b].g = ret.g;
+            infos[b].U_lb = ret.certified ? ret.U : NAN;
+            infos[b].rel_gap = ret.certified ? ret.rel : INFINITY;
+            infos[b].seconds = secs;
+        }
+    }
+    return all ? RA_OK : RA_ENOTCONV;
+}

@@ -1,0 +1,114 @@
+"""GPU tests of the batched solver (C ABI ra_batch_solve)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import round_prices, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_2104_00282_amd as ra
+    c = ra.Context(0)
+    yield c
+    c.close()
+
+
+def _batch_instances():
+    """Uneven sizes (including n < 64 and ragged tiles) and every m class."""
+    out = []
+    rng = np.random.default_rng(77)
+    for k, (n, m) in enumerate([(37, 4), (64, 8), (1000, 16), (5003, 32), (130, 4), (20000, 8),
+                                (777, 32), (4096, 16), (65, 32), (12345, 4), (3000, 8),
+                                (50000, 16)]):
+        I = synth.random_small(n, m, seed=1000 + k, dtype=np.float32)
+        I.T *= (0.2 + 4.8 * rng.random(m)).astype(np.float32)[None, :]
+        out.append(I)
+    return out
+
+
+def _problems(ctx, torch, insts):
+    import paper_2104_00282_amd as ra
+    probs = []
+    for I in insts:
+        T, w, c, kind = to_device(I, torch)
+        probs.append(ra.Problem(ctx, T, w, c, kind, I.R, I.eps))
+    return probs
+
+
+def test_batched_pass_matches_oracle(ctx, torch):
+    """Two passes: the first evaluates p0, the second certifies it; the
+    returned g(p0) and U(X~(p0)) match the oracle for every problem."""
+    import paper_2104_00282_amd as ra
+    insts = _batch_instances()
+    probs = _problems(ctx, torch, insts)
+    rng = np.random.default_rng(5)
+    p0 = [round_prices(0.2 + rng.random(I.m) * 2, np.float32) for I in insts]
+    ps, infos, st = ra.batch_solve(probs, p0=p0, tol_rel=0.0, max_evals=2)
+    for I, p, pi, inf in zip(insts, p0, ps, infos):
+        assert np.array_equal(pi, p)
+        d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+        U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, d.r, d.jobs)
+        scale = abs(float(p @ I.R)) + np.abs(d.jobs["v"]).sum()
+        assert abs(inf["g"] - d.g) <= 1e-5 * scale, (I.n, I.m, inf["g"], d.g)
+        assert abs(inf["U_lb"] - U) <= 1e-5 * (scale + abs(U)), (I.n, I.m, inf["U_lb"], U)
+        assert inf["dual_evals"] == 2
+    for pr in probs:
+        pr.close()
+
+
+def test_batched_solve_matches_single(ctx, torch):
+    """Each problem's batched solve reaches the same quality as its own solve,
+    and the certificate holds under the oracle."""
+    import paper_2104_00282_amd as ra
+    insts = _batch_instances()
+    probs = _problems(ctx, torch, insts)
+    ps, infos, st = ra.batch_solve(probs, tol_rel=1e-5, max_iter=150)
+    for I, pr, p, inf in zip(insts, probs, ps, infos):
+        ps1, i1, _ = pr.solve(tol_rel=1e-5, max_iter=150)
+        # summation order differs between the batched and the single kernel,
+        # so the two trajectories are close but not identical
+        assert inf["rel_gap"] <= max(3 * i1["rel_gap"], 1e-5) + 1e-6
+        d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+        U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, d.r, d.jobs)
+        scale = abs(d.g) + abs(U)
+        assert abs(inf["g"] - d.g) <= 1e-5 * scale
+        assert abs(inf["U_lb"] - U) <= 1e-5 * scale
+    for pr in probs:
+        pr.close()
+
+
+def test_batched_graph_equals_direct(ctx, torch):
+    import paper_2104_00282_amd as ra
+    insts = _batch_instances()[:6]
+    probs = _problems(ctx, torch, insts)
+    pa, ia, _ = ra.batch_solve(probs, tol_rel=1e-6, max_iter=30, use_graph=True)
+    pb, ib, _ = ra.batch_solve(probs, tol_rel=1e-6, max_iter=30, use_graph=False)
+    for x, y, u, v in zip(pa, pb, ia, ib):
+        assert np.array_equal(x, y) and u["g"] == v["g"]
+    for pr in probs:
+        pr.close()
+
+
+def test_batched_rejects_unsupported(ctx, torch):
+    import paper_2104_00282_amd as ra
+    probs = _problems(ctx, torch, [synth.random_small(100, 64, seed=1, dtype=np.float32),
+                                   synth.random_small(100, 4, seed=2, dtype=np.float32)])
+    with pytest.raises(ra.RAError) as e:
+        ra.batch_solve(probs)
+    assert e.value.status == ra.RA_EUNSUPPORTED
+    p64 = _problems(ctx, torch, [synth.random_small(100, 4, seed=3, dtype=np.float64)])
+    with pytest.raises(ra.RAError):
+        ra.batch_solve(p64)
+    for pr in probs + p64:
+        pr.close()
