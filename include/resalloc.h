@@ -132,6 +132,8 @@ typedef struct {
     int32_t use_graph;       /* 1 = replay one captured HIP graph per evaluation    */
     int32_t verbose;         /* 1 = one line per iteration on stderr                */
     int32_t max_evals;       /* > 0: stop after at most this many passes over T      */
+    int32_t stall_evals;     /* > 0: stop when the best certified relative gap has
+                                not improved by 0.1% within this many passes       */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
@@ -147,7 +149,8 @@ typedef struct {
 } ra_solve_info;
 
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
- * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit). */
+ * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
+ * stall_evals = 0 (off). */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
 /* Price discovery (§5, Algorithm 2). Every pass over T evaluates g and its

@@ -140,10 +140,11 @@ class Problem:
         return out
 
     def solve(self, p0=None, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, method=0, use_graph=True,
-              verbose=False, max_evals=0):
+              verbose=False, max_evals=0, stall_evals=0):
         """Price discovery; returns (p, info dict, status)."""
         o = ra_solve_opts_default()
         o.max_evals = max_evals
+        o.stall_evals = stall_evals
         o.tol_rel = tol_rel
         o.max_iter = max_iter
         o.lbfgs_mem = lbfgs_mem
@@ -168,7 +169,7 @@ class Problem:
 
 
 def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lbfgs_mem=10,
-                method=0, use_graph=True, max_evals=0):
+                method=0, use_graph=True, max_evals=0, stall_evals=0):
     """Solve several Problems of one Context together (ra_batch_solve).
     Returns (list of price arrays, list of info dicts, status)."""
     if not problems:
@@ -182,6 +183,7 @@ def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lb
     o.method = method
     o.use_graph = 1 if use_graph else 0
     o.max_evals = max_evals
+    o.stall_evals = stall_evals
     ms = [pr.m for pr in problems]
     offs = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
     p = np.ones(int(offs[-1]))

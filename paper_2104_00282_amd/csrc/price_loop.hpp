@@ -15,7 +15,9 @@
 // if s^T y > 1e-12 |s| |y|.  When the line search fails, one projected
 // subgradient step p+ = max(p - a_k q, 0), a_k = a0 / sqrt(k),
 // a0 = 0.1 |p|_inf / |q|_inf, is taken instead (the fallback of §5); method 1
-// uses only that step.
+// uses only that step.  With stall_evals > 0 the loop also ends when the best
+// certified relative gap has not improved by 0.1 % within that many passes
+// (the column-scaling recovery has a floor, see ra_solve).
 #pragma once
 
 #include <algorithm>
@@ -58,8 +60,16 @@ public:
             certify(pend_, sdu_prev);
             last_cert_ = pend_;
             ++ncert_;
-            if (!best_.certified || pend_.rel < best_.rel) best_ = pend_;
+            if (!best_.certified || pend_.rel < best_.rel) {
+                if (!best_.certified || pend_.rel < 0.999 * best_.rel) improved_at_ = evals_;
+                best_ = pend_;
+            }
             if (pend_.rel <= o_.tol_rel) {
+                state_ = DONE;
+                return;
+            }
+            if (o_.stall_evals > 0 && evals_ - improved_at_ >= o_.stall_evals) {
+                stalled_ = true;  // the best gap stopped improving: end here
                 state_ = DONE;
                 return;
             }
@@ -128,6 +138,7 @@ public:
     int iters() const { return iters_; }
     int evals() const { return evals_; }
     int fallbacks() const { return fallbacks_; }
+    bool stalled() const { return stalled_; }
     // The point certified by the last feed (valid when ncertified() grew).
     const Point& last_certified() const { return last_cert_; }
     int ncertified() const { return ncert_; }
@@ -258,6 +269,8 @@ private:
     int npairs_ = 0, head_ = 0, ls_ = 0;
     double lam_ = 1.0;
     int evals_ = 0, iters_ = 0, fallbacks_ = 0, sg_steps_ = 0;
+    int improved_at_ = 0;
+    bool stalled_ = false;
 };
 
 }  // namespace ra

@@ -483,6 +483,7 @@ void ra_solve_opts_default(ra_solve_opts* o)
     o->use_graph = 1;
     o->verbose = 0;
     o->max_evals = 0;
+    o->stall_evals = 0;
 }
 
 ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opts,
@@ -494,8 +495,8 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
     ra_solve_opts o;
     ra_solve_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.lbfgs_mem < 1 ||
-        o.lbfgs_mem > 64 ||
+    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.stall_evals < 0 ||
+        o.lbfgs_mem < 1 || o.lbfgs_mem > 64 ||
         (o.method != 0 && o.method != 1) || (o.init != 0 && o.init != 1))
         return fail(ctx, RA_EINVAL, "invalid solve options");
     ra_problem* P = const_cast<ra_problem*>(prob);
@@ -851,8 +852,9 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     ra_solve_opts o;
     ra_solve_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.lbfgs_mem < 1 ||
-        o.lbfgs_mem > 64 || (o.method != 0 && o.method != 1) || (o.init != 0 && o.init != 1))
+    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.stall_evals < 0 ||
+        o.lbfgs_mem < 1 || o.lbfgs_mem > 64 || (o.method != 0 && o.method != 1) ||
+        (o.init != 0 && o.init != 1))
         return fail(ctx, RA_EINVAL, "invalid solve options");
     std::vector<ra_problem*> P(probs, probs + B);
     std::vector<size_t> off(B + 1, 0);
