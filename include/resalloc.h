@@ -59,6 +59,7 @@ typedef enum { RA_UTIL_LOG = 0, RA_UTIL_CAPLIN = 1 } ra_util_kind;
 
 typedef struct ra_ctx ra_ctx;         /* device, stream, scratch, pinned staging   */
 typedef struct ra_problem ra_problem; /* borrowed T + packed per-job utilities      */
+typedef struct ra_mlp ra_mlp;         /* warm-start network and its training state */
 
 /* Largest number of resources a problem may have. */
 #define RA_MAX_RESOURCES 256
@@ -146,6 +147,8 @@ typedef struct {
     double U_lb;             /* U(X~) at the returned prices (lower bound)           */
     double rel_gap;          /* (g - U_lb) / max(|g|, |U_lb|)                         */
     double seconds;          /* wall time of the call                                */
+    int32_t restarted;       /* 1 if a learned warm start was abandoned for p = 1    */
+    int32_t warm_evals;      /* passes spent on an abandoned warm start              */
 } ra_solve_info;
 
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
@@ -194,6 +197,65 @@ ra_status ra_get_allocation(ra_ctx *ctx, const ra_problem *prob, const double *p
 ra_status ra_batch_solve(ra_ctx *ctx, int32_t B, ra_problem *const *probs,
                          const ra_solve_opts *opts, const double *tol_each, double *p_inout,
                          ra_solve_info *infos);
+
+/* ---- Learned warm start (not in the paper; the paper's own starting point
+ * is p = 1 or a data-dependent heuristic, §5 "Initialization"). ----------
+ * A multilayer perceptron maps per-problem features to log-prices:
+ *   in_dim -> hidden (ReLU) -> hidden (ReLU) -> out_dim, FP32,
+ * inputs standardised and outputs de-standardised with stored means and
+ * standard deviations.  Parameters are one flat FP32 array in the order
+ * W1 (hidden x in_dim, row-major), b1, W2 (hidden x hidden), b2,
+ * W3 (out_dim x hidden), b3.  Training minimises the mean squared error of
+ * the standardised outputs with Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+
+/* Feature vector of a problem (FP32 problems with m <= 64), 8 m + 16 floats
+ * written to feat (device): for resource j, at 8 j .. 8 j + 7: the 10/50/90 %
+ * nearest-rank quantiles of column j of T over the log jobs, the same over
+ * the capped-linear jobs (0 where a kind has no job), R_j / n, and the log of
+ * the column mean; then 8-bin histograms of w on [0.5, 2] (bins of width
+ * 0.1875, values outside clamped to the end bins) for the log jobs and for
+ * the capped-linear jobs, as fractions of the sample.  All statistics are
+ * taken over the rows floor(k n / S), k < S, S = min(n, 8192). */
+ra_status ra_features(ra_ctx *ctx, const ra_problem *prob, float *feat);
+
+/* Create a network (weights He-normal from `seed`, zero biases, identity
+ * standardisation). Errors: RA_EINVAL for non-positive sizes. */
+ra_status ra_mlp_create(ra_ctx *ctx, int32_t in_dim, int32_t hidden, int32_t out_dim,
+                        uint64_t seed, ra_mlp **out);
+ra_status ra_mlp_destroy(ra_mlp *mlp);
+/* Number of parameters (host output). */
+ra_status ra_mlp_num_params(const ra_mlp *mlp, int64_t *count);
+/* Copy the flat parameter array to / from host memory (num_params floats). */
+ra_status ra_mlp_get_params(ra_mlp *mlp, float *host);
+ra_status ra_mlp_set_params(ra_mlp *mlp, const float *host);
+/* Standardisation (host arrays): x_mean, x_std (in_dim), y_mean, y_std (out_dim);
+ * standard deviations must be > 0. */
+ra_status ra_mlp_set_normalization(ra_mlp *mlp, const float *x_mean, const float *x_std,
+                                   const float *y_mean, const float *y_std);
+/* Forward pass for `batch` feature rows X (device, batch x in_dim) into Y
+ * (device, batch x out_dim, de-standardised log-prices). */
+ra_status ra_mlp_forward(ra_ctx *ctx, ra_mlp *mlp, int32_t batch, const float *X, float *Y);
+/* Loss and gradients at targets Ty (device, batch x out_dim, raw log-prices)
+ * without changing the parameters; grad_host (num_params floats) may be NULL. */
+ra_status ra_mlp_gradients(ra_ctx *ctx, ra_mlp *mlp, int32_t batch, const float *X,
+                           const float *Ty, float *grad_host, double *loss);
+/* One Adam step of learning rate lr on one minibatch; loss before the step. */
+ra_status ra_mlp_train_step(ra_ctx *ctx, ra_mlp *mlp, int32_t batch, const float *X,
+                            const float *Ty, float lr, double *loss);
+/* Save / load the network (dimensions, standardisation, parameters) to a file. */
+ra_status ra_mlp_save(const ra_mlp *mlp, const char *path);
+ra_status ra_mlp_load(ra_ctx *ctx, const char *path, ra_mlp **out);
+
+/* Price discovery from a learned starting point: features, network forward,
+ * p0 = exp(predicted log-prices), then the loop of ra_solve.  If after
+ * `fallback_window` evaluations the certified relative gap has not fallen
+ * below that of the starting point (or any value is non-finite), the warm
+ * run is abandoned and the solve restarts from p = 1 (info->restarted = 1,
+ * info->warm_evals = passes spent before the restart, included in
+ * dual_evals and seconds).  The network's out_dim must equal the problem's m. */
+ra_status ra_solve_learned(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp,
+                           const ra_solve_opts *opts, int32_t fallback_window, double *p_out,
+                           ra_solve_info *info);
 
 /* Kernel timing on the context's stream (for benchmarks and profiling).
  * enable = 1 brackets every launch of the dual kernel with a pair of HIP

@@ -25,7 +25,7 @@ __all__ = [
     "Context", "Problem", "RAError", "ra_create", "ra_destroy", "ra_status_string",
     "ra_last_error", "ra_problem_create", "ra_problem_destroy", "ra_dual_eval",
     "ra_solve_opts_default", "ra_solve", "ra_get_allocation", "ra_solve_opts", "ra_solve_info",
-    "ra_set_kernel_timing", "ra_get_kernel_timing", "ra_batch_solve", "batch_solve",
+    "ra_set_kernel_timing", "ra_get_kernel_timing", "ra_batch_solve", "batch_solve", "MLP",
 ]
 
 
@@ -38,7 +38,7 @@ _LIVE = weakref.WeakSet()
 def _close_all():
     objs = list(_LIVE)
     for o in objs:
-        if isinstance(o, Problem):
+        if not isinstance(o, Context):
             o.close()
     for o in objs:
         o.close()
@@ -159,6 +159,31 @@ class Problem:
         st = ra_solve(self.ctx.handle, self.handle, o, _hbuf(p), info)
         return p, {f: getattr(info, f) for f, _ in ra_solve_info._fields_}, st
 
+    def features(self):
+        """Warm-start feature vector (8 m + 16 floats, device tensor)."""
+        import torch
+        f = torch.empty(8 * self.m + 16, dtype=torch.float32, device=self.T.device)
+        _capi.check(self.ctx.handle, _capi.lib().ra_features(self.ctx.handle, self.handle, _dptr(f)))
+        return f
+
+    def solve_learned(self, mlp, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, use_graph=True,
+                      max_evals=0, stall_evals=0, fallback_window=3):
+        """Price discovery from the network's predicted prices (ra_solve_learned)."""
+        o = ra_solve_opts_default()
+        o.tol_rel = tol_rel
+        o.max_iter = max_iter
+        o.lbfgs_mem = lbfgs_mem
+        o.use_graph = 1 if use_graph else 0
+        o.max_evals = max_evals
+        o.stall_evals = stall_evals
+        p = np.zeros(self.m)
+        info = ra_solve_info()
+        st = _capi.lib().ra_solve_learned(self.ctx.handle, self.handle, mlp.handle,
+                                         ctypes.byref(o), fallback_window, _hbuf(p),
+                                         ctypes.byref(info))
+        _capi.check(self.ctx.handle, st, (RA_OK, RA_ENOTCONV))
+        return p, {f: getattr(info, f) for f, _ in ra_solve_info._fields_}, st
+
     def allocation(self, p):
         """Dense feasible allocation X~ (n, m) at prices p."""
         import torch
@@ -201,3 +226,86 @@ def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lb
     out_p = [p[offs[b]:offs[b + 1]].copy() for b in range(B)]
     out_i = [{f: getattr(infos[b], f) for f, _ in ra_solve_info._fields_} for b in range(B)]
     return out_p, out_i, st
+
+
+class MLP:
+    """Warm-start network (ra_mlp_*): in_dim -> hidden -> hidden -> out_dim."""
+
+    def __init__(self, ctx, in_dim, hidden, out_dim, seed=0, handle=None):
+        self.ctx = ctx
+        self.in_dim, self.hidden, self.out_dim = in_dim, hidden, out_dim
+        if handle is None:
+            h = ctypes.c_void_p()
+            _capi.check(ctx.handle, _capi.lib().ra_mlp_create(ctx.handle, in_dim, hidden, out_dim,
+                                                             seed, ctypes.byref(h)))
+            handle = h
+        self.handle = handle
+        _LIVE.add(self)
+
+    @classmethod
+    def load(cls, ctx, path):
+        h = ctypes.c_void_p()
+        _capi.check(ctx.handle, _capi.lib().ra_mlp_load(ctx.handle, path.encode(), ctypes.byref(h)))
+        import struct
+        with open(path, "rb") as f:
+            f.read(8)
+            D, H, O = struct.unpack("<3i", f.read(12))
+        return cls(ctx, D, H, O, handle=h)
+
+    def save(self, path):
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_save(self.handle, path.encode()))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _capi.lib().ra_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self):
+        k = ctypes.c_int64()
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_num_params(self.handle, ctypes.byref(k)))
+        return k.value
+
+    def get_params(self):
+        a = np.empty(self.num_params(), dtype=np.float32)
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_get_params(self.handle, _hbuf(a)))
+        return a
+
+    def set_params(self, a):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+        assert a.size == self.num_params()
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_set_params(self.handle, _hbuf(a)))
+
+    def set_normalization(self, x_mean, x_std, y_mean, y_std):
+        arrs = [np.ascontiguousarray(np.asarray(v, dtype=np.float32))
+                for v in (x_mean, x_std, y_mean, y_std)]
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_set_normalization(
+            self.handle, *[_hbuf(a) for a in arrs]))
+
+    def forward(self, X):
+        import torch
+        X = X.to(torch.float32).contiguous()
+        Y = torch.empty((X.shape[0], self.out_dim), dtype=torch.float32, device=X.device)
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_forward(self.ctx.handle, self.handle,
+                                                               X.shape[0], _dptr(X), _dptr(Y)))
+        return Y
+
+    def gradients(self, X, Ty):
+        g = np.empty(self.num_params(), dtype=np.float32)
+        loss = ctypes.c_double()
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_gradients(
+            self.ctx.handle, self.handle, X.shape[0], _dptr(X.contiguous()),
+            _dptr(Ty.contiguous()), _hbuf(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, X, Ty, lr):
+        loss = ctypes.c_double()
+        _capi.check(self.ctx.handle, _capi.lib().ra_mlp_train_step(
+            self.ctx.handle, self.handle, X.shape[0], _dptr(X.contiguous()),
+            _dptr(Ty.contiguous()), lr, ctypes.byref(loss)))
+        return loss.value

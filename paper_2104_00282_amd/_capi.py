@@ -41,7 +41,8 @@ class ra_solve_opts(ctypes.Structure):
 
 class ra_solve_info(ctypes.Structure):
     _fields_ = [("iters", _i32), ("dual_evals", _i32), ("fell_back", _i32), ("converged", _i32),
-                ("g", _d), ("U_lb", _d), ("rel_gap", _d), ("seconds", _d)]
+                ("g", _d), ("U_lb", _d), ("rel_gap", _d), ("seconds", _d),
+                ("restarted", _i32), ("warm_evals", _i32)]
 
 
 # name -> (restype, argtypes)
@@ -60,6 +61,20 @@ PROTOTYPES = {
     "ra_get_allocation": (_st, [_vp, _vp, _vp, _vp]),
     "ra_batch_solve": (_st, [_vp, _i32, _vp, ctypes.POINTER(ra_solve_opts), _vp, _vp,
                              _vp]),
+    "ra_features": (_st, [_vp, _vp, _vp]),
+    "ra_mlp_create": (_st, [_vp, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    "ra_mlp_destroy": (_st, [_vp]),
+    "ra_mlp_num_params": (_st, [_vp, ctypes.POINTER(_i64)]),
+    "ra_mlp_get_params": (_st, [_vp, _vp]),
+    "ra_mlp_set_params": (_st, [_vp, _vp]),
+    "ra_mlp_set_normalization": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "ra_mlp_forward": (_st, [_vp, _vp, _i32, _vp, _vp]),
+    "ra_mlp_gradients": (_st, [_vp, _vp, _i32, _vp, _vp, _vp, ctypes.POINTER(_d)]),
+    "ra_mlp_train_step": (_st, [_vp, _vp, _i32, _vp, _vp, ctypes.c_float, ctypes.POINTER(_d)]),
+    "ra_mlp_save": (_st, [_vp, ctypes.c_char_p]),
+    "ra_mlp_load": (_st, [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)]),
+    "ra_solve_learned": (_st, [_vp, _vp, _vp, ctypes.POINTER(ra_solve_opts), _i32, _vp,
+                               ctypes.POINTER(ra_solve_info)]),
     "ra_set_kernel_timing": (_st, [_vp, _int]),
     "ra_get_kernel_timing": (_st, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
 }
@@ -175,4 +190,11 @@ def ra_batch_solve(ctx, B, probs, opts, tol_each, p_inout, infos):
                               tol_each, p_inout, infos)
     if st not in (RA_OK, RA_ENOTCONV):
         raise RAError(st, ra_last_error(ctx))
+    return st
+
+
+def check(ctx, st, allow=(RA_OK,)):
+    """Raise RAError unless st is in allow."""
+    if st not in allow:
+        raise RAError(st, ra_last_error(ctx) if ctx else "")
     return st

@@ -1,0 +1,87 @@
+// Internal definitions shared by the host sources of libresalloc.so.
+// Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "resalloc.h"
+
+struct ra_ctx {
+    int dev = 0;
+    int cus = 1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int live_problems = 0;  // problems created on this context and not destroyed
+    bool closed = false;    // ra_destroy called; freed when the last problem goes
+    bool timing = false;    // bracket dual-kernel launches with events
+    bool timed_pending = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    std::map<std::string, int> batch_tuned;  // batch shape -> blocks per CU
+};
+
+struct ra_problem {
+    ra_ctx* ctx = nullptr;
+    int64_t n = 0;
+    int m = 0;
+    int dt = 0;  // 0 = FP32, 1 = FP64
+    const void* T = nullptr;
+    bool vec_ok = false;
+    void* prm = nullptr;
+    std::vector<double> R;
+    double* Rdev = nullptr;
+    double eps = 0.0;
+    int grid = 1;
+    int lgrid = 1;
+    double* partial = nullptr;
+    double* partial2 = nullptr;
+    double* dout = nullptr;     // r[0..m), sum v, sum u(t~), sum u(t) - u(t~)
+    void* pblock = nullptr;
+    void* h_pblock = nullptr;
+    double* h_out = nullptr;
+    int16_t* jpair_ws = nullptr;
+    void* tpair_ws = nullptr;
+    void* xpair_ws = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+namespace ra {
+
+// Record a failure on ctx (printf-style detail) and return st.
+inline ra_status fail(ra_ctx* ctx, ra_status st, const char* fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof(buf), fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+#define RA_HIP(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::ra::fail((ctx), e_ == hipErrorOutOfMemory ? RA_ENOMEM : RA_EDEVICE, "%s: %s", \
+                        #call, hipGetErrorString(e_));                                      \
+    } while (0)
+
+// Learned warm start (mlp.hip)
+ra_status features_into(ra_problem* P, float* feat);
+ra_status predict_prices(ra_mlp* N, ra_problem* P, std::vector<double>& p0);
+int mlp_out_dim(const ra_mlp* N);
+int mlp_in_dim(const ra_mlp* N);
+
+}  // namespace ra

@@ -12,6 +12,7 @@
 // scaling) and its reduction, copy results out.  The price update (step 3)
 // is a projected L-BFGS on the host over m doubles.
 #include "price_loop.hpp"
+#include "ra_internal.hpp"
 #include "ra_kernels.h"
 #include "resalloc.h"
 
@@ -28,70 +29,9 @@
 #include <string>
 #include <vector>
 
-struct ra_ctx {
-    int dev = 0;
-    int cus = 1;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    std::string err;
-    int live_problems = 0;  // problems created on this context and not destroyed
-    bool closed = false;    // ra_destroy called; freed when the last problem goes
-    bool timing = false;    // bracket dual-kernel launches with events
-    bool timed_pending = false;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
-    std::map<std::string, int> batch_tuned;  // batch shape -> blocks per CU
-};
-
-struct ra_problem {
-    ra_ctx* ctx = nullptr;
-    int64_t n = 0;
-    int m = 0;
-    int dt = 0;  // 0 = FP32, 1 = FP64
-    const void* T = nullptr;
-    bool vec_ok = false;
-    void* prm = nullptr;
-    std::vector<double> R;
-    double* Rdev = nullptr;
-    double eps = 0.0;
-    int grid = 1;
-    int lgrid = 1;
-    double* partial = nullptr;
-    double* partial2 = nullptr;
-    double* dout = nullptr;     // r[0..m), sum v, sum u(t~), sum u(t) - u(t~)
-    void* pblock = nullptr;
-    void* h_pblock = nullptr;
-    double* h_out = nullptr;
-    int16_t* jpair_ws = nullptr;
-    void* tpair_ws = nullptr;
-    void* xpair_ws = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-};
-
 namespace {
 
-ra_status fail(ra_ctx* ctx, ra_status st, const char* fmt, ...)
-{
-    if (ctx) {
-        char buf[512];
-        va_list ap;
-        va_start(ap, fmt);
-        vsnprintf(buf, sizeof(buf), fmt, ap);
-        va_end(ap);
-        ctx->err = buf;
-    }
-    return st;
-}
-
-#define RA_HIP(ctx, call)                                                                   \
-    do {                                                                                    \
-        hipError_t e_ = (call);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail((ctx), e_ == hipErrorOutOfMemory ? RA_ENOMEM : RA_EDEVICE, "%s: %s", \
-                        #call, hipGetErrorString(e_));                                      \
-    } while (0)
+using ra::fail;
 
 size_t elt(int dt) { return dt == 0 ? 4 : 8; }
 size_t price_block_bytes(int dt)
@@ -545,6 +485,103 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
         info->rel_gap = ret.certified ? ret.rel : INFINITY;
         info->seconds =
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->restarted = 0;
+        info->warm_evals = 0;
+    }
+    return conv ? RA_OK : RA_ENOTCONV;
+}
+
+// Learned warm start with a cold restart when the warm run does not improve
+// its starting certificate within `window` certified points.
+ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
+                           const ra_solve_opts* opts, int32_t window, double* p_out,
+                           ra_solve_info* info)
+{
+    if (!ctx || ctx->closed) return RA_EINVAL;
+    if (!prob || prob->ctx != ctx) return fail(ctx, RA_EINVAL, "problem is NULL or from another context");
+    if (!mlp || !p_out) return fail(ctx, RA_EINVAL, "network and p_out are required");
+    ra_problem* P = const_cast<ra_problem*>(prob);
+    const int m = P->m;
+    if (P->dt != 0 || m > 64)
+        return fail(ctx, RA_EUNSUPPORTED, "learned warm start needs an FP32 problem with m <= 64");
+    if (ra::mlp_out_dim(mlp) != m || ra::mlp_in_dim(mlp) != 8 * m + 16)
+        return fail(ctx, RA_EINVAL, "network dimensions do not match the problem (in 8m+16, out m)");
+    if (window < 1) return fail(ctx, RA_EINVAL, "fallback_window must be >= 1");
+    ra_solve_opts o;
+    ra_solve_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.stall_evals < 0 ||
+        o.lbfgs_mem < 1 || o.lbfgs_mem > 64 || (o.method != 0 && o.method != 1))
+        return fail(ctx, RA_EINVAL, "invalid solve options");
+    RA_HIP(ctx, hipSetDevice(ctx->dev));
+    const auto t0 = std::chrono::steady_clock::now();
+    const bool graph = o.use_graph && ctx->stream != nullptr;
+
+    std::vector<double> p0;
+    ra_status st = ra::predict_prices(mlp, P, p0);
+    if (st != RA_OK) return st;
+    bool warm_ok = true;
+    for (double v : p0) warm_ok = warm_ok && std::isfinite(v) && v >= 0.0;
+    int warm_evals = 0;
+    bool restarted = !warm_ok;
+    std::vector<double> pe, rr;
+    double gv = 0.0, sdu = 0.0;
+    const ra::Point* out = nullptr;
+    ra::PriceLoop W(m, P->n, P->R.data(), o, warm_ok ? p0.data() : std::vector<double>(m, 1.0).data());
+    if (warm_ok) {
+        double rel0 = INFINITY;
+        while (!W.done()) {
+            st = run_pass(P, W.next(), W.pending(), graph, pe, gv, rr, sdu);
+            if (st == RA_ENUMERIC) {
+                restarted = true;
+                break;
+            }
+            if (st != RA_OK) return st;
+            W.feed(pe, gv, rr.data(), sdu);
+            if (W.ncertified() == 1 && !std::isfinite(rel0)) rel0 = W.last_certified().rel;
+            if (W.ncertified() >= window && !W.done()) {
+                const double best = W.result().certified ? W.result().rel : INFINITY;
+                if (!(best < rel0)) restarted = true;  // the gap did not fall: go cold
+                break;
+            }
+        }
+        warm_evals = W.evals();
+        if (!restarted) {
+            while (!W.done()) {
+                st = run_pass(P, W.next(), W.pending(), graph, pe, gv, rr, sdu);
+                if (st != RA_OK) return st;
+                W.feed(pe, gv, rr.data(), sdu);
+            }
+            out = &W.result();
+        }
+    }
+    ra_solve_opts oc = o;
+    oc.init = 0;
+    std::vector<double> ones(m, 1.0);
+    ra::PriceLoop C(m, P->n, P->R.data(), oc, ones.data());
+    if (restarted) {
+        while (!C.done()) {
+            st = run_pass(P, C.next(), C.pending(), graph, pe, gv, rr, sdu);
+            if (st != RA_OK) return st;
+            C.feed(pe, gv, rr.data(), sdu);
+        }
+        out = &C.result();
+    }
+    const ra::PriceLoop& L = restarted ? C : W;
+    for (int j = 0; j < m; ++j) p_out[j] = out->p[j];
+    const bool conv = L.converged();
+    if (info) {
+        info->iters = L.iters();
+        info->dual_evals = L.evals() + (restarted ? warm_evals : 0);
+        info->fell_back = L.fallbacks();
+        info->converged = conv ? 1 : 0;
+        info->g = out->g;
+        info->U_lb = out->certified ? out->U : NAN;
+        info->rel_gap = out->certified ? out->rel : INFINITY;
+        info->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->restarted = restarted ? 1 : 0;
+        info->warm_evals = restarted ? warm_evals : 0;
     }
     return conv ? RA_OK : RA_ENOTCONV;
 }
@@ -977,6 +1014,8 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
             infos[b].U_lb = ret.certified ? ret.U : NAN;
             infos[b].rel_gap = ret.certified ? ret.rel : INFINITY;
             infos[b].seconds = secs;
+            infos[b].restarted = 0;
+            infos[b].warm_evals = 0;
         }
     }
     return all ? RA_OK : RA_ENOTCONV;
