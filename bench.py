@@ -174,6 +174,63 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_warmstart(args):
+    """Learned warm start: train the network on `train_count` instances
+    (n = train_n, m = 16) solved by the batched solver, then compare time to
+    each fresh instance's gap target (n = eval_n) from p = 1 and from the
+    network's prediction (with the cold-restart fallback), plus a constant
+    predictor (the training mean) as ablation."""
+    import torch
+    import paper_2104_00282_amd as ra
+    from paper_2104_00282_amd import warmstart as ws
+
+    m = 16
+    ctx = ra.Context(0)
+    t0 = time.perf_counter()
+    log("training set: %d instances, n = %d" % (args.train_count, args.train_n))
+    X, Y, gaps = ws.solved_set(ctx, args.train_count, args.train_n, m,
+                               seed0=synth_seed(100000), log=log)
+    t_data = time.perf_counter() - t0
+    log("training")
+    net, tinfo = ws.train(ctx, X, Y, epochs=args.epochs, log=log)
+    const = ws.constant_network(ctx, net, Y)
+    log("evaluation: %d instances, n = %d" % (args.eval_count, args.eval_n))
+    rows = ws.evaluate(ctx, net, args.eval_count, args.eval_n, m, seed0=synth_seed(200000),
+                       const_net=const, stall_evals=args.stall_evals, log=log)
+    s = ws.summarize(rows)
+    out = {
+        "metric": "time to a 1e-4 relative gap, learned warm start vs cold start (also 1e-3 and "
+                  "max(1e-6, 1.5 floor) in summary)",
+        "value": s["0.0001"]["speedup_total"],
+        "unit": "speedup (x)",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "learned warm start: network 144 -> 256 -> 256 -> 16 trained on %d "
+                        "solved instances (n = %d, m = 16), evaluated on %d fresh instances "
+                        "(n = %d, m = 16)" % (args.train_count, args.train_n, args.eval_count,
+                                              args.eval_n),
+            "targets": "relative gaps 1e-3, 1e-4 and max(1e-6, 1.5 x floor), floor from a "
+                       "reference run",
+            "fallback": "cold restart when the certified gap has not fallen within 3 passes",
+        },
+        "summary": s,
+        "training": dict(tinfo, data_seconds=t_data,
+                         train_gap_median=float(np.median(gaps))),
+    }
+    net.close()
+    const.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def synth_seed(offset):
+    import synth
+    return synth.BASE_SEED + offset
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,21 +240,26 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale the HBM counters")
-    ap.add_argument("--workload", choices=["roofline", "batched"], default="roofline",
+    ap.add_argument("--workload", choices=["roofline", "batched", "warmstart"], default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--floor-iters", type=int, default=300)
     ap.add_argument("--stall-evals", type=int, default=100)
+    ap.add_argument("--train-count", type=int, default=20000)
+    ap.add_argument("--train-n", type=int, default=100000)
+    ap.add_argument("--eval-count", type=int, default=1000)
+    ap.add_argument("--eval-n", type=int, default=1000000)
+    ap.add_argument("--epochs", type=int, default=40)
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload == "batched":
+    if args.workload in ("batched", "warmstart"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        bench_batched(args)
+        (bench_batched if args.workload == "batched" else bench_warmstart)(args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

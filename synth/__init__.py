@@ -241,3 +241,28 @@ CONFIGS = {
     "mixed-16": mixed_16,
     "roofline-64": roofline_64,
 }
+
+
+def warmstart_device(n, m=16, seed=BASE_SEED + 100000, device="cuda"):
+    """The warm-start generator drawn on the GPU with torch's seeded generator
+    (fast enough for tens of thousands of instances): per-instance column
+    scale s_j ~ U[0.2, 5] and limit ratio rho_j ~ U[0.1, 0.5];
+    T_ij = s_j clip(exp(0.5 Z_ij), 0.01, 10); kind ~ Bernoulli(1/2);
+    w, c ~ U[0.5, 2]; R_j = rho_j n / m.  Returns (T, w, c, kind) device
+    tensors and R (numpy).  The streams differ from the numpy generator's, so
+    these instances are checked through properties and per-instance oracle
+    runs on copies, not regenerated on the host."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    colscale = 0.2 + 4.8 * torch.rand(m, generator=g, device=device, dtype=torch.float64)
+    rho = 0.1 + 0.4 * torch.rand(m, generator=g, device=device, dtype=torch.float64)
+    T = torch.randn((n, m), generator=g, device=device, dtype=torch.float32)
+    T.mul_(0.5).exp_().clamp_(0.01, 10.0)
+    T.mul_(colscale.to(torch.float32)[None, :])
+    kind = (torch.rand(n, generator=g, device=device) < 0.5).to(torch.uint8)
+    w = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
+    c = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
+    R = (rho * n / m).cpu().numpy()
+    return T.contiguous(), w, c, kind, R

@@ -1,0 +1,46 @@
+"""GPU test: what a trained warm-start network gains over the cold start.
+
+A small version of the benchmark pipeline: train on 400 solved instances
+(n = 20,000, m = 16), evaluate on 16 fresh ones (n = 50,000): the network's
+starting prices must cut the median number of passes to a 1e-3 relative gap,
+a warm solve's certificate must be confirmed by the oracle, and the
+network must beat the constant (training-mean) predictor on held-out loss.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_trained_network_gains_over_cold_start():
+    import torch
+    import oracle
+    import synth
+    import paper_2104_00282_amd as ra
+    from paper_2104_00282_amd import warmstart as ws
+
+    assert torch.cuda.is_available()
+    ctx = ra.Context(0)
+    m = 16
+    X, Y, gaps = ws.solved_set(ctx, 400, 20000, m, seed0=synth.BASE_SEED + 300000, group=200)
+    net, info = ws.train(ctx, X, Y, hidden=64, epochs=60, batch=64, lr=2e-3)
+    assert info["val_loss"] < 0.5 * info["const_val_loss"]
+    rows = ws.evaluate(ctx, net, 16, 50000, m, seed0=synth.BASE_SEED + 400000, group=16,
+                       levels=(1e-3, 1e-4))
+    s = ws.summarize(rows, levels=(1e-3, 1e-4))
+    print(s)
+    lv = s["0.001"]
+    assert lv["warm"]["evals_median"] < lv["cold"]["evals_median"]
+    assert lv["warm"]["reached"] >= lv["cold"]["reached"] - 1
+    # certificate of one warm solve, re-evaluated by the oracle on a host copy
+    T, w, c, kind, R = synth.warmstart_device(50000, m, seed=synth.BASE_SEED + 400000)
+    pr = ra.Problem(ctx, T, w, c, kind, R, 1e-3)
+    p, inf, _ = pr.solve_learned(net, tol_rel=1e-4, stall_evals=100)
+    Th, wh, ch, kh = T.cpu().numpy(), w.cpu().numpy(), c.cpu().numpy(), kind.cpu().numpy()
+    d = oracle.dual_eval(Th, wh, ch, kh, 1e-3, R, p, per_job=True)
+    U, _ = oracle.lower_bound(Th, wh, ch, kh, 1e-3, R, d.r, d.jobs)
+    assert abs(inf["g"] - d.g) <= 1e-5 * (abs(d.g) + abs(U))
+    assert abs(inf["U_lb"] - U) <= 1e-5 * (abs(d.g) + abs(U))
+    pr.close()
+    net.close()
+    ctx.close()
