@@ -135,6 +135,10 @@ typedef struct {
     int32_t max_evals;       /* > 0: stop after at most this many passes over T      */
     int32_t stall_evals;     /* > 0: stop when the best certified relative gap has
                                 not improved by 0.1% within this many passes       */
+    double init_step;        /* > 0: a step taken with an empty L-BFGS memory moves
+                                the largest price by this fraction of max_j p_j;
+                                0 = the default (0.1, or 0.02 from a learned start);
+                                must be finite, 0 <= init_step <= 10               */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
@@ -153,7 +157,7 @@ typedef struct {
 
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
- * stall_evals = 0 (off). */
+ * stall_evals = 0 (off), init_step = 0 (default step). */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
 /* Price discovery (§5, Algorithm 2). Every pass over T evaluates g and its
@@ -247,9 +251,11 @@ ra_status ra_mlp_save(const ra_mlp *mlp, const char *path);
 ra_status ra_mlp_load(ra_ctx *ctx, const char *path, ra_mlp **out);
 
 /* Price discovery from a learned starting point: features, network forward,
- * p0 = exp(predicted log-prices), then the loop of ra_solve.  If after
- * `fallback_window` evaluations the certified relative gap has not fallen
- * below that of the starting point (or any value is non-finite), the warm
+ * p0 = exp(predicted log-prices), then the loop of ra_solve, with its
+ * empty-memory steps sized by opts->init_step (default 0.02: a prediction is
+ * expected within a few percent).  If after `fallback_window` certificates
+ * the certified relative gap has not fallen below that of the starting
+ * point (or any value is non-finite), the warm
  * run is abandoned and the solve restarts from p = 1 (info->restarted = 1,
  * info->warm_evals = passes spent before the restart, included in
  * dual_evals and seconds).  The network's out_dim must equal the problem's m. */

@@ -140,9 +140,10 @@ class Problem:
         return out
 
     def solve(self, p0=None, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, method=0, use_graph=True,
-              verbose=False, max_evals=0, stall_evals=0):
+              verbose=False, max_evals=0, stall_evals=0, init_step=0.0):
         """Price discovery; returns (p, info dict, status)."""
         o = ra_solve_opts_default()
+        o.init_step = init_step
         o.max_evals = max_evals
         o.stall_evals = stall_evals
         o.tol_rel = tol_rel
@@ -167,9 +168,10 @@ class Problem:
         return f
 
     def solve_learned(self, mlp, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, use_graph=True,
-                      max_evals=0, stall_evals=0, fallback_window=3):
+                      max_evals=0, stall_evals=0, fallback_window=3, init_step=0.0):
         """Price discovery from the network's predicted prices (ra_solve_learned)."""
         o = ra_solve_opts_default()
+        o.init_step = init_step
         o.tol_rel = tol_rel
         o.max_iter = max_iter
         o.lbfgs_mem = lbfgs_mem
@@ -194,7 +196,7 @@ class Problem:
 
 
 def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lbfgs_mem=10,
-                method=0, use_graph=True, max_evals=0, stall_evals=0):
+                method=0, use_graph=True, max_evals=0, stall_evals=0, init_step=0.0):
     """Solve several Problems of one Context together (ra_batch_solve).
     Returns (list of price arrays, list of info dicts, status)."""
     if not problems:
@@ -209,6 +211,7 @@ def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lb
     o.use_graph = 1 if use_graph else 0
     o.max_evals = max_evals
     o.stall_evals = stall_evals
+    o.init_step = init_step
     ms = [pr.m for pr in problems]
     offs = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
     p = np.ones(int(offs[-1]))

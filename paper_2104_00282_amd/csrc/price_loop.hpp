@@ -10,7 +10,8 @@
 // d = -H grad f from the two-loop recursion with H0 = (s^T y / y^T y) I, with
 // components that would push a zero price negative removed (memory cleared if
 // d is then not a descent direction); trial p+ = max(p + lambda d, 0) with
-// lambda = 1, or 0.1 |p|_inf / |d|_inf when the memory is empty; Armijo test
+// lambda = 1, or s0 |p|_inf / |d|_inf when the memory is empty (s0 = init_step,
+// 0.1 when unset); Armijo test
 // f(p+) <= f(p) + 1e-4 grad^T (p+ - p) with up to 20 halvings; a pair is kept
 // if s^T y > 1e-12 |s| |y|.  When the line search fails, one projected
 // subgradient step p+ = max(p - a_k q, 0), a_k = a0 / sqrt(k),
@@ -224,7 +225,8 @@ private:
         lam_ = 1.0;
         if (npairs_ == 0) {
             const double pi = inf_norm(cur_.p);
-            lam_ = 0.1 * (pi > 0.0 ? pi : 1.0) / dn;
+            const double s0 = o_.init_step > 0.0 ? o_.init_step : 0.1;
+            lam_ = s0 * (pi > 0.0 ? pi : 1.0) / dn;
         }
         ls_ = 0;
         state_ = LINE_SEARCH;

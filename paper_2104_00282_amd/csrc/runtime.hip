@@ -424,6 +424,14 @@ void ra_solve_opts_default(ra_solve_opts* o)
     o->verbose = 0;
     o->max_evals = 0;
     o->stall_evals = 0;
+    o->init_step = 0.0;
+}
+
+static bool valid_opts(const ra_solve_opts& o)
+{
+    return o.tol_rel >= 0.0 && o.max_iter >= 0 && o.max_evals >= 0 && o.stall_evals >= 0 &&
+           o.lbfgs_mem >= 1 && o.lbfgs_mem <= 64 && (o.method == 0 || o.method == 1) &&
+           (o.init == 0 || o.init == 1) && o.init_step >= 0.0 && o.init_step <= 10.0;
 }
 
 ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opts,
@@ -435,10 +443,7 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
     ra_solve_opts o;
     ra_solve_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.stall_evals < 0 ||
-        o.lbfgs_mem < 1 || o.lbfgs_mem > 64 ||
-        (o.method != 0 && o.method != 1) || (o.init != 0 && o.init != 1))
-        return fail(ctx, RA_EINVAL, "invalid solve options");
+    if (!valid_opts(o)) return fail(ctx, RA_EINVAL, "invalid solve options");
     ra_problem* P = const_cast<ra_problem*>(prob);
     const int m = P->m;
     std::vector<double> p(m, 1.0);
@@ -510,9 +515,7 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
     ra_solve_opts o;
     ra_solve_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.stall_evals < 0 ||
-        o.lbfgs_mem < 1 || o.lbfgs_mem > 64 || (o.method != 0 && o.method != 1))
-        return fail(ctx, RA_EINVAL, "invalid solve options");
+    if (!valid_opts(o)) return fail(ctx, RA_EINVAL, "invalid solve options");
     RA_HIP(ctx, hipSetDevice(ctx->dev));
     const auto t0 = std::chrono::steady_clock::now();
     const bool graph = o.use_graph && ctx->stream != nullptr;
@@ -527,7 +530,11 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
     std::vector<double> pe, rr;
     double gv = 0.0, sdu = 0.0;
     const ra::Point* out = nullptr;
-    ra::PriceLoop W(m, P->n, P->R.data(), o, warm_ok ? p0.data() : std::vector<double>(m, 1.0).data());
+    // a predicted start is expected within a few percent of p*: the first
+    // step is kept to that scale so that it does not undo the prediction
+    ra_solve_opts ow = o;
+    if (ow.init_step == 0.0) ow.init_step = 0.02;
+    ra::PriceLoop W(m, P->n, P->R.data(), ow, warm_ok ? p0.data() : std::vector<double>(m, 1.0).data());
     if (warm_ok) {
         double rel0 = INFINITY;
         while (!W.done()) {
@@ -889,10 +896,7 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     ra_solve_opts o;
     ra_solve_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.tol_rel >= 0.0) || o.max_iter < 0 || o.max_evals < 0 || o.stall_evals < 0 ||
-        o.lbfgs_mem < 1 || o.lbfgs_mem > 64 || (o.method != 0 && o.method != 1) ||
-        (o.init != 0 && o.init != 1))
-        return fail(ctx, RA_EINVAL, "invalid solve options");
+    if (!valid_opts(o)) return fail(ctx, RA_EINVAL, "invalid solve options");
     std::vector<ra_problem*> P(probs, probs + B);
     std::vector<size_t> off(B + 1, 0);
     for (int b = 0; b < B; ++b) {
