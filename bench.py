@@ -67,7 +67,7 @@ def calibrate_copy(reps=5):
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": reps}))
 
 
-def cpu_baseline(p, target_s=12.0, max_rows=4_000_000):
+def cpu_baseline(p, target_s=15.0, max_rows=10_000_000):
     """The FP64 oracle's dual evaluation on rows [0, S) of the same instance."""
     import oracle
     import synth
