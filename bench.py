@@ -192,7 +192,7 @@ def bench_warmstart(args):
                                seed0=synth_seed(100000), log=log)
     t_data = time.perf_counter() - t0
     log("training")
-    net, tinfo = ws.train(ctx, X, Y, epochs=args.epochs, log=log)
+    net, tinfo = ws.train(ctx, X, Y, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     const = ws.constant_network(ctx, net, Y)
     log("evaluation: %d instances, n = %d" % (args.eval_count, args.eval_n))
     rows = ws.evaluate(ctx, net, args.eval_count, args.eval_n, m, seed0=synth_seed(200000),
@@ -209,12 +209,14 @@ def bench_warmstart(args):
         "data": "synthetic",
         "config": {
             "workload": "learned warm start: network 144 -> 256 -> 256 -> 16 trained on %d "
-                        "solved instances (n = %d, m = 16), evaluated on %d fresh instances "
-                        "(n = %d, m = 16)" % (args.train_count, args.train_n, args.eval_count,
-                                              args.eval_n),
+                        "solved instances (n = %d, m = 16; %d epochs, batch %d, Adam lr %g "
+                        "decayed 10x), evaluated on %d fresh instances (n = %d, m = 16)"
+                        % (args.train_count, args.train_n, args.epochs, args.batch, args.lr,
+                           args.eval_count, args.eval_n),
             "targets": "relative gaps 1e-3, 1e-4 and max(1e-6, 1.5 x floor), floor from a "
                        "reference run",
-            "fallback": "cold restart when the certified gap has not fallen within 3 passes",
+            "fallback": "cold restart when the certified gap has not fallen below the first "
+                        "certificate within 5 certificates",
         },
         "summary": s,
         "training": dict(tinfo, data_seconds=t_data,
@@ -250,7 +252,9 @@ def main():
     ap.add_argument("--train-n", type=int, default=100000)
     ap.add_argument("--eval-count", type=int, default=1000)
     ap.add_argument("--eval-n", type=int, default=1000000)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--lr", type=float, default=3e-3)
     args = ap.parse_args()
     if args.calibrate_copy:
         calibrate_copy()

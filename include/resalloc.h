@@ -263,6 +263,13 @@ ra_status ra_solve_learned(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp,
                            const ra_solve_opts *opts, int32_t fallback_window, double *p_out,
                            ra_solve_info *info);
 
+/* The starting prices ra_solve_learned would use: p_out[j] = exp(y_j), y the
+ * network's de-standardised output on the problem's features (ra_features).
+ * p_out: host, m doubles.  Same requirements as ra_solve_learned; blocks
+ * until the prices are on the host.  Errors: RA_EINVAL, RA_EUNSUPPORTED,
+ * RA_EDEVICE. */
+ra_status ra_predict_prices(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp, double *p_out);
+
 /* Kernel timing on the context's stream (for benchmarks and profiling).
  * enable = 1 brackets every launch of the dual kernel with a pair of HIP
  * events on the context's stream and accumulates the elapsed times; while it

@@ -167,8 +167,15 @@ class Problem:
         _capi.check(self.ctx.handle, _capi.lib().ra_features(self.ctx.handle, self.handle, _dptr(f)))
         return f
 
+    def predict_prices(self, mlp):
+        """Starting prices predicted by the network (ra_predict_prices)."""
+        p = np.zeros(self.m)
+        _capi.check(self.ctx.handle, _capi.lib().ra_predict_prices(self.ctx.handle, self.handle,
+                                                                   mlp.handle, _hbuf(p)))
+        return p
+
     def solve_learned(self, mlp, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, use_graph=True,
-                      max_evals=0, stall_evals=0, fallback_window=3, init_step=0.0):
+                      max_evals=0, stall_evals=0, fallback_window=5, init_step=0.0):
         """Price discovery from the network's predicted prices (ra_solve_learned)."""
         o = ra_solve_opts_default()
         o.init_step = init_step

@@ -658,8 +658,13 @@ __global__ void __launch_bounds__(64) k_batch_reduce(const double* __restrict__ 
 // ------------------------------------------------------------------------
 // Column reduction of block partials: one block per column, fixed order.
 // ------------------------------------------------------------------------
+// With `flag` set, out is host memory the host polls: each block makes its
+// column visible system-wide, takes a ticket, and the block holding the last
+// ticket resets the ticket counter and raises *flag = 1.
 __global__ void __launch_bounds__(256) k_reduce_cols(const double* __restrict__ partial, int nb,
-                                                     int ncols, double* __restrict__ out)
+                                                     int ncols, double* __restrict__ out,
+                                                     unsigned* __restrict__ ticket,
+                                                     unsigned* __restrict__ flag)
 {
     __shared__ double red[256];
     const int j = blockIdx.x;
@@ -671,7 +676,17 @@ __global__ void __launch_bounds__(256) k_reduce_cols(const double* __restrict__ 
         if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[j] = red[0];
+    if (threadIdx.x == 0) {
+        out[j] = red[0];
+        if (flag) {
+            __threadfence_system();
+            if (atomicAdd(ticket, 1u) == (unsigned)gridDim.x - 1u) {
+                atomicExch(ticket, 0u);
+                __threadfence_system();
+                __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -879,9 +894,9 @@ hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem
 }
 
 hipError_t launch_reduce_cols(hipStream_t st, const double* partial, int nb, int ncols,
-                              double* out)
+                              double* out, unsigned* ticket, unsigned* flag)
 {
-    k_reduce_cols<<<ncols, 256, 0, st>>>(partial, nb, ncols, out);
+    k_reduce_cols<<<ncols, 256, 0, st>>>(partial, nb, ncols, out, ticket, flag);
     return hipGetLastError();
 }
 

@@ -194,19 +194,26 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 }
 
 // --------------------------------------------------------------- features --
-// Block j < m: column j of the sampled rows, sorted by (kind, value) with a
-// bitonic sort of 64-bit keys in LDS; nearest-rank quantiles per kind, the
-// FP64 column sum, R_j / n.  Block m: the weight histograms.
+// Block j < m: column j of the sampled rows.  Each sample gets the 32-bit key
+// (kind << 31) | bits(value) (values are >= 0, so key order is (kind, value)
+// order); the nearest-rank quantiles of each kind are the keys of global
+// rank r in that order, found by a radix select (4 passes of 8 bits, all six
+// ranks at once) instead of a full sort.  Also the FP64 column sum and
+// R_j / n.  Block m: the weight histograms.
 __global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
                                                    const float2* __restrict__ prm, int64_t n,
                                                    int m, const double* __restrict__ R,
                                                    float* __restrict__ feat)
 {
-    __shared__ unsigned long long key[FEAT_SAMPLE];
+    __shared__ unsigned key[FEAT_SAMPLE];
     __shared__ double red[1024];
     __shared__ int cnt[16];
+    __shared__ unsigned hist[6][256];
+    __shared__ unsigned tpre[6], trank[6];
+    __shared__ int tgrp[6], tvalid[6], n0s;
     const int S = (int)(n < FEAT_SAMPLE ? n : FEAT_SAMPLE);
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
     const int j = blockIdx.x;
     if (j == m) {
         if (tid < 16) cnt[tid] = 0;
@@ -223,69 +230,147 @@ __global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
         if (tid < 16) feat[8 * m + tid] = (float)cnt[tid] / (float)S;
         return;
     }
-    int P2 = 1;
-    while (P2 < S) P2 <<= 1;
+    if (tid == 0) n0s = 0;
+    __syncthreads();
     double s = 0.0;
-    for (int k = tid; k < P2; k += 1024) {
-        if (k < S) {
-            const int64_t i = ((int64_t)k * n) / S;
-            const float v = T[i * m + j];
-            const unsigned kind = prm[i].y >= 0.f ? 1u : 0u;
-            key[k] = ((unsigned long long)kind << 32) | (unsigned long long)__float_as_uint(v);
-            s += (double)v;
-        } else {
-            key[k] = ~0ull;
-        }
+    int c0 = 0;
+    for (int k = tid; k < S; k += 1024) {
+        const int64_t i = ((int64_t)k * n) / S;
+        const float v = T[i * m + j];
+        const unsigned kind = prm[i].y >= 0.f ? 1u : 0u;
+        // -0 and +0 share a key
+        const unsigned bits = v == 0.f ? 0u : __float_as_uint(v);
+        key[k] = (kind << 31) | (bits & 0x7fffffffu);
+        s += (double)v;
+        c0 += kind == 0u ? 1 : 0;
     }
     red[tid] = s;
+    atomicAdd(&n0s, c0);
     __syncthreads();
     for (int h = 512; h > 0; h >>= 1) {
         if (tid < h) red[tid] += red[tid + h];
         __syncthreads();
     }
-    // bitonic sort, ascending
-    for (int size = 2; size <= P2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int k = tid; k < P2; k += 1024) {
-                const int partner = k ^ stride;
-                if (partner > k) {
-                    const bool up = (k & size) == 0;
-                    const unsigned long long a = key[k], b = key[partner];
-                    if ((a > b) == up) {
-                        key[k] = b;
-                        key[partner] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
     if (tid == 0) {
-        // number of log-kind keys: first index with the kind bit set
-        int lo = 0, hi = S;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((key[mid] >> 32) == 0) lo = mid + 1;
-            else hi = mid;
-        }
-        const int n0 = lo;
+        const int n0 = n0s;
         const double qs[3] = {0.1, 0.5, 0.9};
         for (int kind = 0; kind < 2; ++kind) {
             const int base = kind == 0 ? 0 : n0;
             const int cntk = kind == 0 ? n0 : S - n0;
             for (int q = 0; q < 3; ++q) {
-                float v = 0.f;
-                if (cntk > 0) {
-                    const int idx = (int)floor(qs[q] * (double)(cntk - 1) + 0.5);
-                    v = __uint_as_float((unsigned)(key[base + idx] & 0xffffffffull));
-                }
-                feat[8 * j + 3 * kind + q] = v;
+                const int t = 3 * kind + q;
+                const int idx = cntk > 0 ? (int)floor(qs[q] * (double)(cntk - 1) + 0.5) : 0;
+                tvalid[t] = cntk > 0 ? 1 : 0;
+                trank[t] = (unsigned)(base + idx);
+                tpre[t] = 0u;
             }
         }
+    }
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        const unsigned hmask = pass == 0 ? 0u : (0xffffffffu << (shift + 8));
+        for (int e = tid; e < 6 * 256; e += 1024) (&hist[0][0])[e] = 0u;
+        __syncthreads();
+        if (tid == 0) {
+            // ranks whose key prefixes agree share one histogram
+            for (int t = 0; t < 6; ++t) {
+                int g = t;
+                for (int u = 0; u < t; ++u)
+                    if (tgrp[u] == u && tpre[u] == tpre[t]) {
+                        g = u;
+                        break;
+                    }
+                tgrp[t] = g;
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < S; k += 1024) {
+            const unsigned kv = key[k];
+            const unsigned d = (kv >> shift) & 255u;
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+                if (tgrp[t] == t && (kv & hmask) == tpre[t]) atomicAdd(&hist[t][d], 1u);
+        }
+        __syncthreads();
+        if (wv < 6 && tvalid[wv]) {
+            // wave t: the digit bin holding rank trank[t] of its prefix group
+            const unsigned* h = hist[tgrp[wv]];
+            unsigned c[4], ls = 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                c[q] = h[4 * lane + q];
+                ls += c[q];
+            }
+            unsigned x = ls;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const unsigned y = __shfl_up(x, off);
+                if (lane >= off) x += y;
+            }
+            const unsigned excl = x - ls, r = trank[wv];
+            if (excl <= r && r < x) {
+                unsigned acc = excl;
+                int bsel = 4 * lane + 3;
+                for (int q = 0; q < 4; ++q) {
+                    if (r < acc + c[q]) {
+                        bsel = 4 * lane + q;
+                        break;
+                    }
+                    acc += c[q];
+                }
+                tpre[wv] = tpre[wv] | ((unsigned)bsel << shift);
+                trank[wv] = r - acc;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        for (int t = 0; t < 6; ++t)
+            feat[8 * j + t] = tvalid[t] ? __uint_as_float(tpre[t] & 0x7fffffffu) : 0.f;
         feat[8 * j + 6] = (float)(R[j] / (double)n);
         const double mean = red[0] / (double)S;
         feat[8 * j + 7] = (float)log(mean > 1e-30 ? mean : 1e-30);
     }
+}
+
+// Forward of one feature row in one block (the warm-start prediction):
+// standardise, two ReLU layers, output layer, de-standardise.  One wave per
+// output unit at a time, lanes striding over the inputs (rows of W are
+// contiguous), wave sums by butterfly.  y receives the log-prices.
+__global__ void __launch_bounds__(1024) k_forward1(const float* __restrict__ P, int64_t oW1,
+                                                   int64_t ob1, int64_t oW2, int64_t ob2,
+                                                   int64_t oW3, int64_t ob3,
+                                                   const float* __restrict__ norm, int D, int H,
+                                                   int O, const float* __restrict__ x,
+                                                   float* __restrict__ y)
+{
+    extern __shared__ float fsh[];
+    float* xs = fsh;
+    float* h1 = fsh + D;
+    float* h2 = h1 + H;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    for (int k = tid; k < D; k += blockDim.x) xs[k] = (x[k] - norm[k]) / norm[D + k];
+    __syncthreads();
+    auto layer = [&](const float* W, const float* bias, const float* in, int K, int N, float* out,
+                     bool relu) {
+        for (int r = wv; r < N; r += nw) {
+            const float* w = W + (int64_t)r * K;
+            float acc = 0.f;
+            for (int k = lane; k < K; k += 64) acc += w[k] * in[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if (lane == 0) {
+                const float v = acc + bias[r];
+                out[r] = relu ? fmaxf(v, 0.f) : v;
+            }
+        }
+        __syncthreads();
+    };
+    layer(P + oW1, P + ob1, xs, D, H, h1, true);
+    layer(P + oW2, P + ob2, h1, H, H, h2, true);
+    layer(P + oW3, P + ob3, h2, H, O, xs, false);  // xs is free again
+    const float* ym = norm + 2 * D;
+    for (int k = tid; k < O; k += blockDim.x) y[k] = xs[k] * ym[O + k] + ym[k];
 }
 
 int grid_for(int64_t total) { return (int)std::min<int64_t>(4096, (total + 255) / 256 + 1); }
@@ -402,11 +487,19 @@ ra_status predict_prices(ra_mlp* N, ra_problem* P, std::vector<double>& p0)
     if (ensure_cap(N, 1) != RA_OK) return RA_ENOMEM;
     ra_status s = features_into(P, N->feat);
     if (s != RA_OK) return s;
-    s = forward_std(N, 1, N->feat);
-    if (s != RA_OK) return s;
     float* Y = N->feat + N->D;
-    const float* ym = N->norm + 2 * N->D;
-    k_destandardize<<<1, 256, 0, ctx->stream>>>(N->Ys, ym, ym + N->O, N->O, N->O, Y);
+    const size_t lds = sizeof(float) * ((size_t)N->D + 2 * (size_t)N->H);
+    if (N->O <= N->D && lds <= 48 * 1024) {
+        k_forward1<<<1, 1024, lds, ctx->stream>>>(N->params, N->oW1, N->ob1, N->oW2, N->ob2,
+                                                  N->oW3, N->ob3, N->norm, N->D, N->H, N->O,
+                                                  N->feat, Y);
+        RA_HIP(ctx, hipGetLastError());
+    } else {
+        s = forward_std(N, 1, N->feat);
+        if (s != RA_OK) return s;
+        const float* ym = N->norm + 2 * N->D;
+        k_destandardize<<<1, 256, 0, ctx->stream>>>(N->Ys, ym, ym + N->O, N->O, N->O, Y);
+    }
     std::vector<float> y(N->O);
     RA_HIP(ctx, hipMemcpyAsync(y.data(), Y, sizeof(float) * N->O, hipMemcpyDeviceToHost,
                                ctx->stream));

@@ -46,7 +46,9 @@ struct ra_problem {
     double* dout = nullptr;     // r[0..m), sum v, sum u(t~), sum u(t) - u(t~)
     void* pblock = nullptr;
     void* h_pblock = nullptr;
-    double* h_out = nullptr;
+    double* h_out = nullptr;    // fine-grained host memory: m + 3 results, then the flag
+    unsigned* h_flag = nullptr; // set to 1 by the reduction when a solver pass is done
+    unsigned* ticket = nullptr; // device block counter of that reduction
     int16_t* jpair_ws = nullptr;
     void* tpair_ws = nullptr;
     void* xpair_ws = nullptr;

@@ -61,9 +61,12 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
                        const void* prm, int64_t n, const void* prices, double eps,
                        double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1);
 
-// out[j] = sum_b partial[b * ncols + j], j < ncols (fixed order).
+// out[j] = sum_b partial[b * ncols + j], j < ncols (fixed order).  With flag
+// (host memory, fine-grained) and ticket (device counter, zero between
+// launches), the launch ends by setting *flag = 1 after every out[j] is
+// visible to the host.
 hipError_t launch_reduce_cols(hipStream_t st, const double* partial, int nb, int ncols,
-                              double* out);
+                              double* out, unsigned* ticket = nullptr, unsigned* flag = nullptr);
 
 // Lower bound of the column-scaled allocation (§5): partial2 [grid][2] gets
 // sum_i u_i(t~_i) and sum_i u_i(t_i) - u_i(t~_i); r and R are device m-vectors.

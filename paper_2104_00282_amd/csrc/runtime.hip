@@ -101,9 +101,12 @@ ra_status ensure_support_ws(ra_problem* P)
     return RA_OK;
 }
 
-// Queue one evaluation on the context stream (no synchronisation).
+// Queue one evaluation on the context stream (no synchronisation).  With
+// `signal` (solver passes: no per-job outputs, no separate lower bound) the
+// reduction writes its results straight into P->h_out and raises P->h_flag;
+// otherwise the results are copied to P->h_out and the caller synchronises.
 ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_user,
-                       int16_t* j1_user)
+                       int16_t* j1_user, bool signal = false)
 {
     ra_ctx* ctx = P->ctx;
     hipStream_t st = ctx->stream;
@@ -119,6 +122,11 @@ ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_
         RA_HIP(ctx, hipEventRecord(ctx->ev1, st));
         ctx->timed_pending = true;
     }
+    if (signal) {
+        RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial, P->grid, ra::partial_cols(P->m),
+                                           P->h_out, P->ticket, P->h_flag));
+        return RA_OK;
+    }
     RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial, P->grid, ra::partial_cols(P->m), P->dout));
     if (lb) {
         RA_HIP(ctx, ra::launch_lower(P->dt, P->lgrid, st, jp, tp, P->prm, P->n, P->m, P->Rdev,
@@ -130,10 +138,11 @@ ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_
     return RA_OK;
 }
 
-// Add the last timed launch to the totals (after the stream has synchronised).
+// Add the last timed launch to the totals.
 ra_status collect_timing(ra_ctx* ctx)
 {
     if (!ctx->timed_pending) return RA_OK;
+    RA_HIP(ctx, hipEventSynchronize(ctx->ev1));
     float ms = 0.f;
     RA_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     ctx->timed_ms += ms;
@@ -147,7 +156,7 @@ ra_status capture_graph(ra_problem* P)
     ra_ctx* ctx = P->ctx;
     if (P->gexec) return RA_OK;
     RA_HIP(ctx, hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-    ra_status st = enqueue_eval(P, false, nullptr, nullptr, nullptr);
+    ra_status st = enqueue_eval(P, false, nullptr, nullptr, nullptr, true);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->stream, &g);
     if (st != RA_OK) {
@@ -164,6 +173,27 @@ ra_status capture_graph(ra_problem* P)
     return RA_OK;
 }
 
+// Wait for the completion flag of a signalled pass.  The stream is queried
+// now and then, so that a failed or finished stream without the flag ends
+// the wait with an error instead of spinning.
+ra_status wait_flag(ra_problem* P)
+{
+    ra_ctx* ctx = P->ctx;
+    for (uint64_t k = 1;; ++k) {
+        if (__atomic_load_n(P->h_flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
+        if ((k & 4095) == 0) {
+            const hipError_t e = hipStreamQuery(ctx->stream);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(P->h_flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
+                return fail(ctx, RA_EDEVICE, "evaluation finished without its completion flag");
+            }
+            if (e != hipErrorNotReady)
+                return fail(ctx, RA_EDEVICE, "evaluation failed: %s", hipGetErrorString(e));
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 // One pass over T at p: dual value and usage at p (p_eval = p as rounded for
 // the kernel) and, when prev is given, the utility lost by scaling prev's
 // allocation (sdu), all from one launch of the dual kernel.
@@ -175,15 +205,17 @@ ra_status run_pass(ra_problem* P, const std::vector<double>& p, const ra::Point*
     p_eval.resize(P->m);
     const double pR = fill_prices(P, p.data(), &p_eval);
     if (prev) fill_prev(P, prev->p, prev->r);
+    __atomic_store_n(P->h_flag, 0u, __ATOMIC_RELEASE);
     if (use_graph && !ctx->timing) {
         ra_status st = capture_graph(P);
         if (st != RA_OK) return st;
         RA_HIP(ctx, hipGraphLaunch(P->gexec, ctx->stream));
     } else {
-        ra_status st = enqueue_eval(P, false, nullptr, nullptr, nullptr);
+        ra_status st = enqueue_eval(P, false, nullptr, nullptr, nullptr, true);
         if (st != RA_OK) return st;
     }
-    RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    ra_status ws = wait_flag(P);
+    if (ws != RA_OK) return ws;
     if (collect_timing(ctx) != RA_OK) return RA_EDEVICE;
     const double* o = P->h_out;
     g = pR + o[P->m];
@@ -287,6 +319,7 @@ ra_status ra_problem_destroy(ra_problem* P)
     (void)hipFree(P->xpair_ws);
     if (P->h_pblock) (void)hipHostFree(P->h_pblock);
     if (P->h_out) (void)hipHostFree(P->h_out);
+    (void)hipFree(P->ticket);
     ra_ctx* ctx = P->ctx;
     delete P;
     if (ctx && --ctx->live_problems == 0 && ctx->closed) free_ctx(ctx);
@@ -345,7 +378,11 @@ ra_status ra_problem_create(ra_ctx* ctx, ra_problem** out, int64_t n, int32_t m,
     RA_ALLOC(hipMalloc(&P->dout, sizeof(double) * (m + 3)));
     RA_ALLOC(hipMalloc(&P->pblock, price_block_bytes(P->dt)));
     RA_ALLOC(hipHostMalloc(&P->h_pblock, price_block_bytes(P->dt), hipHostMallocDefault));
-    RA_ALLOC(hipHostMalloc((void**)&P->h_out, sizeof(double) * (m + 3), hipHostMallocDefault));
+    RA_ALLOC(hipHostMalloc((void**)&P->h_out, sizeof(double) * (m + 4), hipHostMallocCoherent));
+    P->h_flag = reinterpret_cast<unsigned*>(P->h_out + m + 3);
+    *P->h_flag = 0u;
+    RA_ALLOC(hipMalloc((void**)&P->ticket, sizeof(unsigned)));
+    RA_ALLOC(hipMemsetAsync(P->ticket, 0, sizeof(unsigned), ctx->stream));
     std::memset(P->h_pblock, 0, price_block_bytes(P->dt));
     RA_ALLOC(hipMemcpyAsync(P->Rdev, R, sizeof(double) * m, hipMemcpyHostToDevice, ctx->stream));
 
@@ -474,6 +511,8 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
                     c.gap / (double)P->n);
         }
     }
+    // the last reduction may still be retiring after its flag
+    RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const ra::Point& ret = L.result();
     const bool conv = L.converged();
     if (o.verbose)
@@ -494,6 +533,24 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
         info->warm_evals = 0;
     }
     return conv ? RA_OK : RA_ENOTCONV;
+}
+
+ra_status ra_predict_prices(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp, double* p_out)
+{
+    if (!ctx || ctx->closed) return RA_EINVAL;
+    if (!prob || prob->ctx != ctx) return fail(ctx, RA_EINVAL, "problem is NULL or from another context");
+    if (!mlp || !p_out) return fail(ctx, RA_EINVAL, "network and p_out are required");
+    ra_problem* P = const_cast<ra_problem*>(prob);
+    if (P->dt != 0 || P->m > 64)
+        return fail(ctx, RA_EUNSUPPORTED, "learned warm start needs an FP32 problem with m <= 64");
+    if (ra::mlp_out_dim(mlp) != P->m || ra::mlp_in_dim(mlp) != 8 * P->m + 16)
+        return fail(ctx, RA_EINVAL, "network dimensions do not match the problem (in 8m+16, out m)");
+    RA_HIP(ctx, hipSetDevice(ctx->dev));
+    std::vector<double> p0;
+    ra_status st = ra::predict_prices(mlp, P, p0);
+    if (st != RA_OK) return st;
+    for (int j = 0; j < P->m; ++j) p_out[j] = p0[j];
+    return RA_OK;
 }
 
 // Learned warm start with a cold restart when the warm run does not improve
@@ -574,6 +631,7 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
         }
         out = &C.result();
     }
+    RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const ra::PriceLoop& L = restarted ? C : W;
     for (int j = 0; j < m; ++j) p_out[j] = out->p[j];
     const bool conv = L.converged();

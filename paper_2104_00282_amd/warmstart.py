@@ -103,7 +103,7 @@ LEVELS = (1e-3, 1e-4, "floor")
 
 
 def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters=300,
-             stall_evals=100, max_iter=500, fallback_window=3, levels=LEVELS, log=None):
+             stall_evals=100, max_iter=500, fallback_window=5, levels=LEVELS, log=None):
     """Cold start (p = 1) vs learned warm start on fresh instances, to each
     relative-gap level of `levels` separately ("floor" = max(1e-6, 1.5 x the
     smallest gap a long reference run certifies), the tightest target the

@@ -85,6 +85,27 @@ def test_forward_and_gradients_match_fp64(ctx, torch, D, H, O, B):
     net.close()
 
 
+@pytest.mark.parametrize("H", [256, 33])
+def test_predicted_prices_match_fp64(ctx, torch, H):
+    """ra_predict_prices (features, then the single-row forward kernel) against
+    the FP64 network on the same feature row."""
+    m = 16
+    D = 8 * m + 16
+    I = synth.warmstart_instance(50000, m=m, seed=777)
+    pr = _problem(ctx, torch, I)
+    net, params, norm, _ = _random_net(ctx, D, H, m, seed=H)
+    f = pr.features().cpu().numpy()
+    p = pr.predict_prices(net)
+    yref, _ = om.forward(params.astype(np.float64), D, H, m, norm, f[None, :])
+    assert np.all(p > 0)
+    assert np.allclose(np.log(p), yref[0], rtol=1e-5, atol=1e-5 * np.abs(yref).max())
+    # the batched forward path gives the same outputs
+    yb = net.forward(torch.from_numpy(f[None, :]).cuda()).cpu().numpy()[0]
+    assert np.allclose(yb, np.log(p), rtol=1e-5, atol=1e-5 * np.abs(yref).max())
+    net.close()
+    pr.close()
+
+
 def test_training_reduces_loss_and_save_load(ctx, torch):
     import paper_2104_00282_amd as ra
     D, H, O, B = 24, 64, 4, 128
