@@ -103,3 +103,19 @@ def test_allocation_matches_certificate(ctx, torch):
     t = np.einsum("ij,ij->i", I.T.astype(np.float64), X)
     u = np.where(I.kind == 0, I.w * np.log(t + I.eps), I.w * np.minimum(t, I.c))
     assert u.sum() == pytest.approx(info["U_lb"], rel=1e-5)
+
+
+@pytest.mark.parametrize("m", [64, 16])
+def test_fused_certificate_matches_separate_bound(ctx, torch, m):
+    """A solve's certificate comes from the fused pass (the next pass solves
+    every job again at the previous prices inside the same sweep over T); it
+    must agree with the separate lower-bound path of ra_dual_eval at the same
+    prices, on a ragged n, after runs of several lengths."""
+    I = synth.random_small(100003, m, seed=46 + m, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    for iters in (1, 2, 5, 17):
+        p, info, _ = prob.solve(tol_rel=0.0, max_iter=iters, max_evals=iters + 1)
+        d = prob.dual_eval(p, lower_bound=True)
+        assert info["g"] == d["g"]
+        assert info["U_lb"] == pytest.approx(d["lower_bound"], rel=1e-10)
+    prob.close()
