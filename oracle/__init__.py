@@ -81,6 +81,8 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p, _p, _d, _p,
                                 ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(SolveInfo)]
+        L.orc_init_prices.restype = ctypes.c_int
+        L.orc_init_prices.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p, _p, _d, _p, _p]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -201,6 +203,22 @@ def solve(T, w, c, kind, eps, R, p0=None, tol_rel=1e-6, max_iter=500, mem=10, me
     if rc != 0:
         raise RuntimeError("oracle solve failed (%d)" % rc)
     return p, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+
+
+def init_prices(T, w, c, kind, eps, R):
+    """The paper's data-dependent starting prices (eq. e-initialization)."""
+    T = np.ascontiguousarray(T)
+    n, m = T.shape
+    w = np.ascontiguousarray(w, dtype=T.dtype)
+    c = np.ascontiguousarray(c, dtype=T.dtype)
+    kind = np.ascontiguousarray(kind, dtype=np.uint8)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    p = np.zeros(m)
+    rc = lib().orc_init_prices(n, m, _tdt(T), _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
+                               _ptr(R), _ptr(p))
+    if rc != 0:
+        raise RuntimeError("oracle init_prices failed (%d)" % rc)
+    return p
 
 
 def dense_allocation(n, m, jobs):

@@ -519,6 +519,53 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------- initial prices -- */
+
+/* Data-dependent starting prices (§5, "Initialization", eq. e-initialization):
+ * every job gets the same share x = R/n of the limits, or R/(kappa n) when
+ * kappa = 1^T R / n exceeds 1 (so that 1^T x = 1), and
+ *   p1 = (1/n) sum_i u_i'(a_i^T x) a_i,
+ * the gradient of U at R under that uniform allocation.  Derivatives:
+ * log, w/(t + eps); capped linear, w below the cap and 0 at or above it
+ * (the right derivative, one supergradient at the kink).
+ * Sums run per fixed chunk of rows, then in chunk order.
+ * Returns 0, or -1 on an allocation failure. */
+int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                    const uint8_t *kind, double eps, const double *R, double *p)
+{
+    double x[512];
+    double kappa = 0.0;
+    for (int j = 0; j < m; ++j) kappa += R[j] / (double)n;
+    const double scale = kappa > 1.0 ? 1.0 / (kappa * (double)n) : 1.0 / (double)n;
+    for (int j = 0; j < m; ++j) x[j] = R[j] * scale;
+    int64_t nchunks = (n + ORC_CHUNK - 1) / ORC_CHUNK;
+    double *part = (double *)calloc((size_t)(nchunks > 0 ? nchunks : 1) * (size_t)m,
+                                    sizeof(double));
+    if (!part) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < nchunks; ++ch) {
+        double *acc = part + ch * m;
+        int64_t lo = ch * ORC_CHUNK, hi = lo + ORC_CHUNK < n ? lo + ORC_CHUNK : n;
+        for (int64_t i = lo; i < hi; ++i) {
+            double t = 0.0;
+            for (int j = 0; j < m; ++j) t += tval(T, tdt, i * m + j) * x[j];
+            const double wi = pval(w, tdt, i);
+            double du;
+            if (kind[i] == ORC_LOG)
+                du = wi / (t + eps);
+            else
+                du = t < pval(c, tdt, i) ? wi : 0.0;
+            for (int j = 0; j < m; ++j) acc[j] += du * tval(T, tdt, i * m + j);
+        }
+    }
+    for (int j = 0; j < m; ++j) p[j] = 0.0;
+    for (int64_t ch = 0; ch < nchunks; ++ch)
+        for (int j = 0; j < m; ++j) p[j] += part[ch * m + j];
+    for (int j = 0; j < m; ++j) p[j] /= (double)n;
+    free(part);
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -345,3 +345,85 @@ def test_generator_determinism():
     full = synth.roofline_64(n=200000, m=8)
     assert rows[0].tobytes() == full.T[65530:65600].tobytes()
     assert rows[1].tobytes() == full.kind[65530:65600].tobytes()
+
+
+# ------------------------------------------------- §5 initialisation -----
+
+def _init_instance(seed, n=40, m=3, R_scale=0.2):
+    rng = np.random.default_rng(seed)
+    T = 0.2 + rng.random((n, m))
+    w = 0.5 + rng.random(n)
+    kind = (rng.random(n) < 0.5).astype(np.uint8)
+    R = R_scale * n / m * (0.5 + rng.random(m))
+    return T, w, kind, R
+
+
+def _phi(T, w, c, kind, eps, y):
+    """sum_i u_i(a_i^T y), numpy."""
+    t = T @ y
+    return float(np.sum(np.where(kind == LOG, w * np.log(t + eps), w * np.minimum(t, c))))
+
+
+def _caps_away_from_kinks(T, kind, y, rng):
+    # capped jobs strictly below or above their cap at the uniform allocation,
+    # so the finite differences below do not straddle a kink
+    t = T @ y
+    below = rng.random(len(t)) < 0.5
+    return np.where(kind == LOG, 0.0, np.where(below, t * 2.0 + 0.5, t * 0.5))
+
+
+def test_init_prices_gradient_of_utility_at_R():
+    """p1 = grad_R sum_i u_i(a_i^T R / n) when 1^T R / n <= 1, by central
+    differences (eq. e-initialization, the sensitivity reading of §5)."""
+    T, w, kind, R = _init_instance(3)
+    n, m = T.shape
+    assert R.sum() / n <= 1
+    c = _caps_away_from_kinks(T, kind, R / n, np.random.default_rng(4))
+    p = oracle.init_prices(T, w, c, kind, 1e-3, R)
+    for j in range(m):
+        h = 1e-5 * R[j]
+        e = np.zeros(m)
+        e[j] = h
+        fd = (_phi(T, w, c, kind, 1e-3, (R + e) / n) - _phi(T, w, c, kind, 1e-3, (R - e) / n)) / (2 * h)
+        assert p[j] == pytest.approx(fd, rel=1e-7)
+
+
+def test_init_prices_rescaled_share_when_limits_exceed_one_unit():
+    """kappa = 1^T R / n > 1: every job gets x = R / (kappa n) (1^T x = 1), so
+    p1 = (1/n) grad_y sum_i u_i(a_i^T y) at y = x, and scaling R up leaves it
+    unchanged."""
+    T, w, kind, R = _init_instance(5, R_scale=2.0)
+    n, m = T.shape
+    kappa = R.sum() / n
+    assert kappa > 1
+    x = R / (kappa * n)
+    c = _caps_away_from_kinks(T, kind, x, np.random.default_rng(6))
+    p = oracle.init_prices(T, w, c, kind, 1e-3, R)
+    for j in range(m):
+        h = 1e-6
+        e = np.zeros(m)
+        e[j] = h
+        fd = (_phi(T, w, c, kind, 1e-3, x + e) - _phi(T, w, c, kind, 1e-3, x - e)) / (2 * h) / n
+        assert p[j] == pytest.approx(fd, rel=1e-7)
+    assert np.allclose(oracle.init_prices(T, w, c, kind, 1e-3, 3.0 * R), p, rtol=1e-13)
+    # below kappa = 1 the share follows R itself: p1 changes when R is scaled
+    Rs = R / (2 * kappa)
+    assert not np.allclose(oracle.init_prices(T, w, c, kind, 1e-3, Rs),
+                           oracle.init_prices(T, w, c, kind, 1e-3, 0.5 * Rs))
+
+
+def test_init_prices_identical_jobs():
+    """n copies of one job: p1 = u'(a^T x) a."""
+    a = np.array([0.5, 2.0, 1.25])
+    n = 7
+    R = np.array([0.5, 1.0, 2.0])
+    T = np.tile(a, (n, 1))
+    x = R / n
+    t = a @ x
+    p = oracle.init_prices(T, np.full(n, 1.5), np.zeros(n), np.zeros(n, np.uint8), 1e-3, R)
+    assert np.allclose(p, 1.5 / (t + 1e-3) * a, rtol=1e-14)
+    # capped linear below its cap: slope w; at or above the cap: 0
+    p = oracle.init_prices(T, np.full(n, 1.5), np.full(n, t + 1), np.ones(n, np.uint8), 1e-3, R)
+    assert np.allclose(p, 1.5 * a, rtol=1e-14)
+    p = oracle.init_prices(T, np.full(n, 1.5), np.full(n, t / 2), np.ones(n, np.uint8), 1e-3, R)
+    assert np.all(p == 0)
