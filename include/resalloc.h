@@ -129,7 +129,9 @@ typedef struct {
     int32_t max_iter;        /* price updates (Algorithm 2, K^max)                   */
     int32_t lbfgs_mem;       /* L-BFGS memory (the paper's default is 10)            */
     int32_t method;          /* 0 = projected L-BFGS, 1 = projected subgradient     */
-    int32_t init;            /* 0 = p = 1, 1 = use p_inout as given                 */
+    int32_t init;            /* 0 = p = 1, 1 = use p_inout as given,
+                                2 = the paper's data-dependent prices (ra_init_prices;
+                                one extra pass, included in the reported time)      */
     int32_t use_graph;       /* 1 = replay one captured HIP graph per evaluation    */
     int32_t verbose;         /* 1 = one line per iteration on stderr                */
     int32_t max_evals;       /* > 0: stop after at most this many passes over T      */
@@ -159,6 +161,17 @@ typedef struct {
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
  * stall_evals = 0 (off), init_step = 0 (default step). */
 void ra_solve_opts_default(ra_solve_opts *opts);
+
+/* The paper's data-dependent starting prices (§5, "Initialization", eq.
+ * e-initialization): every job gets the uniform share x = R/n of the limits
+ * (R/(kappa n) when kappa = 1^T R / n > 1, so that 1^T x = 1), and
+ * p_out = (1/n) sum_i u_i'(a_i^T x) a_i, the sensitivity of the total
+ * utility to R under that allocation.  u' is w/(t + eps) for log jobs, and w
+ * below the cap, 0 at or above it, for capped-linear jobs (one supergradient
+ * at the kink).  One pass over T; x is rounded to the problem dtype.
+ * p_out: host, m doubles.  Blocks until the prices are on the host.
+ * Errors: RA_EINVAL, RA_EDEVICE, RA_ENUMERIC (non-finite result). */
+ra_status ra_init_prices(ra_ctx *ctx, const ra_problem *prob, double *p_out);
 
 /* Price discovery (§5, Algorithm 2). Every pass over T evaluates g and its
  * gradient at the new prices and, in the same pass, the lower bound U(X~) of

@@ -140,8 +140,10 @@ class Problem:
         return out
 
     def solve(self, p0=None, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, method=0, use_graph=True,
-              verbose=False, max_evals=0, stall_evals=0, init_step=0.0):
-        """Price discovery; returns (p, info dict, status)."""
+              verbose=False, max_evals=0, stall_evals=0, init_step=0.0, paper_init=False):
+        """Price discovery; returns (p, info dict, status).  paper_init starts
+        from the paper's data-dependent prices (ra_init_prices) unless p0 is
+        given."""
         o = ra_solve_opts_default()
         o.init_step = init_step
         o.max_evals = max_evals
@@ -156,6 +158,8 @@ class Problem:
         if p0 is not None:
             p = np.ascontiguousarray(np.asarray(p0, dtype=np.float64)).copy()
             o.init = 1
+        elif paper_init:
+            o.init = 2
         info = ra_solve_info()
         st = ra_solve(self.ctx.handle, self.handle, o, _hbuf(p), info)
         return p, {f: getattr(info, f) for f, _ in ra_solve_info._fields_}, st
@@ -166,6 +170,13 @@ class Problem:
         f = torch.empty(8 * self.m + 16, dtype=torch.float32, device=self.T.device)
         _capi.check(self.ctx.handle, _capi.lib().ra_features(self.ctx.handle, self.handle, _dptr(f)))
         return f
+
+    def init_prices(self):
+        """The paper's data-dependent starting prices (ra_init_prices)."""
+        p = np.zeros(self.m)
+        _capi.check(self.ctx.handle, _capi.lib().ra_init_prices(self.ctx.handle, self.handle,
+                                                                _hbuf(p)))
+        return p
 
     def predict_prices(self, mlp):
         """Starting prices predicted by the network (ra_predict_prices)."""
@@ -203,7 +214,8 @@ class Problem:
 
 
 def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lbfgs_mem=10,
-                method=0, use_graph=True, max_evals=0, stall_evals=0, init_step=0.0):
+                method=0, use_graph=True, max_evals=0, stall_evals=0, init_step=0.0,
+                paper_init=False):
     """Solve several Problems of one Context together (ra_batch_solve).
     Returns (list of price arrays, list of info dicts, status)."""
     if not problems:
@@ -226,6 +238,8 @@ def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lb
         for b, pb in enumerate(p0):
             p[offs[b]:offs[b + 1]] = np.asarray(pb, dtype=np.float64)
         o.init = 1
+    elif paper_init:
+        o.init = 2
     handles = (ctypes.c_void_p * B)(*[pr.handle for pr in problems])
     infos = (ra_solve_info * B)()
     tol = None

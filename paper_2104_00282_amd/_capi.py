@@ -63,6 +63,7 @@ PROTOTYPES = {
                              _vp]),
     "ra_features": (_st, [_vp, _vp, _vp]),
     "ra_predict_prices": (_st, [_vp, _vp, _vp, _vp]),
+    "ra_init_prices": (_st, [_vp, _vp, _vp]),
     "ra_mlp_create": (_st, [_vp, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "ra_mlp_destroy": (_st, [_vp]),
     "ra_mlp_num_params": (_st, [_vp, ctypes.POINTER(_i64)]),

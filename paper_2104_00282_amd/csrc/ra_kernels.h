@@ -61,6 +61,12 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
                        const void* prm, int64_t n, const void* prices, double eps,
                        double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1);
 
+// Data-dependent starting prices: partial [grid][m] gets, per block, the sums
+// of u_i'(a_i^T x) a_ij with x = prices->p (the uniform share of R).
+hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
+                       const void* prm, int64_t n, const void* prices, double eps,
+                       double* partial);
+
 // out[j] = sum_b partial[b * ncols + j], j < ncols (fixed order).  With flag
 // (host memory, fine-grained) and ticket (device counter, zero between
 // launches), the launch ends by setting *flag = 1 after every out[j] is

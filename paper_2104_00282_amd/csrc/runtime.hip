@@ -173,6 +173,37 @@ ra_status capture_graph(ra_problem* P)
     return RA_OK;
 }
 
+// The paper's data-dependent starting prices (§5, eq. e-initialization) into
+// p (host, m): the uniform share x = R/n (R/(kappa n) when kappa = 1^T R/n
+// exceeds 1) goes to the device as the price block's p, one pass sums
+// u_i'(a_i^T x) a_i, and the column sums are divided by n.
+ra_status init_prices(ra_problem* P, double* p)
+{
+    ra_ctx* ctx = P->ctx;
+    hipStream_t st = ctx->stream;
+    const int m = P->m;
+    const double n = (double)P->n;
+    double kappa = 0.0;
+    for (int j = 0; j < m; ++j) kappa += P->R[j] / n;
+    const double scale = kappa > 1.0 ? 1.0 / (kappa * n) : 1.0 / n;
+    std::vector<double> x(m);
+    for (int j = 0; j < m; ++j) x[j] = P->R[j] * scale;
+    (void)fill_prices(P, x.data(), nullptr);
+    RA_HIP(ctx, hipMemcpyAsync(P->pblock, P->h_pblock, price_block_bytes(P->dt),
+                               hipMemcpyHostToDevice, st));
+    RA_HIP(ctx, ra::launch_init(P->dt, m, P->vec_ok, P->grid, st, P->T, P->prm, P->n, P->pblock,
+                                P->eps, P->partial));
+    RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial, P->grid, m, P->dout));
+    RA_HIP(ctx, hipMemcpyAsync(P->h_out, P->dout, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+    RA_HIP(ctx, hipStreamSynchronize(st));
+    for (int j = 0; j < m; ++j) {
+        p[j] = P->h_out[j] / n;
+        if (!std::isfinite(p[j]) || p[j] < 0.0)
+            return fail(ctx, RA_ENUMERIC, "initial price %d is %g", j, p[j]);
+    }
+    return RA_OK;
+}
+
 // Wait for the completion flag of a signalled pass.  The stream is queried
 // now and then, so that a failed or finished stream without the flag ends
 // the wait with an error instead of spinning.
@@ -468,7 +499,7 @@ static bool valid_opts(const ra_solve_opts& o)
 {
     return o.tol_rel >= 0.0 && o.max_iter >= 0 && o.max_evals >= 0 && o.stall_evals >= 0 &&
            o.lbfgs_mem >= 1 && o.lbfgs_mem <= 64 && (o.method == 0 || o.method == 1) &&
-           (o.init == 0 || o.init == 1) && o.init_step >= 0.0 && o.init_step <= 10.0;
+           (o.init >= 0 && o.init <= 2) && o.init_step >= 0.0 && o.init_step <= 10.0;
 }
 
 ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opts,
@@ -495,6 +526,10 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
     const auto t0 = std::chrono::steady_clock::now();
     // the NULL stream cannot be captured
     const bool graph = o.use_graph && ctx->stream != nullptr;
+    if (o.init == 2) {
+        ra_status st = init_prices(P, p.data());
+        if (st != RA_OK) return st;
+    }
 
     ra::PriceLoop L(m, P->n, P->R.data(), o, p.data());
     std::vector<double> pe, rr;
@@ -533,6 +568,15 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
         info->warm_evals = 0;
     }
     return conv ? RA_OK : RA_ENOTCONV;
+}
+
+ra_status ra_init_prices(ra_ctx* ctx, const ra_problem* prob, double* p_out)
+{
+    if (!ctx || ctx->closed) return RA_EINVAL;
+    if (!prob || prob->ctx != ctx) return fail(ctx, RA_EINVAL, "problem is NULL or from another context");
+    if (!p_out) return fail(ctx, RA_EINVAL, "p_out is required");
+    RA_HIP(ctx, hipSetDevice(ctx->dev));
+    return init_prices(const_cast<ra_problem*>(prob), p_out);
 }
 
 ra_status ra_predict_prices(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp, double* p_out)
@@ -991,6 +1035,10 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
                     return fail(ctx, RA_EINVAL, "p_inout of problem %d must be >= 0 and finite", b);
                 p0[j] = v;
             }
+        if (o.init == 2) {
+            ra_status st = init_prices(P[b], p0.data());
+            if (st != RA_OK) return st;
+        }
         loops.emplace_back(P[b]->m, P[b]->n, P[b]->R.data(), ob, p0.data());
     }
 

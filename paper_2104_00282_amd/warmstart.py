@@ -104,7 +104,8 @@ LEVELS = (1e-3, 1e-4, "floor")
 
 def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters=300,
              stall_evals=100, max_iter=500, fallback_window=5, levels=LEVELS, log=None):
-    """Cold start (p = 1) vs learned warm start on fresh instances, to each
+    """Cold start (p = 1), the paper's data-dependent start and the learned
+    warm start (and optionally a constant predictor) on fresh instances, to each
     relative-gap level of `levels` separately ("floor" = max(1e-6, 1.5 x the
     smallest gap a long reference run certifies), the tightest target the
     column-scaling recovery allows). Returns a list of per-instance dicts
@@ -130,6 +131,8 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
                 arms["warm"] = pr.solve_learned(net, tol_rel=tol, max_iter=max_iter,
                                                 stall_evals=stall_evals,
                                                 fallback_window=fallback_window)[1]
+                arms["paper"] = pr.solve(tol_rel=tol, max_iter=max_iter, stall_evals=stall_evals,
+                                         paper_init=True)[1]
                 if const_net is not None:
                     arms["const"] = pr.solve_learned(const_net, tol_rel=tol, max_iter=max_iter,
                                                      stall_evals=stall_evals,
@@ -154,7 +157,7 @@ def summarize(rows, levels=LEVELS):
             return np.array([r[key][arm][k] for r in rows], dtype=np.float64)
 
         lvl = {}
-        for arm in ("cold", "warm", "const"):
+        for arm in ("cold", "warm", "paper", "const"):
             if arm not in rows[0][key]:
                 continue
             lvl[arm] = {
@@ -168,6 +171,8 @@ def summarize(rows, levels=LEVELS):
         lvl["speedup_total"] = lvl["cold"]["seconds_total"] / lvl["warm"]["seconds_total"]
         lvl["speedup_median"] = float(np.median(col("cold", "seconds") / col("warm", "seconds")))
         lvl["fallback_rate"] = lvl["warm"]["restarted"] / len(rows)
+        lvl["paper_speedup_total"] = lvl["cold"]["seconds_total"] / lvl["paper"]["seconds_total"]
+        lvl["warm_vs_paper_total"] = lvl["paper"]["seconds_total"] / lvl["warm"]["seconds_total"]
         if "const" in lvl:
             lvl["const_speedup_total"] = (lvl["cold"]["seconds_total"] /
                                           lvl["const"]["seconds_total"])

@@ -119,3 +119,34 @@ def test_fused_certificate_matches_separate_bound(ctx, torch, m):
         assert info["g"] == d["g"]
         assert info["U_lb"] == pytest.approx(d["lower_bound"], rel=1e-10)
     prob.close()
+
+
+@pytest.mark.parametrize("m,dtype,n", [(64, np.float32, 100003), (16, np.float32, 4097),
+                                       (4, np.float32, 1317), (5, np.float32, 3001),
+                                       (7, np.float64, 2049)])
+def test_init_prices_match_oracle(ctx, torch, m, dtype, n):
+    """ra_init_prices (eq. e-initialization) against the oracle, vectorised
+    and generic kernels, ragged n; and kappa > 1 (limits above one unit per
+    job)."""
+    I = synth.random_small(n, m, seed=60 + m, dtype=dtype)
+    prob = _problem(ctx, torch, I)
+    p = prob.init_prices()
+    ref = oracle.init_prices(I.T, I.w, I.c, I.kind, I.eps, I.R)
+    assert np.allclose(p, ref, rtol=1e-5 if dtype == np.float32 else 1e-12)
+    prob.close()
+    I.R[:] = 3.0 * n / m  # kappa = 3
+    prob = _problem(ctx, torch, I)
+    assert np.allclose(prob.init_prices(), oracle.init_prices(I.T, I.w, I.c, I.kind, I.eps, I.R),
+                       rtol=1e-5 if dtype == np.float32 else 1e-12)
+    prob.close()
+
+
+def test_paper_init_solve(ctx, torch):
+    """A solve started from the paper's prices reaches the same optimum."""
+    I = synth.random_small(50000, 8, seed=47, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    p1, i1, _ = prob.solve(tol_rel=1e-4, max_iter=200)
+    p2, i2, _ = prob.solve(tol_rel=1e-4, max_iter=200, paper_init=True)
+    assert i1["converged"] == 1 and i2["converged"] == 1
+    assert i2["g"] == pytest.approx(i1["g"], rel=2e-4)
+    prob.close()
