@@ -228,6 +228,83 @@ def bench_warmstart(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_solves(args):
+    """Time to a relative-gap target on the single-instance configurations:
+    small-log (n = 1e3, m = 4, FP64, target max(1e-8, 1.5 floor)), mixed-16
+    (n = 1e6, m = 16, FP32) and roofline-64 (n = 1e7, m = 64, FP32), both
+    max(1e-6, 1.5 floor); the floor is the best gap of a long reference run.
+    GPU: cold start (p = 1) and the paper's data-dependent start (its extra
+    pass included), median of 3 runs. CPU: the FP64 oracle's own solve from
+    p = 1 to the same target, on the two smaller configurations."""
+    import torch
+    import oracle
+    import synth
+    import paper_2104_00282_amd as ra
+
+    ctx = ra.Context(0)
+    dev = torch.device("cuda:0")
+    rows = {}
+    for name, gen, tol_min, cpu in (("small-log", synth.small_log, 1e-8, True),
+                                    ("mixed-16", synth.mixed_16, 1e-6, True),
+                                    ("roofline-64", synth.roofline_64, 1e-6, False)):
+        log("%s: generating" % name)
+        I = gen()
+        T = torch.from_numpy(I.T).to(dev)
+        w = torch.from_numpy(I.w).to(dev)
+        c = torch.from_numpy(I.c).to(dev)
+        kind = torch.from_numpy(I.kind).to(dev)
+        prob = ra.Problem(ctx, T, w, c, kind, I.R, I.eps, validate=False)
+        _, ref, _ = prob.solve(tol_rel=0.0, max_iter=args.floor_iters, stall_evals=args.stall_evals)
+        floor = ref["rel_gap"]
+        target = max(tol_min, 1.5 * floor)
+        prob.solve(max_iter=0)  # graph capture outside the timings
+        row = {"n": I.n, "m": I.m, "dtype": "f64" if I.T.dtype == np.float64 else "f32",
+               "floor": floor, "target": target}
+        for arm, kw in (("gpu_cold", {}), ("gpu_paper_init", {"paper_init": True})):
+            runs = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info, _ = prob.solve(tol_rel=target, max_iter=2 * args.floor_iters,
+                                        stall_evals=args.stall_evals, **kw)
+                runs.append((time.perf_counter() - t0, info))
+            runs.sort(key=lambda r: r[0])
+            sec, info = runs[1]
+            row[arm] = {"seconds": sec, "dual_evals": info["dual_evals"],
+                        "iters": info["iters"], "rel_gap": info["rel_gap"],
+                        "reached": bool(info["converged"])}
+        if cpu:
+            log("%s: oracle solve" % name)
+            t0 = time.perf_counter()
+            _, oi = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=target,
+                                 max_iter=2 * args.floor_iters)
+            row["cpu_oracle"] = {"seconds": time.perf_counter() - t0, "evals": oi["evals"],
+                                 "rel_gap": oi["rel_gap"], "reached": oi["rel_gap"] <= target,
+                                 "cores": oracle.num_threads()}
+            row["gpu_vs_cpu_oracle"] = row["cpu_oracle"]["seconds"] / row["gpu_cold"]["seconds"]
+        rows[name] = row
+        log("%s: %s" % (name, json.dumps(row)))
+        prob.close()
+        del T, w, c, kind
+    out = {
+        "metric": "time to relative-gap target per configuration (GPU cold start)",
+        "value": rows["mixed-16"]["gpu_cold"]["seconds"],
+        "unit": "s (mixed-16)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "small-log, mixed-16, roofline-64 single-instance solves",
+                   "targets": "max(tol, 1.5 x floor), tol 1e-8 (small-log) / 1e-6, floor from a "
+                              "%d-iteration reference run" % args.floor_iters,
+                   "stop": "target reached, or no 0.1%% gap improvement within %d evaluations"
+                           % args.stall_evals},
+        "solves": rows,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def synth_seed(offset):
     import synth
     return synth.BASE_SEED + offset
@@ -242,9 +319,12 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale the HBM counters")
-    ap.add_argument("--workload", choices=["roofline", "batched", "warmstart"], default="roofline",
+    ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves"],
+                    default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
-                         "instance's gap target, batched solver vs a per-instance loop")
+                         "instance's gap target, batched solver vs a per-instance loop; "
+                         "warmstart: learned start vs cold start; solves: time to gap on the "
+                         "single-instance configurations")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--floor-iters", type=int, default=300)
     ap.add_argument("--stall-evals", type=int, default=100)
@@ -259,11 +339,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload in ("batched", "warmstart"):
+    if args.workload in ("batched", "warmstart", "solves"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        (bench_batched if args.workload == "batched" else bench_warmstart)(args)
+        {"batched": bench_batched, "warmstart": bench_warmstart,
+         "solves": bench_solves}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -338,6 +419,26 @@ def main():
             "launches": launches,
         },
     }
+    # the same evaluation without the certificate (steps a1-a7 only), at p = 1
+    # and at the timed prices; per-launch HIP-event times
+    fixed = {}
+    for label, pf in (("p=1", np.ones(m)), ("timed prices", p2)):
+        ts = []
+        for k in range(23):
+            ra.ra_set_kernel_timing(ctx.handle, True)
+            prob.dual_eval(pf)
+            kk, ll = ra.ra_get_kernel_timing(ctx.handle)
+            ra.ra_set_kernel_timing(ctx.handle, False)
+            if k >= 3:
+                ts.append(kk / ll)
+        fixed[label] = {"median_ms": float(np.median(ts)), "min_ms": float(np.min(ts)),
+                        "GB/s_at_median": bytes_per_launch / (np.median(ts) / 1e3) / 1e9}
+    out["config"]["gradient_only_kernel"] = fixed
+    # attainable: a plain streaming read of T and the packed utilities' size
+    read_ms = ra.ra_stream_read_ms(ctx.handle, T.data_ptr(), n * m * 4, 20)
+    read_gbs = (n * m * 4) / (read_ms / 1e3) / 1e9
+    out["roofline"]["read_ceiling"] = {"GB/s": read_gbs, "frac_of_peak": read_gbs / HBM_PEAK_GBS,
+                                       "kernel_frac_of_ceiling": achieved / read_gbs}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p2)

@@ -283,6 +283,13 @@ ra_status ra_solve_learned(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp,
  * RA_EDEVICE. */
 ra_status ra_predict_prices(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp, double *p_out);
 
+/* Measurement aid: the mean time (ms) of one plain streaming read of `bytes`
+ * bytes at buf (device, 16-byte aligned, bytes a multiple of 16), over `reps`
+ * reads after 3 untimed ones, timed with HIP events on the context's stream.
+ * Gives the attainable read bandwidth that the dual kernel's HBM roofline
+ * fraction can be compared with.  Errors: RA_EINVAL, RA_EDEVICE. */
+ra_status ra_stream_read_ms(ra_ctx *ctx, const void *buf, int64_t bytes, int32_t reps, double *ms);
+
 /* Kernel timing on the context's stream (for benchmarks and profiling).
  * enable = 1 brackets every launch of the dual kernel with a pair of HIP
  * events on the context's stream and accumulates the elapsed times; while it

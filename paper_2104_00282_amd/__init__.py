@@ -19,13 +19,14 @@ from ._capi import (RA_EDEVICE, RA_EINVAL, RA_ENOMEM, RA_ENOTCONV, RA_ENUMERIC, 
                     ra_destroy, ra_dual_eval, ra_get_allocation, ra_last_error, ra_problem_create,
                     ra_problem_destroy, ra_solve, ra_solve_info, ra_solve_opts,
                     ra_solve_opts_default, ra_status_string, ra_set_kernel_timing,
-                    ra_get_kernel_timing, ra_batch_solve)
+                    ra_get_kernel_timing, ra_batch_solve, ra_stream_read_ms)
 
 __all__ = [
     "Context", "Problem", "RAError", "ra_create", "ra_destroy", "ra_status_string",
     "ra_last_error", "ra_problem_create", "ra_problem_destroy", "ra_dual_eval",
     "ra_solve_opts_default", "ra_solve", "ra_get_allocation", "ra_solve_opts", "ra_solve_info",
     "ra_set_kernel_timing", "ra_get_kernel_timing", "ra_batch_solve", "batch_solve", "MLP",
+    "ra_stream_read_ms",
 ]
 
 

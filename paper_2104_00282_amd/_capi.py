@@ -64,6 +64,7 @@ PROTOTYPES = {
     "ra_features": (_st, [_vp, _vp, _vp]),
     "ra_predict_prices": (_st, [_vp, _vp, _vp, _vp]),
     "ra_init_prices": (_st, [_vp, _vp, _vp]),
+    "ra_stream_read_ms": (_st, [_vp, _vp, _i64, _i32, ctypes.POINTER(_d)]),
     "ra_mlp_create": (_st, [_vp, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "ra_mlp_destroy": (_st, [_vp]),
     "ra_mlp_num_params": (_st, [_vp, ctypes.POINTER(_i64)]),
@@ -183,6 +184,15 @@ def ra_get_kernel_timing(ctx):
     if st != RA_OK:
         raise RAError(st, ra_last_error(ctx))
     return ms.value, k.value
+
+
+def ra_stream_read_ms(ctx, ptr, nbytes, reps=20):
+    """Mean ms of one plain streaming read of nbytes at device address ptr."""
+    ms = ctypes.c_double()
+    st = lib().ra_stream_read_ms(ctx, ptr, nbytes, reps, ctypes.byref(ms))
+    if st != RA_OK:
+        raise RAError(st, ra_last_error(ctx))
+    return ms.value
 
 
 def ra_batch_solve(ctx, B, probs, opts, tol_each, p_inout, infos):
