@@ -222,6 +222,23 @@ __device__ __forceinline__ float4 stream_load(const float4* p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// The same loads through pointers known to be global (the batched kernel
+// reads its problems' base pointers from memory, which would otherwise give
+// flat loads, and flat loads also count against the LDS/scalar counter).
+typedef __attribute__((address_space(1))) const f32x4 global_f32x4;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const f32x2 global_f32x2;
+__device__ __forceinline__ float4 stream_load_global(const float4* p)
+{
+    const f32x4 v = __builtin_nontemporal_load((global_f32x4*)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 load_global(const float2* p)
+{
+    const f32x2 v = *(global_f32x2*)p;
+    return make_float2(v.x, v.y);
+}
+
 template <int M>
 struct RegRow {
     float v[M];
@@ -600,66 +617,66 @@ __global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
 
 // ------------------------------------------------------------------------
 // Batched dual kernel: many FP32 problems with m in {4, 8, 16, 32} evaluated
-// in one persistent launch per price iteration.  The host lays the active
-// problems' 64-job tiles end to end and gives each wavefront a contiguous
-// chunk of that tile space, balanced by bytes.  A wave keeps FP64
-// accumulators for the problem it is in and writes them to its next partial
-// slot whenever it crosses into another problem, so the slots of one problem
-// are contiguous and are summed in a fixed order by k_batch_reduce.
+// in one persistent launch per price iteration.  A batched tile is 8 KiB of
+// T whatever m (batch_rows(m) = 2048/m rows: 512 at m = 4, 64 at m = 32,
+// i.e. 32/m jobs per lane), so every wave streams the same bytes per step.
+// The host lays the active problems' tiles end to end and gives each
+// wavefront a contiguous chunk of that tile space, balanced by bytes.  The
+// next tile (possibly of the next problem) is loaded into registers while
+// the current one is solved from LDS.  A wave keeps FP64 accumulators for
+// the problem it is in and writes them to its next partial slot whenever it
+// crosses into another problem, so the slots of one problem are contiguous
+// and are summed in a fixed order by k_batch_reduce.
 // ------------------------------------------------------------------------
+constexpr int BATCH_LDS_WAVE = 3072;  // max over m of batch_rows(m) x padded stride (m = 8)
+
 template <int M>
-__device__ __forceinline__ void batch_tile(const BatchItem& it, int64_t tile, float* tl,
-                                           float* hist, const float* __restrict__ P,
-                                           const float* __restrict__ IP,
-                                           const float* __restrict__ Qp,
-                                           const float* __restrict__ IQ, const float* ptab,
-                                           const float* qtab, const float* stab,
-                                           const float* sctab, bool prev, int lane,
-                                           double& racc, double& vacc, double& uacc,
-                                           double& duacc)
+__device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, const float* tl,
+                                              const float2 (&wc)[8], float* hist,
+                                              const float* __restrict__ P,
+                                              const float* __restrict__ IP,
+                                              const float* __restrict__ Qp,
+                                              const float* __restrict__ IQ, const float* ptab,
+                                              const float* qtab, const float* stab,
+                                              const float* sctab, bool prev, int lane,
+                                              double& racc, double& vacc, double& uacc,
+                                              double& duacc)
 {
     constexpr int Q = M / 4;
     constexpr int S = M + ((Q & 1) ? 0 : 4);
-    const int64_t row0 = tile * 64;
-    const int rows = (int)((it.n - row0) < 64 ? (it.n - row0) : 64);
-    const float4* src = reinterpret_cast<const float4*>(it.T + row0 * M);
-    const int valid = rows * Q;
+    constexpr int JPL = BATCH_TILE_FLOATS / M / 64;  // jobs per lane
+    static_assert(JPL >= 1 && JPL <= 8, "batched tile shape");
+    static_assert((BATCH_TILE_FLOATS / M) * S <= BATCH_LDS_WAVE, "batched LDS tile");
+    const float eps = it.eps;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-        const int ch = lane + 64 * k;
-        if (ch < valid) {
-            const int r = ch / Q, q = ch % Q;
-            *reinterpret_cast<float4*>(tl + r * S + 4 * q) = stream_load(src + ch);
-        }
-    }
-    const float2 wc = (lane < rows) ? it.prm[row0 + lane] : make_float2(1.f, -1.f);
-    wave_sync();
-    if (lane < rows) {
-        RegRow<M> row;
-        row.lds = tl + lane * S;
+    for (int k = 0; k < JPL; ++k) {
+        const int r = 64 * k + lane;
+        if (r < rows) {
+            RegRow<M> row;
+            row.lds = tl + r * S;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
-            row.v[4 * q + 0] = v.x;
-            row.v[4 * q + 1] = v.y;
-            row.v[4 * q + 2] = v.z;
-            row.v[4 * q + 3] = v.w;
-        }
-        const bool caplin = wc.y >= 0.f;
-        const float eps = it.eps;
-        Job<float> J;
-        solve_job<float, M>(row, M, P, IP, ptab, wc.x, wc.y, caplin, eps, J);
-        if (J.jlo >= 0) atomicAdd(&hist[J.jlo], J.xlo);
-        if (J.jhi >= 0) atomicAdd(&hist[J.jhi], J.xhi);
-        vacc += (double)J.v;
-        if (prev) {
-            Job<float> K;
-            solve_job<float, M>(row, M, Qp, IQ, qtab, wc.x, wc.y, caplin, eps, K);
-            float u, loss;
-            scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab, u,
-                           loss);
-            uacc += (double)u;
-            duacc += (double)loss;
+            for (int q = 0; q < Q; ++q) {
+                const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
+                row.v[4 * q + 0] = v.x;
+                row.v[4 * q + 1] = v.y;
+                row.v[4 * q + 2] = v.z;
+                row.v[4 * q + 3] = v.w;
+            }
+            const bool caplin = wc[k].y >= 0.f;
+            Job<float> J;
+            solve_job<float, M>(row, M, P, IP, ptab, wc[k].x, wc[k].y, caplin, eps, J);
+            if (J.jlo >= 0) atomicAdd(&hist[J.jlo], J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[J.jhi], J.xhi);
+            vacc += (double)J.v;
+            if (prev) {
+                Job<float> K;
+                solve_job<float, M>(row, M, Qp, IQ, qtab, wc[k].x, wc[k].y, caplin, eps, K);
+                float u, loss;
+                scaled_utility(caplin, wc[k].x, wc[k].y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab,
+                               sctab, u, loss);
+                uacc += (double)u;
+                duacc += (double)loss;
+            }
         }
     }
     wave_sync();
@@ -676,12 +693,14 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
                                                     const int* __restrict__ segbase,
                                                     double* __restrict__ partial)
 {
-    constexpr int SMAX = BATCH_MAX_M + 4;
-    __shared__ __attribute__((aligned(16))) float tile[4][64 * SMAX];
+    __shared__ __attribute__((aligned(16))) float tile[4][BATCH_LDS_WAVE];
     __shared__ float hist[4][BATCH_MAX_M];
     __shared__ float tabs[4][4][BATCH_MAX_M];
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    // the wave index is uniform: saying so keeps the tile bookkeeping, the
+    // problem records and the price reads in scalar registers and scalar
+    // loads, which do not wait behind the prefetched tile's vector loads
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int w = blockIdx.x * 4 + wv;
     const int t0 = chunk[w], t1 = chunk[w + 1];
     float* tl = tile[wv];
@@ -690,9 +709,35 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
     wave_sync();
     if (t0 >= t1) return;
 
-    // problem of the first tile: the last item with tile0 <= t0
-    int a = 0;
-    while (items[a + 1].tile0 <= t0) ++a;  // items[n_active].tile0 = total tiles
+    // the tile in flight: 8 KiB of T (512 float4, 8 per lane) and the (w, c)
+    // of up to 8 jobs per lane; `an` is the problem of the last tile loaded
+    // (items[A].tile0 is the total tile count, so the scans stop)
+    float4 pre[8];
+    float2 wcn[8];
+    int an = 0, nrows = 0;
+    auto load = [&](int t) {
+        while (items[an + 1].tile0 <= t) ++an;
+        const BatchItem& nx = items[an];
+        const int m = nx.m;
+        const int tr = BATCH_TILE_FLOATS / m;
+        const int64_t row0 = (int64_t)(t - nx.tile0) * tr;
+        const int64_t left = nx.n - row0;
+        const int rows = left < tr ? (int)left : tr;
+        const float4* src = reinterpret_cast<const float4*>(nx.T + row0 * m);
+        const int valid = rows * (m / 4);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ch = lane + 64 * k;
+            pre[k] = (ch < valid) ? stream_load_global(src + ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int r = 64 * k + lane;
+            wcn[k] = (r < rows) ? load_global(nx.prm + row0 + r) : make_float2(1.f, -1.f);
+        }
+        nrows = rows;
+    };
+
     int slot = segbase[w];
     int cur = -1;
     BatchItem it;
@@ -714,8 +759,11 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
         ++slot;
         racc = vacc = uacc = duacc = 0.0;
     };
+
+    load(t0);
     for (int t = t0; t < t1; ++t) {
-        while (items[a + 1].tile0 <= t) ++a;
+        const int a = an;
+        const int rows = nrows;
         if (a != cur) {
             if (cur >= 0) flush();
             cur = a;
@@ -731,49 +779,86 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
                 tabs[wv][2][lane] = pr[4 * BATCH_MAX_M + lane];
                 tabs[wv][3][lane] = pr[5 * BATCH_MAX_M + lane];
             }
-            wave_sync();
         }
-        const int64_t lt = t - it.tile0;
+        // stage the tile in LDS: chunk ch of 16 bytes is row ch / Q, quad ch % Q
+        const int m = it.m;
+        const int Q = m >> 2;
+        const int lq = m == 4 ? 0 : m == 8 ? 1 : m == 16 ? 2 : 3;
+        const int S = m + ((Q & 1) ? 0 : 4);
+        const int valid = rows * Q;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int ch = lane + 64 * k;
+            if (ch < valid)
+                *reinterpret_cast<float4*>(tl + (ch >> lq) * S + 4 * (ch & (Q - 1))) = pre[k];
+        }
+        float2 wc[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wc[k] = wcn[k];
+        wave_sync();
+        if (t + 1 < t1) load(t + 1);
         const bool prev = it.has_prev != 0;
         const float* pt = tabs[wv][0];
         const float* qt = tabs[wv][1];
         const float* st = tabs[wv][2];
         const float* sct = tabs[wv][3];
-        switch (it.m) {
+        switch (m) {
         case 4:
-            batch_tile<4>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
-                          uacc, duacc);
+            batch_compute<4>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+                             vacc, uacc, duacc);
             break;
         case 8:
-            batch_tile<8>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
-                          uacc, duacc);
+            batch_compute<8>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+                             vacc, uacc, duacc);
             break;
         case 16:
-            batch_tile<16>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
-                           uacc, duacc);
+            batch_compute<16>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+                              racc, vacc, uacc, duacc);
             break;
         default:
-            batch_tile<32>(it, lt, tl, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc, vacc,
-                           uacc, duacc);
+            batch_compute<32>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+                              racc, vacc, uacc, duacc);
             break;
         }
     }
     flush();
 }
 
-// out[a][c] = sum of partial slots [seg[2a], seg[2a+1]] of column c.
+// out[a][c] = sum of partial slots [seg[2a], seg[2a+1]] of column c, for the
+// active problems a < header[0] (blocks stride over them).  With `flag`, out
+// is host memory the host polls: one lane per block writes the block's rows
+// (staged in LDS) and makes them visible system-wide, then takes a ticket;
+// the block with the last ticket resets the counter and raises *flag = 1.
 __global__ void __launch_bounds__(64) k_batch_reduce(const double* __restrict__ partial,
                                                      const int* __restrict__ seg,
                                                      const int* __restrict__ header,
-                                                     double* __restrict__ out)
+                                                     double* __restrict__ out,
+                                                     unsigned* __restrict__ ticket,
+                                                     unsigned* __restrict__ flag)
 {
-    const int a = blockIdx.x;
-    if (a >= header[0]) return;
+    __shared__ double row[BATCH_COLS];
     const int c = threadIdx.x;
-    if (c >= BATCH_COLS) return;
-    double s = 0.0;
-    for (int k = seg[2 * a]; k <= seg[2 * a + 1]; ++k) s += partial[(int64_t)k * BATCH_COLS + c];
-    out[(int64_t)a * BATCH_COLS + c] = s;
+    const int A = header[0];
+    for (int a = blockIdx.x; a < A; a += gridDim.x) {
+        if (c < BATCH_COLS) {
+            double s = 0.0;
+            for (int k = seg[2 * a]; k <= seg[2 * a + 1]; ++k)
+                s += partial[(int64_t)k * BATCH_COLS + c];
+            row[c] = s;
+        }
+        __syncthreads();
+        if (c == 0)
+            for (int k = 0; k < BATCH_COLS; ++k) out[(int64_t)a * BATCH_COLS + k] = row[k];
+        __syncthreads();
+    }
+    if (flag && c == 0) {
+        __threadfence_system();
+        if (atomicAdd(ticket, 1u) == (unsigned)gridDim.x - 1u) {
+            atomicExch(ticket, 0u);
+            __threadfence_system();
+            __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -1035,10 +1120,12 @@ int batch_blocks_per_cu()
 
 hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
                         const float* prices, const int* chunk, const int* segbase,
-                        const int* seg, const int* header, double* partial, double* out)
+                        const int* seg, const int* header, double* partial, double* out,
+                        unsigned* ticket, unsigned* flag)
 {
     k_dual_batch<<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
-    k_batch_reduce<<<max_items, 64, 0, st>>>(partial, seg, header, out);
+    const int rgrid = max_items < 64 ? max_items : 64;
+    k_batch_reduce<<<rgrid, 64, 0, st>>>(partial, seg, header, out, ticket, flag);
     return hipGetLastError();
 }
 

@@ -30,6 +30,9 @@ inline int partial_cols(int m) { return m + 3; }
 // items[n_active] is a sentinel whose tile0 is the total tile count.
 constexpr int BATCH_MAX_M = 32;
 constexpr int BATCH_COLS = BATCH_MAX_M + 3;  // r_j (padded), net utility, U(X~), loss
+// A batched tile is BATCH_TILE_FLOATS floats of T: batch_rows(m) jobs.
+constexpr int BATCH_TILE_FLOATS = 2048;
+__host__ __device__ inline int batch_rows(int m) { return BATCH_TILE_FLOATS / m; }
 struct BatchItem {
     const float* T;      // n x m row-major, 16-byte aligned
     const float2* prm;   // packed (w, c) per job
@@ -46,9 +49,12 @@ struct BatchItem {
 // prices: per item 6 x BATCH_MAX_M floats (p, 1/p, q, 1/q, s, 1 - s);
 // header[0] = number of active items.
 int batch_blocks_per_cu();
+// With flag (host, fine-grained) and ticket (device counter, zero between
+// launches), out is host memory and the launch ends by setting *flag = 1.
 hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
                         const float* prices, const int* chunk, const int* segbase,
-                        const int* seg, const int* header, double* partial, double* out);
+                        const int* seg, const int* header, double* partial, double* out,
+                        unsigned* ticket = nullptr, unsigned* flag = nullptr);
 
 // Number of blocks one dual-kernel launch uses for n jobs with m resources.
 int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);

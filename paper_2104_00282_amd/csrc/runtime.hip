@@ -207,15 +207,14 @@ ra_status init_prices(ra_problem* P, double* p)
 // Wait for the completion flag of a signalled pass.  The stream is queried
 // now and then, so that a failed or finished stream without the flag ends
 // the wait with an error instead of spinning.
-ra_status wait_flag(ra_problem* P)
+ra_status wait_flag(ra_ctx* ctx, unsigned* flag)
 {
-    ra_ctx* ctx = P->ctx;
     for (uint64_t k = 1;; ++k) {
-        if (__atomic_load_n(P->h_flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
         if ((k & 4095) == 0) {
             const hipError_t e = hipStreamQuery(ctx->stream);
             if (e == hipSuccess) {
-                if (__atomic_load_n(P->h_flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
+                if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
                 return fail(ctx, RA_EDEVICE, "evaluation finished without its completion flag");
             }
             if (e != hipErrorNotReady)
@@ -245,7 +244,7 @@ ra_status run_pass(ra_problem* P, const std::vector<double>& p, const ra::Point*
         ra_status st = enqueue_eval(P, false, nullptr, nullptr, nullptr, true);
         if (st != RA_OK) return st;
     }
-    ra_status ws = wait_flag(P);
+    ra_status ws = wait_flag(ctx, P->h_flag);
     if (ws != RA_OK) return ws;
     if (collect_timing(ctx) != RA_OK) return RA_EDEVICE;
     const double* o = P->h_out;
@@ -755,18 +754,23 @@ struct BatchWs {
     char* dtab = nullptr;
     char* htab = nullptr;
     double* partial = nullptr;
-    double* dout = nullptr;
-    double* hout = nullptr;
+    bool used = false;
+    hipStream_t st_sync = nullptr;
+    double* hout = nullptr;     // fine-grained host memory: B rows of results, then the flag
+    unsigned* hflag = nullptr;
+    unsigned* ticket = nullptr;  // device block counter of the reduction
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_grid = 0;
     ~BatchWs()
     {
+        // launches that use these buffers must have finished
+        if (used) (void)hipStreamSynchronize(st_sync);
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipFree(dtab);
         (void)hipFree(partial);
-        (void)hipFree(dout);
+        (void)hipFree(ticket);
         if (htab) (void)hipHostFree(htab);
         if (hout) (void)hipHostFree(hout);
     }
@@ -780,6 +784,8 @@ struct BatchWs {
 
 ra_status batch_alloc(ra_ctx* ctx, BatchWs& ws, int B, int Wmax)
 {
+    ws.used = true;
+    ws.st_sync = ctx->stream;
     ws.B = B;
     ws.Wmax = Wmax;
     size_t o = 0;
@@ -801,9 +807,12 @@ ra_status batch_alloc(ra_ctx* ctx, BatchWs& ws, int B, int Wmax)
     std::memset(ws.htab, 0, ws.tab_bytes);
     RA_HIP(ctx, hipMalloc(&ws.partial,
                           sizeof(double) * ra::BATCH_COLS * (size_t)(Wmax + B)));
-    RA_HIP(ctx, hipMalloc(&ws.dout, sizeof(double) * ra::BATCH_COLS * (size_t)B));
-    RA_HIP(ctx, hipHostMalloc((void**)&ws.hout, sizeof(double) * ra::BATCH_COLS * (size_t)B,
-                              hipHostMallocDefault));
+    RA_HIP(ctx, hipHostMalloc((void**)&ws.hout, sizeof(double) * (ra::BATCH_COLS * (size_t)B + 1),
+                              hipHostMallocCoherent));
+    ws.hflag = reinterpret_cast<unsigned*>(ws.hout + ra::BATCH_COLS * (size_t)B);
+    *ws.hflag = 0u;
+    RA_HIP(ctx, hipMalloc((void**)&ws.ticket, sizeof(unsigned)));
+    RA_HIP(ctx, hipMemsetAsync(ws.ticket, 0, sizeof(unsigned), ctx->stream));
     return RA_OK;
 }
 
@@ -822,8 +831,9 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
     for (int a = 0; a < A; ++a) {
         const ra_problem* P = probs[act[a]];
         const ra::PriceLoop& L = loops[act[a]];
-        tiles[a] = (P->n + 63) / 64;
-        cost[a] = 4 * P->m + 8;  // bytes per job
+        const int tr = ra::batch_rows(P->m);
+        tiles[a] = (P->n + tr - 1) / tr;
+        cost[a] = (int64_t)tr * (4 * P->m + 8);  // bytes per tile
         it[a].T = static_cast<const float*>(P->T);
         it[a].prm = static_cast<const float2*>(P->prm);
         it[a].n = P->n;
@@ -908,14 +918,13 @@ ra_status batch_enqueue(ra_ctx* ctx, BatchWs& ws, int grid)
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_segbase),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_seg),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_header), ws.partial,
-                                 ws.dout));
-    RA_HIP(ctx, hipMemcpyAsync(ws.hout, ws.dout, sizeof(double) * ra::BATCH_COLS * (size_t)ws.B,
-                               hipMemcpyDeviceToHost, st));
+                                 ws.hout, ws.ticket, ws.hflag));
     return RA_OK;
 }
 
 ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
 {
+    __atomic_store_n(ws.hflag, 0u, __ATOMIC_RELEASE);
     if (use_graph && !ctx->timing) {
         if (!ws.gexec || ws.graph_grid != grid) {
             if (ws.gexec) (void)hipGraphExecDestroy(ws.gexec);
@@ -945,8 +954,7 @@ ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
         ra_status s = batch_enqueue(ctx, ws, grid);
         if (s != RA_OK) return s;
     }
-    RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    return RA_OK;
+    return wait_flag(ctx, ws.hflag);
 }
 
 std::string batch_signature(const std::vector<ra_problem*>& probs)
@@ -1016,7 +1024,10 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
         off[b + 1] = off[b] + m;
     }
     int64_t total_tiles = 0;
-    for (int b = 0; b < B; ++b) total_tiles += (P[b]->n + 63) / 64;
+    for (int b = 0; b < B; ++b) {
+        const int tr = ra::batch_rows(P[b]->m);
+        total_tiles += (P[b]->n + tr - 1) / tr;
+    }
     if (total_tiles >= ((int64_t)1 << 31))
         return fail(ctx, RA_EUNSUPPORTED, "batch has too many tiles");
     RA_HIP(ctx, hipSetDevice(ctx->dev));
@@ -1109,6 +1120,8 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
             loops[b].feed(p_eval[a], gv, r.data(), row[ra::BATCH_MAX_M + 2]);
         }
     }
+    // the last reduction may still be retiring after its flag
+    RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     bool all = true;
     for (int b = 0; b < B; ++b) {
