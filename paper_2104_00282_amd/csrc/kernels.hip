@@ -171,8 +171,9 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
     }
     // eq. e-xixj on the final segment (lo = -1: the origin, x_hi = t / a_hi)
     const F den = ahi - alo;
-    const F xh = (t - alo) / den;
-    const F xl = (lo >= 0) ? (ahi - t) / den : F(0);
+    const F rden = F(1) / den;
+    const F xh = (t - alo) * rden;
+    const F xl = (lo >= 0) ? (ahi - t) * rden : F(0);
     J.j1 = j1;
     J.v = utility(caplin, w, c, eps, t) - (plo * xl + phi * xh);
     // a zero share is not part of the support; a single resource is
@@ -825,33 +826,47 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
 }
 
 // out[a][c] = sum of partial slots [seg[2a], seg[2a+1]] of column c, for the
-// active problems a < header[0] (blocks stride over them).  With `flag`, out
-// is host memory the host polls: one lane per block writes the block's rows
-// (staged in LDS) and makes them visible system-wide, then takes a ticket;
-// the block with the last ticket resets the counter and raises *flag = 1.
-__global__ void __launch_bounds__(64) k_batch_reduce(const double* __restrict__ partial,
-                                                     const int* __restrict__ seg,
-                                                     const int* __restrict__ header,
-                                                     double* __restrict__ out,
-                                                     unsigned* __restrict__ ticket,
-                                                     unsigned* __restrict__ flag)
+// active problems a < header[0] (blocks stride over them).  Seven groups of
+// BATCH_COLS lanes take every seventh slot, and their sums are added in
+// group order (a fixed order, so results are reproducible).  With `flag`,
+// out is host memory the host polls: one lane per block writes the block's
+// rows and makes them visible system-wide, then takes a ticket; the block
+// with the last ticket resets the counter and raises *flag = 1.
+constexpr int BATCH_RED_GROUPS = 7;  // 7 x 35 lanes of a 256-lane block
+
+__global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__ partial,
+                                                      const int* __restrict__ seg,
+                                                      const int* __restrict__ header,
+                                                      double* __restrict__ out,
+                                                      unsigned* __restrict__ ticket,
+                                                      unsigned* __restrict__ flag)
 {
+    __shared__ double grp[BATCH_RED_GROUPS][BATCH_COLS];
     __shared__ double row[BATCH_COLS];
-    const int c = threadIdx.x;
+    const int tid = threadIdx.x;
+    const int g = tid / BATCH_COLS, c = tid % BATCH_COLS;
     const int A = header[0];
     for (int a = blockIdx.x; a < A; a += gridDim.x) {
-        if (c < BATCH_COLS) {
+        if (g < BATCH_RED_GROUPS) {
             double s = 0.0;
-            for (int k = seg[2 * a]; k <= seg[2 * a + 1]; ++k)
+            const int k1 = seg[2 * a + 1];
+#pragma unroll 4
+            for (int k = seg[2 * a] + g; k <= k1; k += BATCH_RED_GROUPS)
                 s += partial[(int64_t)k * BATCH_COLS + c];
-            row[c] = s;
+            grp[g][c] = s;
         }
         __syncthreads();
-        if (c == 0)
+        if (tid < BATCH_COLS) {
+            double s = grp[0][tid];
+            for (int h = 1; h < BATCH_RED_GROUPS; ++h) s += grp[h][tid];
+            row[tid] = s;
+        }
+        __syncthreads();
+        if (tid == 0)
             for (int k = 0; k < BATCH_COLS; ++k) out[(int64_t)a * BATCH_COLS + k] = row[k];
         __syncthreads();
     }
-    if (flag && c == 0) {
+    if (flag && tid == 0) {
         __threadfence_system();
         if (atomicAdd(ticket, 1u) == (unsigned)gridDim.x - 1u) {
             atomicExch(ticket, 0u);
@@ -1124,8 +1139,8 @@ hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem
                         unsigned* ticket, unsigned* flag)
 {
     k_dual_batch<<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
-    const int rgrid = max_items < 64 ? max_items : 64;
-    k_batch_reduce<<<rgrid, 64, 0, st>>>(partial, seg, header, out, ticket, flag);
+    const int rgrid = max_items < 256 ? max_items : 256;
+    k_batch_reduce<<<rgrid, 256, 0, st>>>(partial, seg, header, out, ticket, flag);
     return hipGetLastError();
 }
 
