@@ -36,9 +36,16 @@ def log(msg):
     sys.stderr.flush()
 
 
+DUAL_SECTION_END = b"// Batched dual kernel:"
+
+
 def kernel_source_hash():
+    """sha256 of the part of kernels.hip that makes up the dual kernel: the
+    per-job helpers, k_dual_vec and k_dual_gen (everything before the batched
+    section)."""
     with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+        src = f.read()
+    return hashlib.sha256(src[:src.index(DUAL_SECTION_END)]).hexdigest()
 
 
 def traffic_from_counters():
@@ -50,7 +57,7 @@ def traffic_from_counters():
             C = json.load(f)
     except (OSError, ValueError):
         return None
-    if C.get("kernels_hip_sha256") != kernel_source_hash():
+    if C.get("dual_kernel_source_sha256") != kernel_source_hash():
         return None
     return C.get("traffic_bytes_per_launch")
 

@@ -496,127 +496,6 @@ __global__ void __launch_bounds__(256) k_dual_gen(
 }
 
 // ------------------------------------------------------------------------
-// Data-dependent starting prices (§5, eq. e-initialization): with the uniform
-// share x (wave-uniform, pb->p), each job's derivative d_i = u_i'(a_i^T x)
-// (log: w / (t + eps); capped linear: w below the cap, 0 at or above it), and
-// partial[b][j] = sum over the block's jobs of d_i a_ij.  The host divides
-// the column sums by n.
-// FP32, m = M in {4, 8, 16, 32, 64}, T 16-byte aligned: tiles staged as in
-// k_dual_vec; lane = job for the derivative, then lane = column for the
-// tile's weighted column sum (column reads of the padded tile are
-// conflict-free).
-// ------------------------------------------------------------------------
-template <int M>
-__global__ void __launch_bounds__(256) k_init_vec(const float* __restrict__ T,
-                                                  const float2* __restrict__ prm, int64_t n,
-                                                  const PriceBlock<float>* __restrict__ pb,
-                                                  float eps, double* __restrict__ partial)
-{
-    constexpr int Q = M / 4;
-    constexpr int S = M + ((Q & 1) ? 0 : 4);
-    constexpr int TR = 64;
-    __shared__ __attribute__((aligned(16))) float tile[4][TR * S];
-    __shared__ float dtab[4][TR];
-    __shared__ float xtab[M];
-    __shared__ double red[4][M];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    if (threadIdx.x < M) xtab[threadIdx.x] = pb->p[threadIdx.x];
-    __syncthreads();
-    double racc = 0.0;
-    const int64_t ntiles = (n + TR - 1) / TR;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    float* tl = tile[wv];
-    for (int64_t ti = (int64_t)blockIdx.x * 4 + wv; ti < ntiles; ti += nw) {
-        const int64_t row0 = ti * TR;
-        const int rows = (int)((n - row0) < TR ? (n - row0) : TR);
-        const float4* src = reinterpret_cast<const float4*>(T + row0 * M);
-        const int valid = rows * Q;
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const int ch = lane + 64 * k;
-            const float4 v = (ch < valid) ? stream_load(src + ch) : make_float4(0.f, 0.f, 0.f, 0.f);
-            const int r = ch / Q, q = ch % Q;
-            *reinterpret_cast<float4*>(tl + r * S + 4 * q) = v;
-        }
-        const float2 wc = (lane < rows) ? prm[row0 + lane] : make_float2(0.f, -1.f);
-        wave_sync();
-        float t = 0.f;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const float4 v = *reinterpret_cast<const float4*>(tl + lane * S + 4 * q);
-            t += v.x * xtab[4 * q] + v.y * xtab[4 * q + 1] + v.z * xtab[4 * q + 2] +
-                 v.w * xtab[4 * q + 3];
-        }
-        const bool caplin = wc.y >= 0.f;
-        const float d = caplin ? (t < wc.y ? wc.x : 0.f) : wc.x / (t + eps);
-        dtab[wv][lane] = lane < rows ? d : 0.f;
-        wave_sync();
-        if (lane < M) {
-            float s = 0.f;
-            for (int r = 0; r < TR; ++r) s += dtab[wv][r] * tl[r * S + lane];
-            racc += (double)s;
-        }
-        wave_sync();
-    }
-    if (lane < M) red[wv][lane] = racc;
-    __syncthreads();
-    if (threadIdx.x < M) {
-        const int j = threadIdx.x;
-        partial[(int64_t)blockIdx.x * M + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
-    }
-}
-
-// Any m <= 256, FP32 or FP64: one lane per job reading its row from global
-// memory; d_i a_ij added into a per-wave LDS row, flushed per tile.
-template <typename F>
-__global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
-                                                  const V2<F>* __restrict__ prm, int64_t n,
-                                                  int m, const PriceBlock<F>* __restrict__ pb,
-                                                  F eps, double* __restrict__ partial)
-{
-    constexpr int TR = 64;
-    __shared__ F hist[4][256];
-    __shared__ double red[4][256];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const F* __restrict__ x = pb->p;
-    for (int j = lane; j < m; j += 64) hist[wv][j] = F(0);
-    __syncthreads();
-    double racc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int64_t ntiles = (n + TR - 1) / TR;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t ti = (int64_t)blockIdx.x * 4 + wv; ti < ntiles; ti += nw) {
-        const int64_t i = ti * TR + lane;
-        if (i < n) {
-            const F* a = T + i * m;
-            F t = F(0);
-            for (int j = 0; j < m; ++j) t += a[j] * x[j];
-            const V2<F> wc = prm[i];
-            const F d = wc.y >= F(0) ? (t < wc.y ? wc.x : F(0)) : wc.x / (t + eps);
-            if (d != F(0))
-                for (int j = 0; j < m; ++j) atomicAdd(&hist[wv][j], d * a[j]);
-        }
-        wave_sync();
-        for (int k = 0; k < 4; ++k) {
-            const int j = lane + 64 * k;
-            if (j < m) {
-                racc[k] += (double)hist[wv][j];
-                hist[wv][j] = F(0);
-            }
-        }
-        wave_sync();
-    }
-    for (int k = 0; k < 4; ++k) {
-        const int j = lane + 64 * k;
-        if (j < m) red[wv][j] = racc[k];
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < m; j += 256)
-        partial[(int64_t)blockIdx.x * m + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
-}
-
-// ------------------------------------------------------------------------
 // Batched dual kernel: many FP32 problems with m in {4, 8, 16, 32} evaluated
 // in one persistent launch per price iteration.  A batched tile is 8 KiB of
 // T whatever m (batch_rows(m) = 2048/m rows: 512 at m = 4, 64 at m = 32,
@@ -874,6 +753,127 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__
             __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
+}
+
+// ------------------------------------------------------------------------
+// Data-dependent starting prices (§5, eq. e-initialization): with the uniform
+// share x (wave-uniform, pb->p), each job's derivative d_i = u_i'(a_i^T x)
+// (log: w / (t + eps); capped linear: w below the cap, 0 at or above it), and
+// partial[b][j] = sum over the block's jobs of d_i a_ij.  The host divides
+// the column sums by n.
+// FP32, m = M in {4, 8, 16, 32, 64}, T 16-byte aligned: tiles staged as in
+// k_dual_vec; lane = job for the derivative, then lane = column for the
+// tile's weighted column sum (column reads of the padded tile are
+// conflict-free).
+// ------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(256) k_init_vec(const float* __restrict__ T,
+                                                  const float2* __restrict__ prm, int64_t n,
+                                                  const PriceBlock<float>* __restrict__ pb,
+                                                  float eps, double* __restrict__ partial)
+{
+    constexpr int Q = M / 4;
+    constexpr int S = M + ((Q & 1) ? 0 : 4);
+    constexpr int TR = 64;
+    __shared__ __attribute__((aligned(16))) float tile[4][TR * S];
+    __shared__ float dtab[4][TR];
+    __shared__ float xtab[M];
+    __shared__ double red[4][M];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    if (threadIdx.x < M) xtab[threadIdx.x] = pb->p[threadIdx.x];
+    __syncthreads();
+    double racc = 0.0;
+    const int64_t ntiles = (n + TR - 1) / TR;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    float* tl = tile[wv];
+    for (int64_t ti = (int64_t)blockIdx.x * 4 + wv; ti < ntiles; ti += nw) {
+        const int64_t row0 = ti * TR;
+        const int rows = (int)((n - row0) < TR ? (n - row0) : TR);
+        const float4* src = reinterpret_cast<const float4*>(T + row0 * M);
+        const int valid = rows * Q;
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int ch = lane + 64 * k;
+            const float4 v = (ch < valid) ? stream_load(src + ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const int r = ch / Q, q = ch % Q;
+            *reinterpret_cast<float4*>(tl + r * S + 4 * q) = v;
+        }
+        const float2 wc = (lane < rows) ? prm[row0 + lane] : make_float2(0.f, -1.f);
+        wave_sync();
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const float4 v = *reinterpret_cast<const float4*>(tl + lane * S + 4 * q);
+            t += v.x * xtab[4 * q] + v.y * xtab[4 * q + 1] + v.z * xtab[4 * q + 2] +
+                 v.w * xtab[4 * q + 3];
+        }
+        const bool caplin = wc.y >= 0.f;
+        const float d = caplin ? (t < wc.y ? wc.x : 0.f) : wc.x / (t + eps);
+        dtab[wv][lane] = lane < rows ? d : 0.f;
+        wave_sync();
+        if (lane < M) {
+            float s = 0.f;
+            for (int r = 0; r < TR; ++r) s += dtab[wv][r] * tl[r * S + lane];
+            racc += (double)s;
+        }
+        wave_sync();
+    }
+    if (lane < M) red[wv][lane] = racc;
+    __syncthreads();
+    if (threadIdx.x < M) {
+        const int j = threadIdx.x;
+        partial[(int64_t)blockIdx.x * M + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    }
+}
+
+// Any m <= 256, FP32 or FP64: one lane per job reading its row from global
+// memory; d_i a_ij added into a per-wave LDS row, flushed per tile.
+template <typename F>
+__global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
+                                                  const V2<F>* __restrict__ prm, int64_t n,
+                                                  int m, const PriceBlock<F>* __restrict__ pb,
+                                                  F eps, double* __restrict__ partial)
+{
+    constexpr int TR = 64;
+    __shared__ F hist[4][256];
+    __shared__ double red[4][256];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const F* __restrict__ x = pb->p;
+    for (int j = lane; j < m; j += 64) hist[wv][j] = F(0);
+    __syncthreads();
+    double racc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t ntiles = (n + TR - 1) / TR;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t ti = (int64_t)blockIdx.x * 4 + wv; ti < ntiles; ti += nw) {
+        const int64_t i = ti * TR + lane;
+        if (i < n) {
+            const F* a = T + i * m;
+            F t = F(0);
+            for (int j = 0; j < m; ++j) t += a[j] * x[j];
+            const V2<F> wc = prm[i];
+            const F d = wc.y >= F(0) ? (t < wc.y ? wc.x : F(0)) : wc.x / (t + eps);
+            if (d != F(0))
+                for (int j = 0; j < m; ++j) atomicAdd(&hist[wv][j], d * a[j]);
+        }
+        wave_sync();
+        for (int k = 0; k < 4; ++k) {
+            const int j = lane + 64 * k;
+            if (j < m) {
+                racc[k] += (double)hist[wv][j];
+                hist[wv][j] = F(0);
+            }
+        }
+        wave_sync();
+    }
+    for (int k = 0; k < 4; ++k) {
+        const int j = lane + 64 * k;
+        if (j < m) red[wv][j] = racc[k];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += 256)
+        partial[(int64_t)blockIdx.x * m + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
 }
 
 // ------------------------------------------------------------------------
