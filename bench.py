@@ -312,6 +312,52 @@ def bench_solves(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_batch_rounds(args):
+    """Throughput of one batched round (all instances active, fixed prices
+    path of the solver, 10 rounds timed on the host after 3 untimed) for
+    256 instances of one m class at a time, and for the mixed batch."""
+    import torch
+    import synth
+    import paper_2104_00282_amd as ra
+
+    dev = torch.device("cuda:0")
+    ctx = ra.Context(0)
+    rows = {}
+    for ms in ((4,), (8,), (16,), (32,), (4, 8, 16, 32)):
+        insts = synth.batch_instances(count=256, ms=ms)
+        probs, keep = [], []
+        for I in insts:
+            ts = [torch.from_numpy(a).to(dev) for a in (I.T, I.w, I.c, I.kind)]
+            keep.append(ts)
+            probs.append(ra.Problem(ctx, ts[0], ts[1], ts[2], ts[3], I.R, I.eps, validate=False))
+        torch.cuda.synchronize()
+        ra.batch_solve(probs, tol_rel=0.0, max_iter=3, max_evals=3)
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ra.batch_solve(probs, tol_rel=0.0, max_iter=10, max_evals=10)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / 10
+            best = t if best is None else min(best, t)
+        nbytes = sum(I.n * I.m * 4 + I.n * 8 for I in insts)
+        rows["m=" + "/".join(str(m) for m in ms)] = {"ms_per_round": best * 1e3, "bytes": nbytes,
+                                                      "TB/s": nbytes / best / 1e12}
+        log("%s: %s" % (ms, rows["m=" + "/".join(str(m) for m in ms)]))
+        for pr in probs:
+            pr.close()
+        del keep
+        torch.cuda.empty_cache()
+    out = {"metric": "batched round throughput by m class", "value": rows["m=4/8/16/32"]["TB/s"],
+           "unit": "TB/s (T and packed utilities)", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "256 instances per class, n log-uniform [1e3, 1e6], mixed-16 "
+                                  "recipe; 10 rounds, best of 3"},
+           "rounds": rows}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def synth_seed(offset):
     import synth
     return synth.BASE_SEED + offset
@@ -326,7 +372,8 @@ def main():
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale the HBM counters")
-    ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves"],
+    ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
+                                           "batch-rounds"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
@@ -346,12 +393,12 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload in ("batched", "warmstart", "solves"):
+    if args.workload in ("batched", "warmstart", "solves", "batch-rounds"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batched": bench_batched, "warmstart": bench_warmstart,
-         "solves": bench_solves}[args.workload](args)
+         "solves": bench_solves, "batch-rounds": bench_batch_rounds}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
