@@ -141,6 +141,8 @@ typedef struct {
                                 the largest price by this fraction of max_j p_j;
                                 0 = the default (0.1, or 0.02 from a learned start);
                                 must be finite, 0 <= init_step <= 10               */
+    double tol_abs;          /* > 0: also stop when g - U(X~) <= tol_abs (Algorithm 2's
+                                absolute test; the paper suggests 1e-3 n)          */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
@@ -159,7 +161,7 @@ typedef struct {
 
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
- * stall_evals = 0 (off), init_step = 0 (default step). */
+ * stall_evals = 0 (off), init_step = 0 (default step), tol_abs = 0 (off). */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
 /* The paper's data-dependent starting prices (§5, "Initialization", eq.

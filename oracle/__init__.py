@@ -51,7 +51,7 @@ class _Job(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("tol_rel", _d), ("max_iter", _i32), ("mem", _i32), ("method", _i32),
-                ("verbose", _i32)]
+                ("verbose", _i32), ("tol_abs", _d)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -187,7 +187,8 @@ def lower_bound(T, w, c, kind, eps, R, r, jobs):
     return U, du.value
 
 
-def solve(T, w, c, kind, eps, R, p0=None, tol_rel=1e-6, max_iter=500, mem=10, method=0):
+def solve(T, w, c, kind, eps, R, p0=None, tol_rel=1e-6, max_iter=500, mem=10, method=0,
+          tol_abs=0.0):
     """Algorithm 2 with the oracle's projected L-BFGS; returns (p, info dict)."""
     T = np.ascontiguousarray(T)
     n, m = T.shape
@@ -196,7 +197,7 @@ def solve(T, w, c, kind, eps, R, p0=None, tol_rel=1e-6, max_iter=500, mem=10, me
     kind = np.ascontiguousarray(kind, dtype=np.uint8)
     R = np.ascontiguousarray(R, dtype=np.float64)
     p = np.ones(m) if p0 is None else np.array(p0, dtype=np.float64)
-    opts = SolveOpts(tol_rel, max_iter, mem, method, 0)
+    opts = SolveOpts(tol_rel, max_iter, mem, method, 0, tol_abs)
     info = SolveInfo()
     rc = lib().orc_solve(n, m, _tdt(T), _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
                          _ptr(R), ctypes.byref(opts), _ptr(p), ctypes.byref(info))

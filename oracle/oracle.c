@@ -37,8 +37,12 @@
  *     (that basic solution is the endpoint of a single-resource segment);
  *   - the target-priority table has no row for w > alpha with c < gamma: the
  *     utility is flat on the whole segment, so the cheapest point gamma wins;
- *   - a segment with alpha <= 0 (never on the lower envelope for p >= 0) is
- *     maximised at delta for both utilities (increasing objective);
+ *   - a segment with alpha < 0 (never on the lower envelope for p >= 0) is
+ *     maximised at delta for both utilities (increasing objective); a
+ *     segment with alpha = 0 (a free resource, on the envelope) follows the
+ *     closed forms: delta for log (w/alpha is infinite), and the
+ *     target-priority table's w > alpha row, clip(c, gamma, delta), for the
+ *     capped-linear utility;
  *   - ties between segments keep the first one in enumeration order
  *     (origin point, then single-resource segments, then pairs);
  *   - the L-BFGS details (projection, line search, memory) are not in the
@@ -75,7 +79,7 @@ double orc_utility(int kind, double w, double c, double eps, double t)
 double orc_segment_argmax(int kind, double w, double c, double eps, double alpha, double gamma,
                           double delta)
 {
-    if (alpha <= 0.0)
+    if (alpha < 0.0)
         return delta;
     if (kind == ORC_LOG) {
         double t = w / alpha - eps;
@@ -299,7 +303,16 @@ typedef struct {
     int32_t mem;      /* L-BFGS memory (the paper uses 10)                     */
     int32_t method;   /* 0 = L-BFGS, 1 = projected subgradient only            */
     int32_t verbose;
+    double tol_abs;   /* > 0: also stop when g - U <= tol_abs (Algorithm 2's
+                         test "g - U(X~) <= epsilon"; the paper suggests
+                         epsilon = 1e-3 n)                                   */
 } orc_solve_opts;
+
+/* The stopping test of Algorithm 2 on a certified point. */
+static int orc_met(double g, double U, double rel, const orc_solve_opts *o)
+{
+    return rel <= o->tol_rel || (o->tol_abs > 0.0 && g - U <= o->tol_abs);
+}
 
 typedef struct {
     int32_t iters, evals, status; /* status 0 = converged, 1 = max_iter        */
@@ -396,7 +409,7 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
             best_U = E->U;
             memcpy(pbest, p, sizeof(double) * m);
         }
-        if (E->rel <= opt->tol_rel) {
+        if (orc_met(E->g, E->U, E->rel, opt)) {
             status = 0;
             break;
         }
@@ -449,7 +462,7 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
                     goto done;
                 }
                 ++evals;
-                if (E2->rel <= opt->tol_rel ||
+                if (orc_met(E2->g, E2->U, E2->rel, opt) ||
                     E2->f <= E->f + 1e-4 * dot(m, E->grad, q)) {
                     took = 1;
                     break;
@@ -498,7 +511,7 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
         best_U = E->U;
         memcpy(pbest, p, sizeof(double) * m);
     }
-    if (best_rel <= opt->tol_rel) status = 0;
+    if (orc_met(best_g, best_U, best_rel, opt)) status = 0;
     for (int j = 0; j < m; ++j) p_inout[j] = pbest[j];
     info->iters = iters;
     info->evals = evals;

@@ -141,12 +141,14 @@ class Problem:
         return out
 
     def solve(self, p0=None, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, method=0, use_graph=True,
-              verbose=False, max_evals=0, stall_evals=0, init_step=0.0, paper_init=False):
+              verbose=False, max_evals=0, stall_evals=0, init_step=0.0, paper_init=False,
+              tol_abs=0.0):
         """Price discovery; returns (p, info dict, status).  paper_init starts
         from the paper's data-dependent prices (ra_init_prices) unless p0 is
         given."""
         o = ra_solve_opts_default()
         o.init_step = init_step
+        o.tol_abs = tol_abs
         o.max_evals = max_evals
         o.stall_evals = stall_evals
         o.tol_rel = tol_rel
@@ -216,7 +218,7 @@ class Problem:
 
 def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lbfgs_mem=10,
                 method=0, use_graph=True, max_evals=0, stall_evals=0, init_step=0.0,
-                paper_init=False):
+                paper_init=False, tol_abs=0.0):
     """Solve several Problems of one Context together (ra_batch_solve).
     Returns (list of price arrays, list of info dicts, status)."""
     if not problems:
@@ -232,6 +234,7 @@ def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lb
     o.max_evals = max_evals
     o.stall_evals = stall_evals
     o.init_step = init_step
+    o.tol_abs = tol_abs
     ms = [pr.m for pr in problems]
     offs = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
     p = np.ones(int(offs[-1]))

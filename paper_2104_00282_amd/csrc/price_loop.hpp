@@ -65,7 +65,7 @@ public:
                 if (!best_.certified || pend_.rel < 0.999 * best_.rel) improved_at_ = evals_;
                 best_ = pend_;
             }
-            if (pend_.rel <= o_.tol_rel) {
+            if (met(pend_)) {
                 state_ = DONE;
                 return;
             }
@@ -135,7 +135,13 @@ public:
     // Outcome: the certified point with the smallest relative gap (or the
     // last point evaluated if none could be certified).
     const Point& result() const { return best_.certified ? best_ : pend_; }
-    bool converged() const { return best_.certified && best_.rel <= o_.tol_rel; }
+    bool converged() const { return best_.certified && met(best_); }
+    // Algorithm 2's stopping test on a certified point: relative gap, or the
+    // absolute gap g - U(X~) when tol_abs is set
+    bool met(const Point& e) const
+    {
+        return e.rel <= o_.tol_rel || (o_.tol_abs > 0.0 && e.gap <= o_.tol_abs);
+    }
     int iters() const { return iters_; }
     int evals() const { return evals_; }
     int fallbacks() const { return fallbacks_; }

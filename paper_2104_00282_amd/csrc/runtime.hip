@@ -492,13 +492,15 @@ void ra_solve_opts_default(ra_solve_opts* o)
     o->max_evals = 0;
     o->stall_evals = 0;
     o->init_step = 0.0;
+    o->tol_abs = 0.0;
 }
 
 static bool valid_opts(const ra_solve_opts& o)
 {
     return o.tol_rel >= 0.0 && o.max_iter >= 0 && o.max_evals >= 0 && o.stall_evals >= 0 &&
            o.lbfgs_mem >= 1 && o.lbfgs_mem <= 64 && (o.method == 0 || o.method == 1) &&
-           (o.init >= 0 && o.init <= 2) && o.init_step >= 0.0 && o.init_step <= 10.0;
+           (o.init >= 0 && o.init <= 2) && o.init_step >= 0.0 && o.init_step <= 10.0 &&
+           o.tol_abs >= 0.0 && std::isfinite(o.tol_abs);
 }
 
 ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opts,

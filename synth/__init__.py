@@ -236,6 +236,32 @@ def random_small(n, m, seed, dtype=np.float64, log_frac=0.5, zero_frac=0.0, eps=
                     eps, seed)
 
 
+def e1_instance(kind, n=1_000_000, seed=BASE_SEED + 5, dtype=np.float32):
+    """The paper's medium-size example (§6.2): m = 4 with a_i1 ~ U(0.1, 0.3),
+    a_i2 ~ U(0.1, 0.5), a_i3 ~ U(0.3, 0.8), a_i4 ~ U(0.6, 1.0) and limits
+    R = (8e5, 1e5, 1e4, 1e3) (scaled by n / 1e6 for other n).
+    kind "log": u_i = log t (w = 1, eps = 0).  kind "target": target-priority
+    utility with target throughput 0.2 and priority w_i = 1 or 2 with
+    probability 1/2 each, in the capped form w min(t, 0.2) (same maximisers).
+    The paper's draws are not published; these are seeded."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 11]))
+    lo = np.array([0.1, 0.1, 0.3, 0.6])
+    hi = np.array([0.3, 0.5, 0.8, 1.0])
+    T = (lo + (hi - lo) * rng.random((n, 4))).astype(dtype)
+    R = np.array([8e5, 1e5, 1e4, 1e3]) * (n / 1e6)
+    if kind == "log":
+        w = np.ones(n)
+        c = np.zeros(n)
+        k = np.full(n, LOG, np.uint8)
+    elif kind == "target":
+        w = np.where(rng.random(n) < 0.5, 1.0, 2.0)
+        c = np.full(n, 0.2)
+        k = np.full(n, CAPLIN, np.uint8)
+    else:
+        raise ValueError(kind)
+    return Instance("e1-" + kind, T, w.astype(dtype), c.astype(dtype), k, R, 0.0, seed)
+
+
 CONFIGS = {
     "small-log": small_log,
     "mixed-16": mixed_16,

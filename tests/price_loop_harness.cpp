@@ -33,6 +33,7 @@ int main(int argc, char** argv)
     o.max_evals = !std::strcmp(mode, "budget") ? 7 : 0;
     o.stall_evals = !std::strcmp(mode, "stall") ? 25 : 0;
     o.init_step = 0.0;
+    o.tol_abs = 0.0;
     if (!std::strcmp(mode, "subgradient")) o.max_iter = 400;
     std::vector<double> p0(m, 3.0);
     ra::PriceLoop L(m, n, R.data(), o, p0.data());
