@@ -28,11 +28,14 @@ from scipy.optimize import linprog, minimize_scalar
 
 LOG = 0
 CAPLIN = 1
+AFAIR = 2
 
 
 def u(kind, w, c, eps, t):
-    if kind == LOG:
+    if kind == LOG or (kind == AFAIR and c == 1.0):
         return w * math.log(t + eps)
+    if kind == AFAIR:
+        return w * (t + eps) ** (1.0 - c) / (1.0 - c)
     return w * min(t, c)
 
 

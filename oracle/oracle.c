@@ -30,7 +30,11 @@
  *
  * Utilities (§2.2): kind 0 = log, u(t) = w*log(t + eps); kind 1 = capped
  * linear, u(t) = w*min(t, c), which is the target-priority utility
- * w*min(t - c, 0) plus the constant w*c (same maximisers).
+ * w*min(t - c, 0) plus the constant w*c (same maximisers); kind 2 =
+ * alpha-fair with exponent c (the family that holds the linear, log and
+ * power utilities of §2.2), u(t) = w*(t + eps)^(1 - c)/(1 - c) for c != 1
+ * (c = 0: linear, 0 < c < 1: power t^q with q = 1 - c, c > 1: -t^q with
+ * q < 0 up to the factor 1/|1 - c|) and w*log(t + eps) for c = 1.
  *
  * Readings taken where the paper is silent:
  *   - equal efficiencies a_k = a_l give a zero-width segment and are skipped
@@ -61,21 +65,27 @@
 
 #define ORC_LOG 0
 #define ORC_CAPLIN 1
+#define ORC_AFAIR 2
 #define ORC_CHUNK 4096
 
 /* ------------------------------------------------------------ utilities -- */
 
-/* u_i(t) of §2.2 for the two kinds used here. */
+/* u_i(t) of §2.2 for the kinds used here. */
 double orc_utility(int kind, double w, double c, double eps, double t)
 {
-    if (kind == ORC_LOG)
+    if (kind == ORC_LOG || (kind == ORC_AFAIR && c == 1.0))
         return w * log(t + eps);
+    if (kind == ORC_AFAIR)
+        return w * pow(t + eps, 1.0 - c) / (1.0 - c);
     return w * (t < c ? t : c);
 }
 
 /* Maximiser of u(t) - (alpha t + beta) over [gamma, delta] (§4.2).
  * Log: t = projection of (u')^{-1}(alpha) = w/alpha - eps onto the interval
- * (eq. e-opt-t-log).  Capped-linear: eq. e-opt-t-target with t_des = c. */
+ * (eq. e-opt-t-log).  Capped-linear: eq. e-opt-t-target with t_des = c.
+ * Alpha-fair with exponent c > 0: the same projection of (u')^{-1}(alpha) =
+ * (w/alpha)^(1/c) - eps (u' = w (t + eps)^(-c) is decreasing); c = 0
+ * (linear): the right end if w > alpha, else the left end. */
 double orc_segment_argmax(int kind, double w, double c, double eps, double alpha, double gamma,
                           double delta)
 {
@@ -83,6 +93,13 @@ double orc_segment_argmax(int kind, double w, double c, double eps, double alpha
         return delta;
     if (kind == ORC_LOG) {
         double t = w / alpha - eps;
+        if (t < gamma) t = gamma;
+        if (t > delta) t = delta;
+        return t;
+    }
+    if (kind == ORC_AFAIR) {
+        if (c == 0.0) return w > alpha ? delta : gamma;
+        double t = pow(w / alpha, 1.0 / c) - eps;
         if (t < gamma) t = gamma;
         if (t > delta) t = delta;
         return t;
@@ -539,8 +556,9 @@ done:
  * kappa = 1^T R / n exceeds 1 (so that 1^T x = 1), and
  *   p1 = (1/n) sum_i u_i'(a_i^T x) a_i,
  * the gradient of U at R under that uniform allocation.  Derivatives:
- * log, w/(t + eps); capped linear, w below the cap and 0 at or above it
- * (the right derivative, one supergradient at the kink).
+ * log, w/(t + eps); alpha-fair, w (t + eps)^(-c); capped linear, w below
+ * the cap and 0 at or above it (the right derivative, one supergradient at
+ * the kink).
  * Sums run per fixed chunk of rows, then in chunk order.
  * Returns 0, or -1 on an allocation failure. */
 int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
@@ -566,6 +584,8 @@ int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, con
             double du;
             if (kind[i] == ORC_LOG)
                 du = wi / (t + eps);
+            else if (kind[i] == ORC_AFAIR)
+                du = wi * pow(t + eps, -pval(c, tdt, i));
             else
                 du = t < pval(c, tdt, i) ? wi : 0.0;
             for (int j = 0; j < m; ++j) acc[j] += du * tval(T, tdt, i * m + j);

@@ -477,3 +477,91 @@ def test_free_resource_segment_follows_the_tables():
     assert oracle.segment_argmax(LOG, 1.5, 0.0, 1e-3, 0.0, 0.0, 0.3) == 0.3
     J = oracle.subproblem([0.3, 0.9], [0.0, 2.0], CAPLIN, 1.0, 0.2, 0.0)
     assert J["t"] == pytest.approx(0.2) and J["xhi"] == pytest.approx(0.2 / 0.3)
+
+
+# -------------------------------------------- alpha-fair utilities ----
+
+AFAIR = 2
+
+
+@pytest.mark.parametrize("a", [0.5, 2.0, 3.5])
+def test_alpha_fair_segment_argmax_vs_scalar(a):
+    """Alpha-fair maximiser on a segment ((u')^{-1} projected, §4.2's log
+    rule generalised) against numerical maximisation of u(t) - alpha t."""
+    rng = np.random.default_rng(int(17 * a))
+    for _ in range(200):
+        g = rng.random() * 2
+        d = g + rng.random() * 2 + 1e-3
+        alpha = rng.random() * 3 + 1e-3
+        w = 0.5 + 1.5 * rng.random()
+        t = oracle.segment_argmax(AFAIR, w, a, 1e-3, alpha, g, d)
+        tn, vn = brute.segment_scalar(AFAIR, w, a, 1e-3, alpha, 0.0, g, d)
+        assert brute.u(AFAIR, w, a, 1e-3, t) - alpha * t >= vn - 1e-9
+        assert t == pytest.approx(tn, abs=1e-5)
+
+
+def test_alpha_fair_linear_case_takes_an_end():
+    """Exponent 0 is linear utility: the right end when w > alpha, else the left."""
+    assert oracle.segment_argmax(AFAIR, 2.0, 0.0, 0.0, 1.5, 0.5, 1.0) == 1.0
+    assert oracle.segment_argmax(AFAIR, 1.0, 0.0, 0.0, 1.5, 0.5, 1.0) == 0.5
+    assert oracle.segment_argmax(AFAIR, 1.5, 0.0, 0.0, 1.5, 0.5, 1.0) == 0.5
+
+
+@pytest.mark.parametrize("a", [0.0, 0.5, 2.0])
+def test_alpha_fair_job_optimum_vs_lp_golden(a):
+    rng = np.random.default_rng(int(23 + 10 * a))
+    for _ in range(30):
+        m = int(rng.integers(1, 6))
+        A = rng.random(m) * 2 + 0.01
+        p = rng.random(m) * 2 + 0.01
+        w = 0.5 + 1.5 * rng.random()
+        J = oracle.subproblem(A, p, AFAIR, w, a, 1e-3)
+        t, v = brute.job_golden(A, p, AFAIR, w, a, 1e-3)
+        assert J["v"] == pytest.approx(v, abs=1e-7)
+        if a > 0:
+            assert J["t"] == pytest.approx(t, abs=1e-5)
+
+
+def test_alpha_fair_near_one_is_log():
+    """The family's exponent 1 is the log utility: nearby exponents give
+    nearly the log optimum (continuity in the exponent)."""
+    rng = np.random.default_rng(29)
+    for _ in range(20):
+        A = rng.random(4) * 2 + 0.01
+        p = rng.random(4) * 2 + 0.01
+        Jl = oracle.subproblem(A, p, LOG, 1.3, 0.0, 1e-3)
+        for a in (1.0 - 1e-7, 1.0 + 1e-7):
+            Ja = oracle.subproblem(A, p, AFAIR, 1.3, a, 1e-3)
+            assert Ja["t"] == pytest.approx(Jl["t"], abs=1e-5)
+        assert oracle.subproblem(A, p, AFAIR, 1.3, 1.0, 1e-3)["t"] == pytest.approx(Jl["t"], abs=1e-12)
+
+
+def test_alpha_fair_zero_is_the_linear_lp():
+    """Exponent 0 (u = w (t + eps), eps = 0: linear utility) over a whole
+    problem: the dual optimum equals the LP optimum."""
+    I = _inst(80, 3, 7)
+    kind = np.full(I.n, AFAIR, np.uint8)
+    c = np.zeros(I.n)
+    Ulp = brute.lp_linear(I.T, I.w, I.R)
+    p, info = oracle.solve(I.T, I.w, c, kind, 0.0, I.R, tol_rel=1e-10, max_iter=400)
+    assert info["g"] == pytest.approx(Ulp, rel=1e-7)
+
+
+def test_alpha_fair_initial_prices_gradient():
+    """eq. e-initialization with alpha-fair jobs: central differences of
+    sum_i u_i(a_i^T R / n)."""
+    rng = np.random.default_rng(31)
+    n, m = 50, 3
+    T = 0.2 + rng.random((n, m))
+    w = 0.5 + rng.random(n)
+    c = rng.choice([0.0, 0.5, 2.0], n)
+    kind = np.full(n, AFAIR, np.uint8)
+    R = 0.2 * n / m * (0.5 + rng.random(m))
+    p = oracle.init_prices(T, w, c, kind, 1e-3, R)
+    phi = lambda y: sum(brute.u(AFAIR, w[i], c[i], 1e-3, float(T[i] @ y)) for i in range(n))
+    for j in range(m):
+        h = 1e-5 * R[j]
+        e = np.zeros(m)
+        e[j] = h
+        fd = (phi((R + e) / n) - phi((R - e) / n)) / (2 * h)
+        assert p[j] == pytest.approx(fd, rel=1e-7)
