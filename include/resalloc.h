@@ -33,6 +33,11 @@
  *   RA_UTIL_LOG     u(t) = w * log(t + eps)                    (w > 0)
  *   RA_UTIL_CAPLIN  u(t) = w * min(t, c)   (capped linear; the target-priority
  *                   utility w*min(t - c, 0) of §2.2 shifted by w*c; c >= 0)
+ *   RA_UTIL_ALPHA_FAIR  u(t) = w * (t + eps)^(1 - a) / (1 - a) with exponent
+ *                   a = c >= 0 (the alpha-fair family of §2.2: a = 0 linear,
+ *                   0 < a < 1 power t^q, a > 1 -t^q with q < 0 up to a positive
+ *                   factor; a = 1 is taken as RA_UTIL_LOG). With a > 1 and
+ *                   eps = 0 every optimum must have t > 0.
  */
 #ifndef RESALLOC_H
 #define RESALLOC_H
@@ -55,7 +60,7 @@ typedef enum {
 
 typedef enum { RA_F32 = 0, RA_F64 = 1 } ra_dtype;
 
-typedef enum { RA_UTIL_LOG = 0, RA_UTIL_CAPLIN = 1 } ra_util_kind;
+typedef enum { RA_UTIL_LOG = 0, RA_UTIL_CAPLIN = 1, RA_UTIL_ALPHA_FAIR = 2 } ra_util_kind;
 
 typedef struct ra_ctx ra_ctx;         /* device, stream, scratch, pinned staging   */
 typedef struct ra_problem ra_problem; /* borrowed T + packed per-job utilities      */
@@ -86,7 +91,8 @@ const char *ra_last_error(const ra_ctx *ctx);
  *   T         device, n x m row-major efficiency matrix; row i is the job's
  *             efficiency vector a_i of §2.1 (entries >= 0, finite)
  *   w, c      device, n values each: utility weight (> 0) and, for capped
- *             linear jobs, the cap c (>= 0; ignored for log jobs)
+ *             linear jobs, the cap c (>= 0), for alpha-fair jobs the exponent
+ *             (>= 0); ignored for log jobs
  *   kind      device, n bytes of ra_util_kind, or NULL for all RA_UTIL_LOG
  *   R         host, m resource limits R_j (> 0, finite); copied
  *   eps       log offset (>= 0; eps = 0 requires every optimum t_i > 0)

@@ -15,7 +15,8 @@ import numpy as np
 
 from . import _capi
 from ._capi import (RA_EDEVICE, RA_EINVAL, RA_ENOMEM, RA_ENOTCONV, RA_ENUMERIC, RA_EUNSUPPORTED,
-                    RA_F32, RA_F64, RA_OK, RA_UTIL_CAPLIN, RA_UTIL_LOG, RAError, ra_create,
+                    RA_F32, RA_F64, RA_OK, RA_UTIL_ALPHA_FAIR, RA_UTIL_CAPLIN, RA_UTIL_LOG,
+                    RAError, ra_create,
                     ra_destroy, ra_dual_eval, ra_get_allocation, ra_last_error, ra_problem_create,
                     ra_problem_destroy, ra_solve, ra_solve_info, ra_solve_opts,
                     ra_solve_opts_default, ra_status_string, ra_set_kernel_timing,

@@ -23,6 +23,7 @@ RA_F32 = 0
 RA_F64 = 1
 RA_UTIL_LOG = 0
 RA_UTIL_CAPLIN = 1
+RA_UTIL_ALPHA_FAIR = 2
 RA_MAX_RESOURCES = 256
 
 _vp = ctypes.c_void_p

@@ -39,12 +39,26 @@ template <typename F> using V2 = typename Vec2<F>::type;
 
 __device__ __forceinline__ float dlog(float x) { return logf(x); }
 __device__ __forceinline__ double dlog(double x) { return log(x); }
+__device__ __forceinline__ float dpow(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double dpow(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float dexpm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double dexpm1(double x) { return expm1(x); }
+
+// Packed utility code c of a job (second field of prm): c >= 0 capped linear
+// w min(t, c) (the target-priority utility plus a constant); c = -1 log
+// w log(t + eps); c <= -2 alpha-fair with exponent a = -c - 2 (a != 1),
+// w (t + eps)^(1 - a) / (1 - a) (a = 0: linear), the family of §2.2.
+template <typename F>
+__device__ __forceinline__ F afair_exponent(F c) { return -c - F(2); }
 
 // u(t) of §2.2: log utility w log(t + eps) or capped linear w min(t, c).
 template <typename F>
 __device__ __forceinline__ F utility(bool caplin, F w, F c, F eps, F t)
 {
-    return caplin ? w * (t < c ? t : c) : w * dlog(t + eps);
+    if (caplin) return w * (t < c ? t : c);
+    if (c == F(-1)) return w * dlog(t + eps);
+    const F e = F(1) - afair_exponent(c);
+    return w * dpow(t + eps, e) / e;
 }
 
 __device__ __forceinline__ void wave_sync()
@@ -143,8 +157,19 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
         const F num = phi - plo, den = ahi - alo;
         if (!caplin) {
             // eq. e-opt-t-log: t = clip((u')^{-1}(alpha), alo, ahi),
-            // (u')^{-1}(alpha) = w / alpha - eps (+inf for alpha = 0)
-            const F tu = w * den / num - eps;
+            // (u')^{-1}(alpha) = w / alpha - eps (+inf for alpha = 0); the
+            // alpha-fair family: (w / alpha)^(1/a) - eps, and for a = 0
+            // (linear) the right end if w > alpha, else the left end
+            F tu;
+            if (c == F(-1)) {
+                tu = w * den / num - eps;
+            } else {
+                const F a = afair_exponent(c);
+                if (a == F(0))
+                    tu = (w * den > num) ? F(INFINITY) : F(-INFINITY);
+                else
+                    tu = dpow(w * den / num, F(1) / a) - eps;
+            }
             t = fmin(fmax(tu, alo), ahi);
             walk = tu >= ahi;
         } else if (w * den <= num) {  // eq. e-opt-t-target, w <= alpha
@@ -206,8 +231,12 @@ __device__ __forceinline__ void scaled_utility(bool caplin, F w, F c, F eps, int
     const F tt = (jlo >= 0 ? S[jlo] * tlo : F(0)) + (jhi >= 0 ? S[jhi] * thi : F(0));
     const F dt = (jlo >= 0 ? SC[jlo] * tlo : F(0)) + (jhi >= 0 ? SC[jhi] * thi : F(0));
     U = utility(caplin, w, c, eps, tt);
-    if (!caplin) {
+    if (!caplin && c == F(-1)) {
         du = w * dlog1p(dt / (tt + eps));
+    } else if (!caplin) {
+        // u(t) - u(t~) = U ((1 + dt / (t~ + eps))^(1 - a) - 1)
+        const F e = F(1) - afair_exponent(c);
+        du = U * dexpm1(e * dlog1p(dt / (tt + eps)));
     } else {
         const F t = tlo + thi;
         du = (tt >= c) ? F(0) : (t <= c ? w * dt : w * (c - tt));
@@ -809,7 +838,13 @@ __global__ void __launch_bounds__(256) k_init_vec(const float* __restrict__ T,
                  v.w * xtab[4 * q + 3];
         }
         const bool caplin = wc.y >= 0.f;
-        const float d = caplin ? (t < wc.y ? wc.x : 0.f) : wc.x / (t + eps);
+        float d;
+        if (caplin)
+            d = t < wc.y ? wc.x : 0.f;
+        else if (wc.y == -1.f)
+            d = wc.x / (t + eps);
+        else
+            d = wc.x * powf(t + eps, -afair_exponent(wc.y));
         dtab[wv][lane] = lane < rows ? d : 0.f;
         wave_sync();
         if (lane < M) {
@@ -853,7 +888,13 @@ __global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
             F t = F(0);
             for (int j = 0; j < m; ++j) t += a[j] * x[j];
             const V2<F> wc = prm[i];
-            const F d = wc.y >= F(0) ? (t < wc.y ? wc.x : F(0)) : wc.x / (t + eps);
+            F d;
+            if (wc.y >= F(0))
+                d = t < wc.y ? wc.x : F(0);
+            else if (wc.y == F(-1))
+                d = wc.x / (t + eps);
+            else
+                d = wc.x * dpow(t + eps, -afair_exponent(wc.y));
             if (d != F(0))
                 for (int j = 0; j < m; ++j) atomicAdd(&hist[wv][j], d * a[j]);
         }
@@ -981,7 +1022,12 @@ __global__ void k_pack(const F* __restrict__ w, const F* __restrict__ c,
         if (k == 1) {
             ci = c[i];
             if (!(ci >= F(0)) || !isfinite(ci)) flags |= 2;
-        } else if (k > 1) {
+        } else if (k == 2) {
+            // alpha-fair exponent a >= 0; a = 1 is the log utility
+            const F a = c[i];
+            if (!(a >= F(0)) || !isfinite(a)) flags |= 2;
+            ci = (a == F(1)) ? F(-1) : -(F(2) + a);
+        } else if (k > 2) {
             flags |= 4;
         }
         prm[i] = V2<F>{wi, ci};

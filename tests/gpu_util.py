@@ -33,6 +33,15 @@ def job_values(T, p, kind, w, c, eps, X):
     T = T.astype(np.float64)
     t = np.einsum("ij,ij->i", T, X)
     u = np.where(kind == 0, w * np.log(np.maximum(t + eps, 1e-300)), w * np.minimum(t, c))
+    af = kind == 2
+    if af.any():
+        # alpha-fair with exponent c (c = 1: log)
+        e = 1.0 - c[af]
+        te = np.maximum(t[af] + eps, 1e-300)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ua = np.where(e == 0, w[af] * np.log(te), w[af] * te ** e / np.where(e == 0, 1, e))
+        u = u.copy()
+        u[af] = ua
     return u - X @ p, t
 
 

@@ -46,11 +46,24 @@ def _problems(ctx, torch, insts):
     return probs
 
 
-def test_batched_pass_matches_oracle(ctx, torch):
+def _with_alpha_fair(insts, seed):
+    rng = np.random.default_rng(seed)
+    for I in insts:
+        sel = rng.random(I.n) < 0.5
+        I.kind = np.where(sel, 2, I.kind).astype(np.uint8)
+        I.c = np.where(sel, rng.choice([0.0, 0.5, 2.0], I.n), I.c).astype(np.float32)
+    return insts
+
+
+@pytest.mark.parametrize("alpha_fair", [False, True])
+def test_batched_pass_matches_oracle(ctx, torch, alpha_fair):
     """Two passes: the first evaluates p0, the second certifies it; the
-    returned g(p0) and U(X~(p0)) match the oracle for every problem."""
+    returned g(p0) and U(X~(p0)) match the oracle for every problem (also
+    with half of the jobs alpha-fair)."""
     import paper_2104_00282_amd as ra
     insts = _batch_instances()
+    if alpha_fair:
+        insts = _with_alpha_fair(insts, 78)
     probs = _problems(ctx, torch, insts)
     rng = np.random.default_rng(5)
     p0 = [round_prices(0.2 + rng.random(I.m) * 2, np.float32) for I in insts]

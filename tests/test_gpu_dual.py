@@ -212,3 +212,37 @@ def test_invalid_inputs_rejected(ctx, torch):
     assert e.value.status == ra.RA_EINVAL
     with pytest.raises(ra.RAError):
         prob.dual_eval(np.array([1.0, np.nan, 1.0, 1.0]))
+
+
+def _with_alpha_fair(I, seed, frac=0.5):
+    """Half of the jobs become alpha-fair with exponents in {0, 0.5, 2, 3}
+    (linear, power, and the two negative-power cases)."""
+    rng = np.random.default_rng(seed)
+    sel = rng.random(I.n) < frac
+    I.kind = np.where(sel, 2, I.kind).astype(np.uint8)
+    I.c = np.where(sel, rng.choice([0.0, 0.5, 2.0, 3.0], I.n), I.c).astype(I.c.dtype)
+    return I
+
+
+@pytest.mark.parametrize("m,dtype", [(4, np.float32), (16, np.float32), (64, np.float32),
+                                     (5, np.float32), (7, np.float64)])
+def test_alpha_fair_utilities(ctx, torch, m, dtype):
+    """Log, capped-linear and alpha-fair jobs mixed in one problem:
+    vectorised and generic FP32 kernels and FP64, against the oracle."""
+    print("alpha-fair m=%d %s" % (m, np.dtype(dtype).name), flush=True)
+    I = _with_alpha_fair(synth.random_small(N_SMALL, m, seed=300 + m, dtype=dtype), 400 + m)
+    rng = np.random.default_rng(500 + m)
+    for p in (np.ones(m), 0.2 + rng.random(m) * 3):
+        _run(ctx, torch, I, p, TOL32 if dtype == np.float32 else TOL64)
+
+
+def test_alpha_fair_exponent_one_is_log(ctx, torch):
+    """Exponent 1 is packed as the log utility: identical results."""
+    I = synth.random_small(N_SMALL, 8, seed=600, dtype=np.float32, log_frac=1.0)
+    p = round_prices(0.3 + np.arange(8) * 0.2, np.float32)
+    a = _problem(ctx, torch, I).dual_eval(p, lower_bound=True)
+    I.kind = np.full(I.n, 2, np.uint8)
+    I.c = np.ones(I.n, np.float32)
+    b = _problem(ctx, torch, I).dual_eval(p, lower_bound=True)
+    assert a["g"] == b["g"] and a["lower_bound"] == b["lower_bound"]
+    assert np.array_equal(a["grad"], b["grad"])

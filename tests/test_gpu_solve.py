@@ -150,3 +150,23 @@ def test_paper_init_solve(ctx, torch):
     assert i1["converged"] == 1 and i2["converged"] == 1
     assert i2["g"] == pytest.approx(i1["g"], rel=2e-4)
     prob.close()
+
+
+def test_alpha_fair_solve_certificate(ctx, torch):
+    """A mixed-utility problem with alpha-fair jobs, solved on the GPU from
+    the paper's start; the oracle confirms the certificate at the returned
+    prices."""
+    I = synth.random_small(50000, 8, seed=48, dtype=np.float32)
+    rng = np.random.default_rng(49)
+    sel = rng.random(I.n) < 0.5
+    I.kind = np.where(sel, 2, I.kind).astype(np.uint8)
+    I.c = np.where(sel, rng.choice([0.0, 0.5, 2.0], I.n), I.c).astype(np.float32)
+    prob = _problem(ctx, torch, I)
+    p, info, _ = prob.solve(tol_rel=1e-4, max_iter=200, paper_init=True)
+    assert info["rel_gap"] <= 2e-4
+    g, U = _certificate(I, p)
+    scale = abs(g) + abs(U)
+    assert abs(info["g"] - g) <= 1e-5 * scale
+    assert abs(info["U_lb"] - U) <= 1e-5 * scale
+    assert U <= g
+    prob.close()
