@@ -81,6 +81,10 @@ def lib():
         L.orc_solve.restype = ctypes.c_int
         L.orc_solve.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p, _p, _d, _p,
                                 ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(SolveInfo)]
+        L.orc_dual_eval_d.restype = ctypes.c_int
+        L.orc_dual_eval_d.argtypes = L.orc_dual_eval.argtypes + [_p]
+        L.orc_solve_d.restype = ctypes.c_int
+        L.orc_solve_d.argtypes = L.orc_solve.argtypes + [_p]
         L.orc_init_prices.restype = ctypes.c_int
         L.orc_init_prices.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p, _p, _d, _p, _p]
         L.orc_num_threads.restype = ctypes.c_int
@@ -139,8 +143,9 @@ class DualResult:
         return self._R - self.r
 
 
-def dual_eval(T, w, c, kind, eps, R, p, per_job=False):
-    """Dual function value, usage r and (per_job) the per-job optimum."""
+def dual_eval(T, w, c, kind, eps, R, p, per_job=False, d=None):
+    """Dual function value, usage r and (per_job) the per-job optimum.
+    d: optional per-job demands (usage limit sum_i d_i x_i <= R)."""
     T = np.ascontiguousarray(T)
     n, m = T.shape
     tdt = _tdt(T)
@@ -161,9 +166,10 @@ def dual_eval(T, w, c, kind, eps, R, p, per_job=False):
             "j1": np.empty(n, np.int32), "margin1": np.empty(n),
         }
         outs = [jobs[k] for k in ("jlo", "jhi", "xlo", "xhi", "t", "v", "j1", "margin1")]
-    rc = lib().orc_dual_eval(n, m, tdt, _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
-                             _ptr(R), _ptr(p), ctypes.byref(g), _ptr(r), ctypes.byref(sv),
-                             *[_ptr(o) for o in outs])
+    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    rc = lib().orc_dual_eval_d(n, m, tdt, _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
+                               _ptr(R), _ptr(p), ctypes.byref(g), _ptr(r), ctypes.byref(sv),
+                               *[_ptr(o) for o in outs], _ptr(dd))
     if rc != 0:
         raise MemoryError("oracle dual_eval failed")
     res = DualResult(g.value, r, sv.value, jobs)
@@ -188,7 +194,7 @@ def lower_bound(T, w, c, kind, eps, R, r, jobs):
 
 
 def solve(T, w, c, kind, eps, R, p0=None, tol_rel=1e-6, max_iter=500, mem=10, method=0,
-          tol_abs=0.0):
+          tol_abs=0.0, d=None):
     """Algorithm 2 with the oracle's projected L-BFGS; returns (p, info dict)."""
     T = np.ascontiguousarray(T)
     n, m = T.shape
@@ -199,8 +205,9 @@ def solve(T, w, c, kind, eps, R, p0=None, tol_rel=1e-6, max_iter=500, mem=10, me
     p = np.ones(m) if p0 is None else np.array(p0, dtype=np.float64)
     opts = SolveOpts(tol_rel, max_iter, mem, method, 0, tol_abs)
     info = SolveInfo()
-    rc = lib().orc_solve(n, m, _tdt(T), _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
-                         _ptr(R), ctypes.byref(opts), _ptr(p), ctypes.byref(info))
+    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    rc = lib().orc_solve_d(n, m, _tdt(T), _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
+                           _ptr(R), ctypes.byref(opts), _ptr(p), ctypes.byref(info), _ptr(dd))
     if rc != 0:
         raise RuntimeError("oracle solve failed (%d)" % rc)
     return p, {f: getattr(info, f) for f, _ in SolveInfo._fields_}

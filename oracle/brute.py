@@ -111,14 +111,16 @@ def job_grid(a, p, kind, w, c, eps, h=1e-3):
     return best, bx
 
 
-def problem_grid(T, kind, w, c, eps, R, h=0.01):
-    """max sum_i u_i(a_i^T x_i) over grid allocations with sum_i x_i <= R."""
+def problem_grid(T, kind, w, c, eps, R, h=0.01, d=None):
+    """max sum_i u_i(a_i^T x_i) over grid allocations with sum_i d_i x_i <= R
+    (d = 1 by default)."""
     n, m = T.shape
+    dd = np.ones(n) if d is None else np.asarray(d, float)
     pts = list(simplex_grid(m, h))
     best = -math.inf
     for combo in itertools.product(range(len(pts)), repeat=n):
         X = np.array([pts[k] for k in combo])
-        if np.any(X.sum(0) > np.asarray(R) + 1e-12):
+        if np.any((dd[:, None] * X).sum(0) > np.asarray(R) + 1e-12):
             continue
         val = sum(u(kind[i], w[i], c[i], eps, float(T[i] @ X[i])) for i in range(n))
         best = max(best, val)

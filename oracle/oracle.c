@@ -221,10 +221,14 @@ static inline double pval(const void *v, int tdt, int64_t idx)
  * T is n x m row-major, float32 (tdt = 0) or float64 (tdt = 1); w, c have
  * T's type; kind is one byte per job.  Per-job outputs may be NULL.
  * Returns 0, or -1 on an allocation failure. */
-int orc_dual_eval(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
-                  const uint8_t *kind, double eps, const double *R, const double *p, double *g,
-                  double *r, double *sumv_out, int32_t *jlo, int32_t *jhi, double *xlo,
-                  double *xhi, double *tout, double *vout, int32_t *j1, double *margin1)
+/* With per-job demands d (NULL = all 1; §7, "Extensions and variations"):
+ * the usage limit becomes sum_i d_i x_i <= R, job i sees the prices d_i p,
+ * and r = sum_i d_i x_i. */
+int orc_dual_eval_d(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                    const uint8_t *kind, double eps, const double *R, const double *p, double *g,
+                    double *r, double *sumv_out, int32_t *jlo, int32_t *jhi, double *xlo,
+                    double *xhi, double *tout, double *vout, int32_t *j1, double *margin1,
+                    const double *d)
 {
     int64_t nchunks = (n + ORC_CHUNK - 1) / ORC_CHUNK;
     double *part = (double *)calloc((size_t)(nchunks > 0 ? nchunks : 1) * (size_t)(m + 1),
@@ -233,15 +237,17 @@ int orc_dual_eval(int64_t n, int m, int tdt, const void *T, const void *w, const
 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t ch = 0; ch < nchunks; ++ch) {
-        double a[512];
+        double a[512], pd[512];
         double *acc = part + ch * (m + 1);
         int64_t lo = ch * ORC_CHUNK, hi = lo + ORC_CHUNK < n ? lo + ORC_CHUNK : n;
         for (int64_t i = lo; i < hi; ++i) {
             for (int j = 0; j < m; ++j) a[j] = tval(T, tdt, i * m + j);
+            const double di = d ? d[i] : 1.0;
+            for (int j = 0; j < m; ++j) pd[j] = di * p[j];
             orc_job J;
-            orc_subproblem(m, a, p, kind[i], pval(w, tdt, i), pval(c, tdt, i), eps, &J);
-            if (J.jlo >= 0) acc[J.jlo] += J.xlo;
-            if (J.jhi >= 0) acc[J.jhi] += J.xhi;
+            orc_subproblem(m, a, pd, kind[i], pval(w, tdt, i), pval(c, tdt, i), eps, &J);
+            if (J.jlo >= 0) acc[J.jlo] += di * J.xlo;
+            if (J.jhi >= 0) acc[J.jhi] += di * J.xhi;
             acc[m] += J.v;
             if (jlo) jlo[i] = J.jlo;
             if (jhi) jhi[i] = J.jhi;
@@ -265,6 +271,15 @@ int orc_dual_eval(int64_t n, int m, int tdt, const void *T, const void *w, const
     *g = pr + sv;
     if (sumv_out) *sumv_out = sv;
     return 0;
+}
+
+int orc_dual_eval(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                  const uint8_t *kind, double eps, const double *R, const double *p, double *g,
+                  double *r, double *sumv_out, int32_t *jlo, int32_t *jhi, double *xlo,
+                  double *xhi, double *tout, double *vout, int32_t *j1, double *margin1)
+{
+    return orc_dual_eval_d(n, m, tdt, T, w, c, kind, eps, R, p, g, r, sumv_out, jlo, jhi, xlo,
+                           xhi, tout, vout, j1, margin1, NULL);
 }
 
 /* Feasible allocation and its utility (§5): column j of X is scaled by
@@ -344,11 +359,12 @@ typedef struct {
 
 static int orc_eval_at(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
                        const uint8_t *kind, double eps, const double *R, const double *p,
-                       int32_t *jlo, int32_t *jhi, double *xlo, double *xhi, orc_eval *E)
+                       int32_t *jlo, int32_t *jhi, double *xlo, double *xhi, const double *d,
+                       orc_eval *E)
 {
     double r[512];
-    if (orc_dual_eval(n, m, tdt, T, w, c, kind, eps, R, p, &E->g, r, NULL, jlo, jhi, xlo, xhi,
-                      NULL, NULL, NULL, NULL))
+    if (orc_dual_eval_d(n, m, tdt, T, w, c, kind, eps, R, p, &E->g, r, NULL, jlo, jhi, xlo, xhi,
+                        NULL, NULL, NULL, NULL, d))
         return -1;
     E->U = orc_lower_bound(n, m, tdt, T, w, c, kind, eps, R, r, jlo, jhi, xlo, xhi, NULL);
     double den = fabs(E->g) > fabs(E->U) ? fabs(E->g) : fabs(E->U);
@@ -387,9 +403,9 @@ static double amax(int m, const double *x)
  * memory is cleared (the fallback of §5).  method = 1 uses only that step.
  * Every evaluated point is tested against the tolerance; p_inout receives
  * the iterate with the smallest relative gap (the certificate reported). */
-int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
-              const uint8_t *kind, double eps, const double *R, const orc_solve_opts *opt,
-              double *p_inout, orc_solve_info *info)
+int orc_solve_d(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                const uint8_t *kind, double eps, const double *R, const orc_solve_opts *opt,
+                double *p_inout, orc_solve_info *info, const double *dem)
 {
     if (m > 512 || n < 1) return -2;
     int M = opt->mem > 0 ? opt->mem : 10;
@@ -411,7 +427,7 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
     double p[512], pn[512], d[512], q[512], al[64];
     for (int j = 0; j < m; ++j) p[j] = p_inout[j] > 0 ? p_inout[j] : 0.0;
     int evals = 0, iters = 0, npairs = 0, head = 0, sg_k = 0;
-    if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, p, jlo, jhi, xlo, xhi, E)) {
+    if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, p, jlo, jhi, xlo, xhi, dem, E)) {
         rc = -1;
         goto done;
     }
@@ -474,7 +490,7 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
                     if (pn[j] < 0.0) pn[j] = 0.0;
                     q[j] = pn[j] - p[j];
                 }
-                if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, E2)) {
+                if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, dem, E2)) {
                     rc = -1;
                     goto done;
                 }
@@ -511,7 +527,7 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
                 pn[j] = p[j] - step * E->grad[j];
                 if (pn[j] < 0.0) pn[j] = 0.0;
             }
-            if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, E2)) {
+            if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, dem, E2)) {
                 rc = -1;
                 goto done;
             }
@@ -547,6 +563,13 @@ done:
     free(E);
     free(E2);
     return rc;
+}
+
+int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+              const uint8_t *kind, double eps, const double *R, const orc_solve_opts *opt,
+              double *p_inout, orc_solve_info *info)
+{
+    return orc_solve_d(n, m, tdt, T, w, c, kind, eps, R, opt, p_inout, info, NULL);
 }
 
 /* ------------------------------------------------- initial prices -- */

@@ -565,3 +565,59 @@ def test_alpha_fair_initial_prices_gradient():
         e[j] = h
         fd = (phi((R + e) / n) - phi((R - e) / n)) / (2 * h)
         assert p[j] == pytest.approx(fd, rel=1e-7)
+
+
+# ------------------------------------ per-job demands (extensions) ----
+
+def test_uniform_demand_is_a_rescaling():
+    """Demand d_i = 2 for every job with limits 2R is the same primal problem
+    as d = 1 with R: at prices p/2 the dual value, every job's allocation and
+    (twice) the usage agree."""
+    I = _inst(300, 4, 40)
+    rng = np.random.default_rng(41)
+    p = 0.2 + rng.random(4) * 2
+    a = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+    b = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, 2 * I.R, p / 2, per_job=True,
+                         d=np.full(I.n, 2.0))
+    assert b.g == pytest.approx(a.g, rel=1e-12)
+    assert np.allclose(b.r, 2 * a.r, rtol=1e-12)
+    for k in ("jlo", "jhi"):
+        assert np.array_equal(a.jobs[k], b.jobs[k])
+    assert np.allclose(a.jobs["xhi"], b.jobs["xhi"], rtol=1e-12)
+
+
+def test_demands_whole_problem_grid():
+    """Two jobs with different demands: the dual optimum equals the best
+    grid allocation with sum_i d_i x_i <= R (strong duality)."""
+    rng = np.random.default_rng(42)
+    for _ in range(3):
+        n, m = 2, 2
+        T = 0.3 + rng.random((n, m))
+        w = 0.5 + rng.random(n)
+        c = np.zeros(n)
+        kind = np.zeros(n, np.uint8)
+        d = np.array([1.0, 2.5])
+        R = np.array([0.9, 0.8])
+        eps, h = 0.05, 0.02
+        Ug = brute.problem_grid(T, kind, w, c, eps, R, h=h, d=d)
+        p, info = oracle.solve(T, w, c, kind, eps, R, tol_rel=1e-10, max_iter=400, d=d)
+        Lip = float(np.max(w[:, None] * T) / eps) * 2
+        assert Ug <= info["g"] + 1e-7
+        assert info["g"] <= Ug + Lip * h * m
+
+
+def test_demands_kkt_at_optimum():
+    """With heterogeneous demands: at the solution, usage r = sum_i d_i x_i
+    respects R up to the gap, and prices are zero on slack resources.  (Log
+    jobs alone would not show the demands: x = w / (d p) makes d x
+    independent of d; capped-linear jobs do.)"""
+    I = _inst(2000, 3, 43)
+    d = 0.5 + np.random.default_rng(44).random(I.n) * 2
+    p, info = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=1e-9, max_iter=400, d=d)
+    assert info["rel_gap"] <= 1e-4  # the recovery's floor for n = 2000 with capped jobs
+    r = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, d=d).r
+    assert np.all(r <= I.R * (1 + 5e-3))
+    assert np.all(p * np.abs(I.R - r) <= 5e-3 * np.abs(p @ I.R) + 1e-9)
+    # a demand-blind usage would not balance: sum_i x_i differs from R
+    r1 = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p).r
+    assert np.max(np.abs(r1 - I.R) / I.R) > 0.01
