@@ -170,6 +170,18 @@ typedef struct {
  * stall_evals = 0 (off), init_step = 0 (default step), tol_abs = 0 (off). */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
+/* Per-job demands (§7, "Extensions and variations"): the usage limit becomes
+ * sum_i d_i x_i <= R, so job i sees the prices d_i p and adds d_i x_i to the
+ * usage r (g, the gradient R - r, the certificate and the batched solver all
+ * follow).  x_i stays the job's time fractions (ra_get_allocation, support
+ * outputs).  d: device, n values of the problem's dtype, each > 0 and finite,
+ * copied; NULL removes the demands (all 1).  Implemented by packing w_i / d_i
+ * as the job's weight (every utility here is linear in w), so the warm-start
+ * features and the data-dependent start see w_i / d_i.  Invalidates the
+ * problem's captured evaluation graph.  On a bad value returns RA_EINVAL and
+ * leaves the problem without demands.  Errors: RA_EINVAL, RA_EDEVICE. */
+ra_status ra_problem_set_demands(ra_ctx *ctx, ra_problem *prob, const void *d);
+
 /* The paper's data-dependent starting prices (§5, "Initialization", eq.
  * e-initialization): every job gets the uniform share x = R/n of the limits
  * (R/(kappa n) when kappa = 1^T R / n > 1, so that 1^T x = 1), and

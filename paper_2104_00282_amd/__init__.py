@@ -175,6 +175,17 @@ class Problem:
         _capi.check(self.ctx.handle, _capi.lib().ra_features(self.ctx.handle, self.handle, _dptr(f)))
         return f
 
+    def set_demands(self, d):
+        """Per-job demands d (device tensor of the problem's dtype, n values
+        > 0), or None to remove them (ra_problem_set_demands)."""
+        if d is not None:
+            d = d.to(self.dtype).contiguous()
+            self._demands = d
+        else:
+            self._demands = None
+        _capi.check(self.ctx.handle, _capi.lib().ra_problem_set_demands(
+            self.ctx.handle, self.handle, _dptr(d) if d is not None else None))
+
     def init_prices(self):
         """The paper's data-dependent starting prices (ra_init_prices)."""
         p = np.zeros(self.m)

@@ -30,6 +30,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace ra {
 
 template <typename F> struct Vec2;
@@ -287,13 +289,16 @@ struct GlobalRow {
 // ------------------------------------------------------------------------
 // Dual kernel, FP32, m = M in {4, 8, 16, 32, 64}, T 16-byte aligned.
 // ------------------------------------------------------------------------
-template <int M>
+template <int M, bool DEM>
 __global__ void __launch_bounds__(256) k_dual_vec(
     const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
     const PriceBlock<float>* __restrict__ pb, float eps, double* __restrict__ partial,
     int* __restrict__ jpair, float2* __restrict__ xpair, float2* __restrict__ tpair,
-    int16_t* __restrict__ j1out)
+    int16_t* __restrict__ j1out, const float* __restrict__ dem)
 {
+    // dem (optional): per-job demands d_i; prm then holds w_i / d_i, so each
+    // job is solved at prices p unchanged, and its net value, usage and
+    // certificate terms are scaled by d_i (the subproblem at prices d_i p)
     constexpr int Q = M / 4;                    // 16-byte chunks per row
     constexpr int S = M + ((Q & 1) ? 0 : 4);    // LDS row stride in words
     constexpr int TR = 64;                      // rows per wave tile
@@ -324,6 +329,7 @@ __global__ void __launch_bounds__(256) k_dual_vec(
     float* tl = tile[wv];
     float4 pre[Q];
     float2 wcn = make_float2(0.f, 0.f);
+    float dn = 1.f;
 
     auto load_tile = [&](int64_t tix) {
         const int64_t row0 = tix * TR;
@@ -333,6 +339,7 @@ __global__ void __launch_bounds__(256) k_dual_vec(
 #pragma unroll
             for (int k = 0; k < Q; ++k) pre[k] = stream_load(src + lane + 64 * k);
             wcn = prm[row0 + lane];
+            if constexpr (DEM) dn = dem[row0 + lane];
         } else {
             const int valid = (int)rows * Q;
 #pragma unroll
@@ -341,6 +348,7 @@ __global__ void __launch_bounds__(256) k_dual_vec(
                 pre[k] = (ch < valid) ? stream_load(src + ch) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
             wcn = (lane < rows) ? prm[row0 + lane] : make_float2(1.f, -1.f);
+            if constexpr (DEM) dn = (lane < rows) ? dem[row0 + lane] : 1.f;
         }
     };
 
@@ -370,6 +378,7 @@ __global__ void __launch_bounds__(256) k_dual_vec(
             *reinterpret_cast<float4*>(tl + r * S + 4 * q) = pre[k];
         }
         const float2 wc = wcn;
+        const float dj = DEM ? dn : 1.f;
         wave_sync();
         flush_outputs();
         if (ti + nw < ntiles) load_tile(ti + nw);
@@ -390,17 +399,17 @@ __global__ void __launch_bounds__(256) k_dual_vec(
             Job<float> J;
             const bool caplin = wc.y >= 0.f;
             solve_job<float, M>(row, M, P, IP, ptab, wc.x, wc.y, caplin, eps, J);
-            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], J.xhi);
-            vacc += (double)J.v;
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], dj * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], dj * J.xhi);
+            vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<float> K;
                 solve_job<float, M>(row, M, Qp, IQ, qtab, wc.x, wc.y, caplin, eps, K);
                 float u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab,
                                u, loss);
-                uacc += (double)u;
-                duacc += (double)loss;
+                uacc += (double)u * (double)dj;
+                duacc += (double)loss * (double)dj;
             }
             pend_i = i;
             pend_jp = (J.jlo & 0xffff) | (J.jhi << 16);
@@ -450,7 +459,7 @@ __global__ void __launch_bounds__(256) k_dual_gen(
     const F* __restrict__ T, const V2<F>* __restrict__ prm, int64_t n, int m,
     const PriceBlock<F>* __restrict__ pb, F eps, double* __restrict__ partial,
     int* __restrict__ jpair, V2<F>* __restrict__ xpair, V2<F>* __restrict__ tpair,
-    int16_t* __restrict__ j1out)
+    int16_t* __restrict__ j1out, const F* __restrict__ dem)
 {
     constexpr int TR = 64;
     __shared__ F hist[4][256];
@@ -474,18 +483,19 @@ __global__ void __launch_bounds__(256) k_dual_gen(
             const V2<F> wc = prm[i];
             Job<F> J;
             const bool caplin = wc.y >= F(0);
+            const F dj = dem ? dem[i] : F(1);
             solve_job<F, 0>(row, m, P, IP, P, wc.x, wc.y, caplin, eps, J);
-            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], J.xhi);
-            vacc += (double)J.v;
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], dj * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], dj * J.xhi);
+            vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<F> K;
                 solve_job<F, 0>(row, m, pb->q, pb->invq, pb->q, wc.x, wc.y, caplin, eps, K);
                 F u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, pb->s, pb->sc,
                                u, loss);
-                uacc += (double)u;
-                duacc += (double)loss;
+                uacc += (double)u * (double)dj;
+                duacc += (double)loss * (double)dj;
             }
             if (jpair) jpair[i] = (J.jlo & 0xffff) | (J.jhi << 16);
             if (xpair) xpair[i] = V2<F>{J.xlo, J.xhi};
@@ -541,7 +551,8 @@ constexpr int BATCH_LDS_WAVE = 3072;  // max over m of batch_rows(m) x padded st
 
 template <int M>
 __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, const float* tl,
-                                              const float2 (&wc)[8], float* hist,
+                                              const float2 (&wc)[8], const float (&dm)[8],
+                                              float* hist,
                                               const float* __restrict__ P,
                                               const float* __restrict__ IP,
                                               const float* __restrict__ Qp,
@@ -574,17 +585,17 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
             const bool caplin = wc[k].y >= 0.f;
             Job<float> J;
             solve_job<float, M>(row, M, P, IP, ptab, wc[k].x, wc[k].y, caplin, eps, J);
-            if (J.jlo >= 0) atomicAdd(&hist[J.jlo], J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[J.jhi], J.xhi);
-            vacc += (double)J.v;
+            if (J.jlo >= 0) atomicAdd(&hist[J.jlo], dm[k] * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[J.jhi], dm[k] * J.xhi);
+            vacc += (double)J.v * (double)dm[k];
             if (prev) {
                 Job<float> K;
                 solve_job<float, M>(row, M, Qp, IQ, qtab, wc[k].x, wc[k].y, caplin, eps, K);
                 float u, loss;
                 scaled_utility(caplin, wc[k].x, wc[k].y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab,
                                sctab, u, loss);
-                uacc += (double)u;
-                duacc += (double)loss;
+                uacc += (double)u * (double)dm[k];
+                duacc += (double)loss * (double)dm[k];
             }
         }
     }
@@ -596,7 +607,8 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
     wave_sync();
 }
 
-__global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict__ items,
+template <bool DEM>
+__global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem* __restrict__ items,
                                                     const float* __restrict__ prices,
                                                     const int* __restrict__ chunk,
                                                     const int* __restrict__ segbase,
@@ -623,6 +635,7 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
     // (items[A].tile0 is the total tile count, so the scans stop)
     float4 pre[8];
     float2 wcn[8];
+    float dmn[8];
     int an = 0, nrows = 0;
     auto load = [&](int t) {
         while (items[an + 1].tile0 <= t) ++an;
@@ -643,6 +656,17 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
         for (int k = 0; k < 8; ++k) {
             const int r = 64 * k + lane;
             wcn[k] = (r < rows) ? load_global(nx.prm + row0 + r) : make_float2(1.f, -1.f);
+        }
+        if (DEM && nx.dem) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int r = 64 * k + lane;
+                dmn[k] = (r < rows) ? *(__attribute__((address_space(1))) const float*)(nx.dem + row0 + r)
+                                    : 1.f;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dmn[k] = 1.f;
         }
         nrows = rows;
     };
@@ -702,8 +726,12 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
                 *reinterpret_cast<float4*>(tl + (ch >> lq) * S + 4 * (ch & (Q - 1))) = pre[k];
         }
         float2 wc[8];
+        float dm[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) wc[k] = wcn[k];
+        for (int k = 0; k < 8; ++k) {
+            wc[k] = wcn[k];
+            dm[k] = dmn[k];
+        }
         wave_sync();
         if (t + 1 < t1) load(t + 1);
         const bool prev = it.has_prev != 0;
@@ -713,19 +741,19 @@ __global__ void __launch_bounds__(256) k_dual_batch(const BatchItem* __restrict_
         const float* sct = tabs[wv][3];
         switch (m) {
         case 4:
-            batch_compute<4>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+            batch_compute<4>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
                              vacc, uacc, duacc);
             break;
         case 8:
-            batch_compute<8>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+            batch_compute<8>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
                              vacc, uacc, duacc);
             break;
         case 16:
-            batch_compute<16>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+            batch_compute<16>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
                               racc, vacc, uacc, duacc);
             break;
         default:
-            batch_compute<32>(it, rows, tl, wc, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+            batch_compute<32>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
                               racc, vacc, uacc, duacc);
             break;
         }
@@ -964,7 +992,8 @@ __global__ void __launch_bounds__(256) k_lower(const int* __restrict__ jpair,
                                                const V2<F>* __restrict__ prm, int64_t n, int m,
                                                const double* __restrict__ R,
                                                const double* __restrict__ r, F eps,
-                                               double* __restrict__ partial2)
+                                               double* __restrict__ partial2,
+                                               const F* __restrict__ dem)
 {
     __shared__ F s[256];
     __shared__ F sc[256];
@@ -985,8 +1014,9 @@ __global__ void __launch_bounds__(256) k_lower(const int* __restrict__ jpair,
         const V2<F> wc = prm[i];
         F u, loss;
         scaled_utility(wc.y >= F(0), wc.x, wc.y, eps, jlo, jhi, tp.x, tp.y, s, sc, u, loss);
-        U += (double)u;
-        du += (double)loss;
+        const double dj = dem ? (double)dem[i] : 1.0;
+        U += (double)u * dj;
+        du += (double)loss * dj;
     }
     for (int off = 32; off > 0; off >>= 1) {
         U += __shfl_xor(U, off);
@@ -1096,11 +1126,11 @@ int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok)
     }
     if (occ[slot] == 0) {
         switch (slot) {
-        case 0: occ[slot] = occupancy_blocks(k_dual_vec<4>); break;
-        case 1: occ[slot] = occupancy_blocks(k_dual_vec<8>); break;
-        case 2: occ[slot] = occupancy_blocks(k_dual_vec<16>); break;
-        case 3: occ[slot] = occupancy_blocks(k_dual_vec<32>); break;
-        case 4: occ[slot] = occupancy_blocks(k_dual_vec<64>); break;
+        case 0: occ[slot] = occupancy_blocks(k_dual_vec<4, false>); break;
+        case 1: occ[slot] = occupancy_blocks(k_dual_vec<8, false>); break;
+        case 2: occ[slot] = occupancy_blocks(k_dual_vec<16, false>); break;
+        case 3: occ[slot] = occupancy_blocks(k_dual_vec<32, false>); break;
+        case 4: occ[slot] = occupancy_blocks(k_dual_vec<64, false>); break;
         case 5: occ[slot] = occupancy_blocks(k_dual_gen<float>); break;
         default: occ[slot] = occupancy_blocks(k_dual_gen<double>); break;
         }
@@ -1114,7 +1144,8 @@ int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok)
 
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
                        const void* prm, int64_t n, const void* prices, double eps,
-                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1)
+                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1,
+                       const void* dem)
 {
     int* jp = reinterpret_cast<int*>(jpair);
     if (dtype == 0) {
@@ -1124,22 +1155,35 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
         float2* xp = static_cast<float2*>(xpair);
         float2* tp = static_cast<float2*>(tpair);
         const float e = (float)eps;
+        const float* df = static_cast<const float*>(dem);
+#define DUAL_VEC(MM)                                                                        \
+    do {                                                                                    \
+        if (df)                                                                             \
+            k_dual_vec<MM, true><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, \
+                                                       j1, df);                             \
+        else                                                                                \
+            k_dual_vec<MM, false><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp,    \
+                                                        tp, j1, nullptr);                   \
+    } while (0)
         if (vec_ok && vec_class(m)) {
             switch (m) {
-            case 4: k_dual_vec<4><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
-            case 8: k_dual_vec<8><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
-            case 16: k_dual_vec<16><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
-            case 32: k_dual_vec<32><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
-            default: k_dual_vec<64><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, j1); break;
+            case 4: DUAL_VEC(4); break;
+            case 8: DUAL_VEC(8); break;
+            case 16: DUAL_VEC(16); break;
+            case 32: DUAL_VEC(32); break;
+            default: DUAL_VEC(64); break;
             }
         } else {
-            k_dual_gen<float><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp, tp, j1);
+            k_dual_gen<float><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp, tp, j1,
+                                                    df);
         }
+#undef DUAL_VEC
     } else {
         k_dual_gen<double><<<grid, 256, 0, st>>>(
             static_cast<const double*>(T), static_cast<const double2*>(prm), n, m,
             static_cast<const PriceBlock<double>*>(prices), eps, partial, jp,
-            static_cast<double2*>(xpair), static_cast<double2*>(tpair), j1);
+            static_cast<double2*>(xpair), static_cast<double2*>(tpair), j1,
+            static_cast<const double*>(dem));
     }
     return hipGetLastError();
 }
@@ -1175,16 +1219,19 @@ hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
 int batch_blocks_per_cu()
 {
     static int occ = 0;
-    if (occ == 0) occ = occupancy_blocks(k_dual_batch);
+    if (occ == 0) occ = occupancy_blocks(k_dual_batch<false>);
     return occ;
 }
 
 hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
                         const float* prices, const int* chunk, const int* segbase,
                         const int* seg, const int* header, double* partial, double* out,
-                        unsigned* ticket, unsigned* flag)
+                        unsigned* ticket, unsigned* flag, bool demands)
 {
-    k_dual_batch<<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+    if (demands)
+        k_dual_batch<true><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+    else
+        k_dual_batch<false><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
     const int rgrid = max_items < 256 ? max_items : 256;
     k_batch_reduce<<<rgrid, 256, 0, st>>>(partial, seg, header, out, ticket, flag);
     return hipGetLastError();
@@ -1207,17 +1254,86 @@ int lower_grid(int dev_cus, int64_t n)
 
 hipError_t launch_lower(int dtype, int grid, hipStream_t st, const int16_t* jpair,
                         const void* tpair, const void* prm, int64_t n, int m, const double* R,
-                        const double* r, double eps, double* partial2)
+                        const double* r, double eps, double* partial2, const void* dem)
 {
     const int* jp = reinterpret_cast<const int*>(jpair);
     if (dtype == 0)
         k_lower<float><<<grid, 256, 0, st>>>(jp, static_cast<const float2*>(tpair),
                                              static_cast<const float2*>(prm), n, m, R, r,
-                                             (float)eps, partial2);
+                                             (float)eps, partial2, static_cast<const float*>(dem));
     else
         k_lower<double><<<grid, 256, 0, st>>>(jp, static_cast<const double2*>(tpair),
                                               static_cast<const double2*>(prm), n, m, R, r, eps,
-                                              partial2);
+                                              partial2, static_cast<const double*>(dem));
+    return hipGetLastError();
+}
+
+namespace {
+// Per-job demands (§7, extensions): w0 holds the weights as packed, dem the
+// demands; the packed weight becomes w0 / d (a job solved at prices d p with
+// weight w is solved at prices p with weight w / d, its utilities being
+// linear in w).  bad |= 1 for a demand that is not positive and finite.
+template <typename F>
+__global__ void k_apply_demands(const F* __restrict__ d, const F* __restrict__ w0, int64_t n,
+                                V2<F>* __restrict__ prm, F* __restrict__ dem, int* __restrict__ bad)
+{
+    int flag = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const F di = d ? d[i] : F(1);
+        if (!(di > F(0)) || !isfinite(di)) flag = 1;
+        dem[i] = di;
+        prm[i].x = w0[i] / di;
+    }
+    if (flag) atomicOr(bad, 1);
+}
+
+template <typename F>
+__global__ void k_weights(const V2<F>* __restrict__ prm, int64_t n, F* __restrict__ w0)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        w0[i] = prm[i].x;
+}
+
+template <typename F>
+__global__ void k_restore_weights(const F* __restrict__ w0, int64_t n, V2<F>* __restrict__ prm)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        prm[i].x = w0[i];
+}
+}  // namespace
+
+hipError_t launch_demands(int dtype, hipStream_t st, int op, const void* d, void* w0, int64_t n,
+                          void* prm, void* dem, int* bad)
+{
+    const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    if (dtype == 0) {
+        if (op == 0)
+            k_weights<float><<<grid, 256, 0, st>>>(static_cast<const float2*>(prm), n,
+                                                   static_cast<float*>(w0));
+        else if (op == 1)
+            k_apply_demands<float><<<grid, 256, 0, st>>>(static_cast<const float*>(d),
+                                                         static_cast<const float*>(w0), n,
+                                                         static_cast<float2*>(prm),
+                                                         static_cast<float*>(dem), bad);
+        else
+            k_restore_weights<float><<<grid, 256, 0, st>>>(static_cast<const float*>(w0), n,
+                                                           static_cast<float2*>(prm));
+    } else {
+        if (op == 0)
+            k_weights<double><<<grid, 256, 0, st>>>(static_cast<const double2*>(prm), n,
+                                                    static_cast<double*>(w0));
+        else if (op == 1)
+            k_apply_demands<double><<<grid, 256, 0, st>>>(static_cast<const double*>(d),
+                                                          static_cast<const double*>(w0), n,
+                                                          static_cast<double2*>(prm),
+                                                          static_cast<double*>(dem), bad);
+        else
+            k_restore_weights<double><<<grid, 256, 0, st>>>(static_cast<const double*>(w0), n,
+                                                            static_cast<double2*>(prm));
+    }
     return hipGetLastError();
 }
 

@@ -49,6 +49,8 @@ struct ra_problem {
     double* h_out = nullptr;    // fine-grained host memory: m + 3 results, then the flag
     unsigned* h_flag = nullptr; // set to 1 by the reduction when a solver pass is done
     unsigned* ticket = nullptr; // device block counter of that reduction
+    void* dem = nullptr;        // per-job demands (dtype, n), or NULL
+    void* w0 = nullptr;         // the weights as packed before demands were applied
     int16_t* jpair_ws = nullptr;
     void* tpair_ws = nullptr;
     void* xpair_ws = nullptr;

@@ -41,6 +41,7 @@ struct BatchItem {
     int tile0;           // first tile of this problem in the batch's tile space
     float eps;
     int has_prev;        // the pass also certifies the problem's previous prices
+    const float* dem;    // per-job demands, or NULL
 };
 
 // Batched evaluation: k_dual_batch (grid blocks of 4 waves; wave w covers
@@ -54,7 +55,8 @@ int batch_blocks_per_cu();
 hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
                         const float* prices, const int* chunk, const int* segbase,
                         const int* seg, const int* header, double* partial, double* out,
-                        unsigned* ticket = nullptr, unsigned* flag = nullptr);
+                        unsigned* ticket = nullptr, unsigned* flag = nullptr,
+                        bool demands = false);
 
 // Number of blocks one dual-kernel launch uses for n jobs with m resources.
 int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);
@@ -65,7 +67,8 @@ int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);
 // tpair (n x 2 F, a_lo x_lo and a_hi x_hi), j1 (n int16).
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
                        const void* prm, int64_t n, const void* prices, double eps,
-                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1);
+                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1,
+                       const void* dem = nullptr);
 
 // Data-dependent starting prices: partial [grid][m] gets, per block, the sums
 // of u_i'(a_i^T x) a_ij with x = prices->p (the uniform share of R).
@@ -85,7 +88,12 @@ hipError_t launch_reduce_cols(hipStream_t st, const double* partial, int nb, int
 int lower_grid(int dev_cus, int64_t n);
 hipError_t launch_lower(int dtype, int grid, hipStream_t st, const int16_t* jpair,
                         const void* tpair, const void* prm, int64_t n, int m, const double* R,
-                        const double* r, double eps, double* partial2);
+                        const double* r, double eps, double* partial2, const void* dem = nullptr);
+
+// Per-job demands: op 0 copies the packed weights into w0; op 1 checks d
+// (NULL = all 1) into dem and packs w0 / d; op 2 restores the weights from w0.
+hipError_t launch_demands(int dtype, hipStream_t st, int op, const void* d, void* w0, int64_t n,
+                          void* prm, void* dem, int* bad);
 
 // Pack (w, c, kind) into one 2-vector per job: (w, c) for capped-linear jobs,
 // (w, -1) for log jobs. bad gets bit 1 for w <= 0 / non-finite, bit 2 for a

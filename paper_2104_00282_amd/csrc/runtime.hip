@@ -117,7 +117,7 @@ ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_
     if (ctx->timing) RA_HIP(ctx, hipEventRecord(ctx->ev0, st));
     RA_HIP(ctx, ra::launch_dual(P->dt, P->m, P->vec_ok, P->grid, st, P->T, P->prm, P->n,
                                 P->pblock, P->eps, P->partial, jp, jpair_user ? xpair_user : nullptr,
-                                tp, j1_user));
+                                tp, j1_user, P->dem));
     if (ctx->timing) {
         RA_HIP(ctx, hipEventRecord(ctx->ev1, st));
         ctx->timed_pending = true;
@@ -130,7 +130,7 @@ ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_
     RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial, P->grid, ra::partial_cols(P->m), P->dout));
     if (lb) {
         RA_HIP(ctx, ra::launch_lower(P->dt, P->lgrid, st, jp, tp, P->prm, P->n, P->m, P->Rdev,
-                                     P->dout, P->eps, P->partial2));
+                                     P->dout, P->eps, P->partial2, P->dem));
         RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial2, P->lgrid, 2, P->dout + P->m + 1));
     }
     RA_HIP(ctx, hipMemcpyAsync(P->h_out, P->dout, sizeof(double) * (P->m + 3),
@@ -350,6 +350,8 @@ ra_status ra_problem_destroy(ra_problem* P)
     if (P->h_pblock) (void)hipHostFree(P->h_pblock);
     if (P->h_out) (void)hipHostFree(P->h_out);
     (void)hipFree(P->ticket);
+    (void)hipFree(P->dem);
+    (void)hipFree(P->w0);
     ra_ctx* ctx = P->ctx;
     delete P;
     if (ctx && --ctx->live_problems == 0 && ctx->closed) free_ctx(ctx);
@@ -571,6 +573,56 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
     return conv ? RA_OK : RA_ENOTCONV;
 }
 
+ra_status ra_problem_set_demands(ra_ctx* ctx, ra_problem* P, const void* d)
+{
+    if (!ctx || ctx->closed) return RA_EINVAL;
+    if (!P || P->ctx != ctx) return fail(ctx, RA_EINVAL, "problem is NULL or from another context");
+    RA_HIP(ctx, hipSetDevice(ctx->dev));
+    hipStream_t st = ctx->stream;
+    const size_t bytes = (size_t)P->n * elt(P->dt);
+    // captured graphs hold the previous demand pointer
+    if (P->gexec) {
+        (void)hipGraphExecDestroy(P->gexec);
+        P->gexec = nullptr;
+    }
+    if (P->graph) {
+        (void)hipGraphDestroy(P->graph);
+        P->graph = nullptr;
+    }
+    if (!d) {
+        if (!P->dem) return RA_OK;
+        RA_HIP(ctx, ra::launch_demands(P->dt, st, 2, nullptr, P->w0, P->n, P->prm, nullptr, nullptr));
+        RA_HIP(ctx, hipStreamSynchronize(st));
+        (void)hipFree(P->dem);
+        P->dem = nullptr;
+        return RA_OK;
+    }
+    if (!P->w0) {
+        RA_HIP(ctx, hipMalloc(&P->w0, bytes));
+        RA_HIP(ctx, ra::launch_demands(P->dt, st, 0, nullptr, P->w0, P->n, P->prm, nullptr, nullptr));
+    }
+    const bool fresh = P->dem == nullptr;
+    if (fresh) RA_HIP(ctx, hipMalloc(&P->dem, bytes));
+    int* dbad = nullptr;
+    RA_HIP(ctx, hipMalloc((void**)&dbad, sizeof(int)));
+    int bad = 0;
+    hipError_t e = hipMemsetAsync(dbad, 0, sizeof(int), st);
+    if (e == hipSuccess) e = ra::launch_demands(P->dt, st, 1, d, P->w0, P->n, P->prm, P->dem, dbad);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dbad);
+    if (e != hipSuccess) return fail(ctx, RA_EDEVICE, "set demands: %s", hipGetErrorString(e));
+    if (bad) {
+        // leave the problem as it was before demands: weights restored, no demands
+        RA_HIP(ctx, ra::launch_demands(P->dt, st, 2, nullptr, P->w0, P->n, P->prm, nullptr, nullptr));
+        RA_HIP(ctx, hipStreamSynchronize(st));
+        (void)hipFree(P->dem);
+        P->dem = nullptr;
+        return fail(ctx, RA_EINVAL, "demands must be positive and finite");
+    }
+    return RA_OK;
+}
+
 ra_status ra_init_prices(ra_ctx* ctx, const ra_problem* prob, double* p_out)
 {
     if (!ctx || ctx->closed) return RA_EINVAL;
@@ -757,6 +809,7 @@ struct BatchWs {
     char* htab = nullptr;
     double* partial = nullptr;
     bool used = false;
+    bool demands = false;  // some problem of the batch has per-job demands
     hipStream_t st_sync = nullptr;
     double* hout = nullptr;     // fine-grained host memory: B rows of results, then the flag
     unsigned* hflag = nullptr;
@@ -844,6 +897,7 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
         it[a].eps = (float)P->eps;
         const ra::Point* prev = L.pending();
         it[a].has_prev = prev ? 1 : 0;
+        it[a].dem = static_cast<const float*>(P->dem);
         float* row = pr + (size_t)a * 6 * ra::BATCH_MAX_M;
         const std::vector<double>& nx = L.next();
         p_eval[a].resize(P->m);
@@ -920,7 +974,7 @@ ra_status batch_enqueue(ra_ctx* ctx, BatchWs& ws, int grid)
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_segbase),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_seg),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_header), ws.partial,
-                                 ws.hout, ws.ticket, ws.hflag));
+                                 ws.hout, ws.ticket, ws.hflag, ws.demands));
     return RA_OK;
 }
 
@@ -1059,6 +1113,7 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     const int Wmax = ctx->cus * occ * 4;
     BatchWs ws;
     if (batch_alloc(ctx, ws, B, Wmax) != RA_OK) return RA_ENOMEM;
+    for (int b = 0; b < B; ++b) ws.demands = ws.demands || P[b]->dem != nullptr;
     const bool graph = o.use_graph && ctx->stream != nullptr;
 
     // grid: tuned per batch shape (timing one round per candidate)
