@@ -54,11 +54,12 @@ template <typename F>
 __device__ __forceinline__ F afair_exponent(F c) { return -c - F(2); }
 
 // u(t) of §2.2: log utility w log(t + eps) or capped linear w min(t, c).
-template <typename F>
+// AF = false compiles the alpha-fair branches out (for problems without such jobs).
+template <typename F, bool AF = true>
 __device__ __forceinline__ F utility(bool caplin, F w, F c, F eps, F t)
 {
     if (caplin) return w * (t < c ? t : c);
-    if (c == F(-1)) return w * dlog(t + eps);
+    if (!AF || c == F(-1)) return w * dlog(t + eps);
     const F e = F(1) - afair_exponent(c);
     return w * dpow(t + eps, e) / e;
 }
@@ -140,7 +141,7 @@ __device__ __forceinline__ int scan_next(const Row& a, int mm, const F* __restri
 // a.get(j): entry j in an unrolled scan; a.at(j): entry j for a per-lane j;
 // P, IP: prices and reciprocals (wave-uniform); Pdyn: prices for a per-lane
 // index.
-template <typename F, int M, class Row>
+template <typename F, int M, class Row, bool AF = true>
 __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restrict__ P,
                                           const F* __restrict__ IP, const F* Pdyn, F w, F c,
                                           bool caplin, F eps, Job<F>& J)
@@ -163,7 +164,7 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
             // alpha-fair family: (w / alpha)^(1/a) - eps, and for a = 0
             // (linear) the right end if w > alpha, else the left end
             F tu;
-            if (c == F(-1)) {
+            if (!AF || c == F(-1)) {
                 tu = w * den / num - eps;
             } else {
                 const F a = afair_exponent(c);
@@ -202,7 +203,7 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
     const F xh = (t - alo) * rden;
     const F xl = (lo >= 0) ? (ahi - t) * rden : F(0);
     J.j1 = j1;
-    J.v = utility(caplin, w, c, eps, t) - (plo * xl + phi * xh);
+    J.v = utility<F, AF>(caplin, w, c, eps, t) - (plo * xl + phi * xh);
     // a zero share is not part of the support; a single resource is
     // reported as (j_lo, j_hi) = (-1, j).  Written with selects only, so the
     // result stays in registers.
@@ -225,15 +226,15 @@ __device__ __forceinline__ double dlog1p(double x) { return log1p(x); }
 // utility lost, du = u(t) - u(t~), is formed from t - t~ = (1 - s_lo) tlo +
 // (1 - s_hi) thi (1 - s_j given in FP64-rounded form) so that it keeps its
 // relative accuracy when the scales are close to 1.
-template <typename F>
+template <typename F, bool AF = true>
 __device__ __forceinline__ void scaled_utility(bool caplin, F w, F c, F eps, int jlo, int jhi,
                                                F tlo, F thi, const F* S, const F* SC, F& U,
                                                F& du)
 {
     const F tt = (jlo >= 0 ? S[jlo] * tlo : F(0)) + (jhi >= 0 ? S[jhi] * thi : F(0));
     const F dt = (jlo >= 0 ? SC[jlo] * tlo : F(0)) + (jhi >= 0 ? SC[jhi] * thi : F(0));
-    U = utility(caplin, w, c, eps, tt);
-    if (!caplin && c == F(-1)) {
+    U = utility<F, AF>(caplin, w, c, eps, tt);
+    if (!caplin && (!AF || c == F(-1))) {
         du = w * dlog1p(dt / (tt + eps));
     } else if (!caplin) {
         // u(t) - u(t~) = U ((1 + dt / (t~ + eps))^(1 - a) - 1)
@@ -549,7 +550,7 @@ __global__ void __launch_bounds__(256) k_dual_gen(
 // ------------------------------------------------------------------------
 constexpr int BATCH_LDS_WAVE = 3072;  // max over m of batch_rows(m) x padded stride (m = 8)
 
-template <int M>
+template <int M, bool AF>
 __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, const float* tl,
                                               const float2 (&wc)[8], const float (&dm)[8],
                                               float* hist,
@@ -584,16 +585,18 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
             }
             const bool caplin = wc[k].y >= 0.f;
             Job<float> J;
-            solve_job<float, M>(row, M, P, IP, ptab, wc[k].x, wc[k].y, caplin, eps, J);
+            solve_job<float, M, RegRow<M>, AF>(row, M, P, IP, ptab, wc[k].x, wc[k].y, caplin,
+                                               eps, J);
             if (J.jlo >= 0) atomicAdd(&hist[J.jlo], dm[k] * J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[J.jhi], dm[k] * J.xhi);
             vacc += (double)J.v * (double)dm[k];
             if (prev) {
                 Job<float> K;
-                solve_job<float, M>(row, M, Qp, IQ, qtab, wc[k].x, wc[k].y, caplin, eps, K);
+                solve_job<float, M, RegRow<M>, AF>(row, M, Qp, IQ, qtab, wc[k].x, wc[k].y, caplin,
+                                                   eps, K);
                 float u, loss;
-                scaled_utility(caplin, wc[k].x, wc[k].y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab,
-                               sctab, u, loss);
+                scaled_utility<float, AF>(caplin, wc[k].x, wc[k].y, eps, K.jlo, K.jhi, K.tlo,
+                                          K.thi, stab, sctab, u, loss);
                 uacc += (double)u * (double)dm[k];
                 duacc += (double)loss * (double)dm[k];
             }
@@ -607,7 +610,7 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
     wave_sync();
 }
 
-template <bool DEM>
+template <bool DEM, bool AF>
 __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem* __restrict__ items,
                                                     const float* __restrict__ prices,
                                                     const int* __restrict__ chunk,
@@ -741,19 +744,19 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
         const float* sct = tabs[wv][3];
         switch (m) {
         case 4:
-            batch_compute<4>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+            batch_compute<4, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
                              vacc, uacc, duacc);
             break;
         case 8:
-            batch_compute<8>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+            batch_compute<8, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
                              vacc, uacc, duacc);
             break;
         case 16:
-            batch_compute<16>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+            batch_compute<16, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
                               racc, vacc, uacc, duacc);
             break;
         default:
-            batch_compute<32>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+            batch_compute<32, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
                               racc, vacc, uacc, duacc);
             break;
         }
@@ -1057,6 +1060,7 @@ __global__ void k_pack(const F* __restrict__ w, const F* __restrict__ c,
             const F a = c[i];
             if (!(a >= F(0)) || !isfinite(a)) flags |= 2;
             ci = (a == F(1)) ? F(-1) : -(F(2) + a);
+            if (a != F(1)) flags |= 16;  // the problem has alpha-fair jobs (not an error)
         } else if (k > 2) {
             flags |= 4;
         }
@@ -1219,19 +1223,23 @@ hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
 int batch_blocks_per_cu()
 {
     static int occ = 0;
-    if (occ == 0) occ = occupancy_blocks(k_dual_batch<false>);
+    if (occ == 0) occ = occupancy_blocks(k_dual_batch<false, false>);
     return occ;
 }
 
 hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
                         const float* prices, const int* chunk, const int* segbase,
                         const int* seg, const int* header, double* partial, double* out,
-                        unsigned* ticket, unsigned* flag, bool demands)
+                        unsigned* ticket, unsigned* flag, bool demands, bool alpha_fair)
 {
-    if (demands)
-        k_dual_batch<true><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+    if (demands && alpha_fair)
+        k_dual_batch<true, true><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+    else if (demands)
+        k_dual_batch<true, false><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+    else if (alpha_fair)
+        k_dual_batch<false, true><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
     else
-        k_dual_batch<false><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+        k_dual_batch<false, false><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
     const int rgrid = max_items < 256 ? max_items : 256;
     k_batch_reduce<<<rgrid, 256, 0, st>>>(partial, seg, header, out, ticket, flag);
     return hipGetLastError();

@@ -49,6 +49,7 @@ struct ra_problem {
     double* h_out = nullptr;    // fine-grained host memory: m + 3 results, then the flag
     unsigned* h_flag = nullptr; // set to 1 by the reduction when a solver pass is done
     unsigned* ticket = nullptr; // device block counter of that reduction
+    bool alpha_fair = false;    // some job has an alpha-fair utility other than log
     void* dem = nullptr;        // per-job demands (dtype, n), or NULL
     void* w0 = nullptr;         // the weights as packed before demands were applied
     int16_t* jpair_ws = nullptr;

@@ -56,7 +56,7 @@ hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem
                         const float* prices, const int* chunk, const int* segbase,
                         const int* seg, const int* header, double* partial, double* out,
                         unsigned* ticket = nullptr, unsigned* flag = nullptr,
-                        bool demands = false);
+                        bool demands = false, bool alpha_fair = true);
 
 // Number of blocks one dual-kernel launch uses for n jobs with m resources.
 int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);

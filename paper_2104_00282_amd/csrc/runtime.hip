@@ -430,10 +430,12 @@ ra_status ra_problem_create(ra_ctx* ctx, ra_problem** out, int64_t n, int32_t m,
     (void)hipFree(dbad);
     if (e != hipSuccess)
         return cleanup(fail(ctx, RA_EDEVICE, "packing inputs: %s", hipGetErrorString(e)));
+    P->alpha_fair = (bad & 16) != 0;
+    bad &= ~16;
     if (validate && bad) {
         return cleanup(fail(ctx, RA_EINVAL, "invalid input:%s%s%s%s",
                             (bad & 1) ? " w <= 0 or non-finite;" : "",
-                            (bad & 2) ? " capped-linear c < 0 or non-finite;" : "",
+                            (bad & 2) ? " cap or alpha-fair exponent c < 0 or non-finite;" : "",
                             (bad & 4) ? " unknown utility kind;" : "",
                             (bad & 8) ? " T negative or non-finite;" : ""));
     }
@@ -809,7 +811,8 @@ struct BatchWs {
     char* htab = nullptr;
     double* partial = nullptr;
     bool used = false;
-    bool demands = false;  // some problem of the batch has per-job demands
+    bool demands = false;     // some problem of the batch has per-job demands
+    bool alpha_fair = false;  // some problem of the batch has alpha-fair jobs
     hipStream_t st_sync = nullptr;
     double* hout = nullptr;     // fine-grained host memory: B rows of results, then the flag
     unsigned* hflag = nullptr;
@@ -974,7 +977,7 @@ ra_status batch_enqueue(ra_ctx* ctx, BatchWs& ws, int grid)
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_segbase),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_seg),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_header), ws.partial,
-                                 ws.hout, ws.ticket, ws.hflag, ws.demands));
+                                 ws.hout, ws.ticket, ws.hflag, ws.demands, ws.alpha_fair));
     return RA_OK;
 }
 
@@ -1113,7 +1116,10 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     const int Wmax = ctx->cus * occ * 4;
     BatchWs ws;
     if (batch_alloc(ctx, ws, B, Wmax) != RA_OK) return RA_ENOMEM;
-    for (int b = 0; b < B; ++b) ws.demands = ws.demands || P[b]->dem != nullptr;
+    for (int b = 0; b < B; ++b) {
+        ws.demands = ws.demands || P[b]->dem != nullptr;
+        ws.alpha_fair = ws.alpha_fair || P[b]->alpha_fair;
+    }
     const bool graph = o.use_graph && ctx->stream != nullptr;
 
     // grid: tuned per batch shape (timing one round per candidate)
