@@ -82,11 +82,13 @@ def lib():
         L.orc_solve.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p, _p, _d, _p,
                                 ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(SolveInfo)]
         L.orc_dual_eval_d.restype = ctypes.c_int
-        L.orc_dual_eval_d.argtypes = L.orc_dual_eval.argtypes + [_p]
+        L.orc_dual_eval_d.argtypes = L.orc_dual_eval.argtypes + [_p, ctypes.c_int]
         L.orc_solve_d.restype = ctypes.c_int
-        L.orc_solve_d.argtypes = L.orc_solve.argtypes + [_p]
+        L.orc_solve_d.argtypes = L.orc_solve.argtypes + [_p, ctypes.c_int]
         L.orc_init_prices.restype = ctypes.c_int
         L.orc_init_prices.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p, _p, _d, _p, _p]
+        L.orc_init_prices_d.restype = ctypes.c_int
+        L.orc_init_prices_d.argtypes = L.orc_init_prices.argtypes + [_p, ctypes.c_int]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -143,9 +145,23 @@ class DualResult:
         return self._R - self.r
 
 
+def _demands(d, n, m):
+    """(array, columns) for optional demands: n scalars, or an n x m matrix
+    of per-job demand vectors."""
+    if d is None:
+        return None, 0
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    if dd.shape == (n,):
+        return dd, 1
+    if dd.shape == (n, m):
+        return dd, m
+    raise ValueError("demands must have shape (n,) or (n, m)")
+
+
 def dual_eval(T, w, c, kind, eps, R, p, per_job=False, d=None):
     """Dual function value, usage r and (per_job) the per-job optimum.
-    d: optional per-job demands (usage limit sum_i d_i x_i <= R)."""
+    d: optional per-job demands, n scalars or n x m vectors (usage limit
+    sum_i d_i * x_i <= R)."""
     T = np.ascontiguousarray(T)
     n, m = T.shape
     tdt = _tdt(T)
@@ -166,10 +182,10 @@ def dual_eval(T, w, c, kind, eps, R, p, per_job=False, d=None):
             "j1": np.empty(n, np.int32), "margin1": np.empty(n),
         }
         outs = [jobs[k] for k in ("jlo", "jhi", "xlo", "xhi", "t", "v", "j1", "margin1")]
-    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    dd, dc = _demands(d, n, m)
     rc = lib().orc_dual_eval_d(n, m, tdt, _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
                                _ptr(R), _ptr(p), ctypes.byref(g), _ptr(r), ctypes.byref(sv),
-                               *[_ptr(o) for o in outs], _ptr(dd))
+                               *[_ptr(o) for o in outs], _ptr(dd), dc)
     if rc != 0:
         raise MemoryError("oracle dual_eval failed")
     res = DualResult(g.value, r, sv.value, jobs)
@@ -205,16 +221,17 @@ def solve(T, w, c, kind, eps, R, p0=None, tol_rel=1e-6, max_iter=500, mem=10, me
     p = np.ones(m) if p0 is None else np.array(p0, dtype=np.float64)
     opts = SolveOpts(tol_rel, max_iter, mem, method, 0, tol_abs)
     info = SolveInfo()
-    dd = None if d is None else np.ascontiguousarray(d, dtype=np.float64)
+    dd, dc = _demands(d, n, m)
     rc = lib().orc_solve_d(n, m, _tdt(T), _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
-                           _ptr(R), ctypes.byref(opts), _ptr(p), ctypes.byref(info), _ptr(dd))
+                           _ptr(R), ctypes.byref(opts), _ptr(p), ctypes.byref(info), _ptr(dd), dc)
     if rc != 0:
         raise RuntimeError("oracle solve failed (%d)" % rc)
     return p, {f: getattr(info, f) for f, _ in SolveInfo._fields_}
 
 
-def init_prices(T, w, c, kind, eps, R):
-    """The paper's data-dependent starting prices (eq. e-initialization)."""
+def init_prices(T, w, c, kind, eps, R, d=None):
+    """The paper's data-dependent starting prices (eq. e-initialization);
+    with demands d (n or n x m), each job's term is divided by its demand."""
     T = np.ascontiguousarray(T)
     n, m = T.shape
     w = np.ascontiguousarray(w, dtype=T.dtype)
@@ -222,8 +239,9 @@ def init_prices(T, w, c, kind, eps, R):
     kind = np.ascontiguousarray(kind, dtype=np.uint8)
     R = np.ascontiguousarray(R, dtype=np.float64)
     p = np.zeros(m)
-    rc = lib().orc_init_prices(n, m, _tdt(T), _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
-                               _ptr(R), _ptr(p))
+    dd, dc = _demands(d, n, m)
+    rc = lib().orc_init_prices_d(n, m, _tdt(T), _ptr(T), _ptr(w), _ptr(c), _ptr(kind),
+                                 float(eps), _ptr(R), _ptr(p), _ptr(dd), dc)
     if rc != 0:
         raise RuntimeError("oracle init_prices failed (%d)" % rc)
     return p

@@ -112,15 +112,17 @@ def job_grid(a, p, kind, w, c, eps, h=1e-3):
 
 
 def problem_grid(T, kind, w, c, eps, R, h=0.01, d=None):
-    """max sum_i u_i(a_i^T x_i) over grid allocations with sum_i d_i x_i <= R
-    (d = 1 by default)."""
+    """max sum_i u_i(a_i^T x_i) over grid allocations with sum_i d_i * x_i <= R
+    (d = 1 by default; n scalar demands, or n x m demand vectors)."""
     n, m = T.shape
-    dd = np.ones(n) if d is None else np.asarray(d, float)
+    dd = np.ones((n, 1)) if d is None else np.asarray(d, float)
+    if dd.ndim == 1:
+        dd = dd[:, None]
     pts = list(simplex_grid(m, h))
     best = -math.inf
     for combo in itertools.product(range(len(pts)), repeat=n):
         X = np.array([pts[k] for k in combo])
-        if np.any((dd[:, None] * X).sum(0) > np.asarray(R) + 1e-12):
+        if np.any((dd * X).sum(0) > np.asarray(R) + 1e-12):
             continue
         val = sum(u(kind[i], w[i], c[i], eps, float(T[i] @ X[i])) for i in range(n))
         best = max(best, val)
@@ -183,3 +185,36 @@ def lp_linear(T, w, R):
                   method="highs")
     assert res.status == 0
     return -float(res.fun)
+
+
+def problem_slsqp_log(T, w, eps, R, d=None, starts=4, seed=0):
+    """Log utilities: max sum_i w_i log(a_i^T x_i + eps) subject to x >= 0,
+    1^T x_i <= 1 and sum_i d_i * x_i <= R (scalar or vector demands), by
+    scipy's SLSQP from a few feasible starts (a smooth concave program, so
+    every start reaches the same optimum up to the solver's tolerance)."""
+    from scipy.optimize import minimize
+    n, m = T.shape
+    dd = np.ones((n, m)) if d is None else np.broadcast_to(
+        np.asarray(d, float).reshape(n, -1), (n, m))
+    R = np.asarray(R, float)
+    f = lambda z: -float(np.sum(w * np.log((T * z.reshape(n, m)).sum(1) + eps)))
+    def grad(z):
+        X = z.reshape(n, m)
+        t = (T * X).sum(1) + eps
+        return -(w[:, None] * T / t[:, None]).ravel()
+    cons = [{"type": "ineq", "fun": lambda z: 1.0 - z.reshape(n, m).sum(1)},
+            {"type": "ineq", "fun": lambda z: R - (dd * z.reshape(n, m)).sum(0)}]
+    rng = np.random.default_rng(seed)
+    best = -math.inf
+    for _ in range(starts):
+        x0 = rng.random((n, m))
+        x0 /= x0.sum(1, keepdims=True)
+        x0 *= min(1.0, float(np.min(R / (dd * x0).sum(0)))) * 0.5
+        res = minimize(f, x0.ravel(), jac=grad, bounds=[(0.0, 1.0)] * (n * m),
+                       constraints=cons, method="SLSQP",
+                       options={"ftol": 1e-14, "maxiter": 2000})
+        X = res.x.reshape(n, m)
+        if np.all(X >= -1e-9) and np.all(X.sum(1) <= 1 + 1e-7) and \
+                np.all((dd * X).sum(0) <= R + 1e-7):
+            best = max(best, -res.fun)
+    return best

@@ -221,14 +221,22 @@ static inline double pval(const void *v, int tdt, int64_t idx)
  * T is n x m row-major, float32 (tdt = 0) or float64 (tdt = 1); w, c have
  * T's type; kind is one byte per job.  Per-job outputs may be NULL.
  * Returns 0, or -1 on an allocation failure. */
-/* With per-job demands d (NULL = all 1; §7, "Extensions and variations"):
- * the usage limit becomes sum_i d_i x_i <= R, job i sees the prices d_i p,
- * and r = sum_i d_i x_i. */
+/* With per-job demands (NULL = all 1; §7, "Extensions and variations"):
+ * the usage limit becomes sum_i d_i * x_i <= R, job i sees the prices
+ * d_i * p (elementwise), and r = sum_i d_i * x_i.  dcols = 1: one scalar
+ * demand per job (d has n entries); dcols = m: a demand vector per job (d is
+ * n x m, row-major). */
+static inline double demand(const double *d, int dcols, int64_t i, int j)
+{
+    if (!d) return 1.0;
+    return dcols == 1 ? d[i] : d[i * dcols + j];
+}
+
 int orc_dual_eval_d(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
                     const uint8_t *kind, double eps, const double *R, const double *p, double *g,
                     double *r, double *sumv_out, int32_t *jlo, int32_t *jhi, double *xlo,
                     double *xhi, double *tout, double *vout, int32_t *j1, double *margin1,
-                    const double *d)
+                    const double *d, int dcols)
 {
     int64_t nchunks = (n + ORC_CHUNK - 1) / ORC_CHUNK;
     double *part = (double *)calloc((size_t)(nchunks > 0 ? nchunks : 1) * (size_t)(m + 1),
@@ -242,12 +250,11 @@ int orc_dual_eval_d(int64_t n, int m, int tdt, const void *T, const void *w, con
         int64_t lo = ch * ORC_CHUNK, hi = lo + ORC_CHUNK < n ? lo + ORC_CHUNK : n;
         for (int64_t i = lo; i < hi; ++i) {
             for (int j = 0; j < m; ++j) a[j] = tval(T, tdt, i * m + j);
-            const double di = d ? d[i] : 1.0;
-            for (int j = 0; j < m; ++j) pd[j] = di * p[j];
+            for (int j = 0; j < m; ++j) pd[j] = demand(d, dcols, i, j) * p[j];
             orc_job J;
             orc_subproblem(m, a, pd, kind[i], pval(w, tdt, i), pval(c, tdt, i), eps, &J);
-            if (J.jlo >= 0) acc[J.jlo] += di * J.xlo;
-            if (J.jhi >= 0) acc[J.jhi] += di * J.xhi;
+            if (J.jlo >= 0) acc[J.jlo] += demand(d, dcols, i, J.jlo) * J.xlo;
+            if (J.jhi >= 0) acc[J.jhi] += demand(d, dcols, i, J.jhi) * J.xhi;
             acc[m] += J.v;
             if (jlo) jlo[i] = J.jlo;
             if (jhi) jhi[i] = J.jhi;
@@ -279,7 +286,7 @@ int orc_dual_eval(int64_t n, int m, int tdt, const void *T, const void *w, const
                   double *xhi, double *tout, double *vout, int32_t *j1, double *margin1)
 {
     return orc_dual_eval_d(n, m, tdt, T, w, c, kind, eps, R, p, g, r, sumv_out, jlo, jhi, xlo,
-                           xhi, tout, vout, j1, margin1, NULL);
+                           xhi, tout, vout, j1, margin1, NULL, 0);
 }
 
 /* Feasible allocation and its utility (§5): column j of X is scaled by
@@ -360,11 +367,11 @@ typedef struct {
 static int orc_eval_at(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
                        const uint8_t *kind, double eps, const double *R, const double *p,
                        int32_t *jlo, int32_t *jhi, double *xlo, double *xhi, const double *d,
-                       orc_eval *E)
+                       int dcols, orc_eval *E)
 {
     double r[512];
     if (orc_dual_eval_d(n, m, tdt, T, w, c, kind, eps, R, p, &E->g, r, NULL, jlo, jhi, xlo, xhi,
-                        NULL, NULL, NULL, NULL, d))
+                        NULL, NULL, NULL, NULL, d, dcols))
         return -1;
     E->U = orc_lower_bound(n, m, tdt, T, w, c, kind, eps, R, r, jlo, jhi, xlo, xhi, NULL);
     double den = fabs(E->g) > fabs(E->U) ? fabs(E->g) : fabs(E->U);
@@ -405,7 +412,7 @@ static double amax(int m, const double *x)
  * the iterate with the smallest relative gap (the certificate reported). */
 int orc_solve_d(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
                 const uint8_t *kind, double eps, const double *R, const orc_solve_opts *opt,
-                double *p_inout, orc_solve_info *info, const double *dem)
+                double *p_inout, orc_solve_info *info, const double *dem, int dcols)
 {
     if (m > 512 || n < 1) return -2;
     int M = opt->mem > 0 ? opt->mem : 10;
@@ -427,7 +434,7 @@ int orc_solve_d(int64_t n, int m, int tdt, const void *T, const void *w, const v
     double p[512], pn[512], d[512], q[512], al[64];
     for (int j = 0; j < m; ++j) p[j] = p_inout[j] > 0 ? p_inout[j] : 0.0;
     int evals = 0, iters = 0, npairs = 0, head = 0, sg_k = 0;
-    if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, p, jlo, jhi, xlo, xhi, dem, E)) {
+    if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, p, jlo, jhi, xlo, xhi, dem, dcols, E)) {
         rc = -1;
         goto done;
     }
@@ -490,7 +497,7 @@ int orc_solve_d(int64_t n, int m, int tdt, const void *T, const void *w, const v
                     if (pn[j] < 0.0) pn[j] = 0.0;
                     q[j] = pn[j] - p[j];
                 }
-                if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, dem, E2)) {
+                if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, dem, dcols, E2)) {
                     rc = -1;
                     goto done;
                 }
@@ -527,7 +534,7 @@ int orc_solve_d(int64_t n, int m, int tdt, const void *T, const void *w, const v
                 pn[j] = p[j] - step * E->grad[j];
                 if (pn[j] < 0.0) pn[j] = 0.0;
             }
-            if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, dem, E2)) {
+            if (orc_eval_at(n, m, tdt, T, w, c, kind, eps, R, pn, jlo, jhi, xlo, xhi, dem, dcols, E2)) {
                 rc = -1;
                 goto done;
             }
@@ -569,7 +576,7 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
               const uint8_t *kind, double eps, const double *R, const orc_solve_opts *opt,
               double *p_inout, orc_solve_info *info)
 {
-    return orc_solve_d(n, m, tdt, T, w, c, kind, eps, R, opt, p_inout, info, NULL);
+    return orc_solve_d(n, m, tdt, T, w, c, kind, eps, R, opt, p_inout, info, NULL, 0);
 }
 
 /* ------------------------------------------------- initial prices -- */
@@ -582,10 +589,15 @@ int orc_solve(int64_t n, int m, int tdt, const void *T, const void *w, const voi
  * log, w/(t + eps); alpha-fair, w (t + eps)^(-c); capped linear, w below
  * the cap and 0 at or above it (the right derivative, one supergradient at
  * the kink).
+ * With per-job demands (d, dcols as in orc_dual_eval_d) each job's term is
+ * u_i'(a_i^T x) a_ij / d_ij: what the job would pay per unit of resource j it
+ * demands (the paper states no start for demands; this is the formula's
+ * reading per unit of demand, and equals dividing w_i by a scalar d_i).
  * Sums run per fixed chunk of rows, then in chunk order.
  * Returns 0, or -1 on an allocation failure. */
-int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
-                    const uint8_t *kind, double eps, const double *R, double *p)
+int orc_init_prices_d(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                      const uint8_t *kind, double eps, const double *R, double *p,
+                      const double *d, int dcols)
 {
     double x[512];
     double kappa = 0.0;
@@ -611,7 +623,8 @@ int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, con
                 du = wi * pow(t + eps, -pval(c, tdt, i));
             else
                 du = t < pval(c, tdt, i) ? wi : 0.0;
-            for (int j = 0; j < m; ++j) acc[j] += du * tval(T, tdt, i * m + j);
+            for (int j = 0; j < m; ++j)
+                acc[j] += du * tval(T, tdt, i * m + j) / demand(d, dcols, i, j);
         }
     }
     for (int j = 0; j < m; ++j) p[j] = 0.0;
@@ -620,6 +633,12 @@ int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, con
     for (int j = 0; j < m; ++j) p[j] /= (double)n;
     free(part);
     return 0;
+}
+
+int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                    const uint8_t *kind, double eps, const double *R, double *p)
+{
+    return orc_init_prices_d(n, m, tdt, T, w, c, kind, eps, R, p, NULL, 0);
 }
 
 int orc_num_threads(void)

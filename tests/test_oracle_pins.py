@@ -621,3 +621,125 @@ def test_demands_kkt_at_optimum():
     # a demand-blind usage would not balance: sum_i x_i differs from R
     r1 = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p).r
     assert np.max(np.abs(r1 - I.R) / I.R) > 0.01
+
+
+# ------------------------------- per-job demand vectors (extensions) ----
+
+def test_demand_vectors_with_equal_columns_are_scalar_demands():
+    """A demand vector whose entries all equal d_i is the scalar demand d_i."""
+    I = _inst(300, 4, 45)
+    rng = np.random.default_rng(46)
+    d = 0.5 + rng.random(I.n) * 2
+    D = np.repeat(d[:, None], I.m, axis=1)
+    p = 0.2 + rng.random(4) * 2
+    a = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True, d=d)
+    b = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True, d=D)
+    assert b.g == a.g and np.array_equal(a.r, b.r)
+    for k in ("jlo", "jhi", "xlo", "xhi"):
+        assert np.array_equal(a.jobs[k], b.jobs[k])
+
+
+def test_demand_vectors_danskin_gradient():
+    """With a demand vector per job, job i pays d_ij p_j per unit of x_ij, so
+    dg/dp_j = R_j - sum_i d_ij x_ij: central differences of g in FP64 (log
+    jobs, where g is differentiable) against R - r.  A usage that ignored the
+    demands, or took them from the wrong column, fails this."""
+    I = _inst(80, 4, 47, log_frac=1.0)
+    rng = np.random.default_rng(48)
+    D = 0.4 + rng.random((I.n, I.m)) * 2.5
+    for _ in range(4):
+        p = 0.5 + rng.random(4) * 2
+        r = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, d=D).r
+        r1 = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p).r
+        assert np.max(np.abs(r - r1) / r1) > 0.05  # the demands matter here
+        for j in range(4):
+            h = 1e-6
+            e = np.zeros(4)
+            e[j] = h
+            gp = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p + e, d=D).g
+            gm = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p - e, d=D).g
+            assert (gp - gm) / (2 * h) == pytest.approx(I.R[j] - r[j], rel=1e-6, abs=1e-6)
+
+
+def test_demand_vectors_job_sees_scaled_prices():
+    """Each job's optimum under a demand vector is its subproblem at the
+    prices d_i * p (the only change the extension makes), checked by scalar
+    maximisation of u(t) - c(t) on the LP cost curve at those prices."""
+    rng = np.random.default_rng(49)
+    for _ in range(20):
+        m = 3
+        T = 0.2 + rng.random((1, m))
+        D = 0.3 + rng.random((1, m)) * 3
+        w = np.array([0.5 + rng.random()])
+        p = 0.2 + rng.random(m)
+        R = np.ones(m)
+        res = oracle.dual_eval(T, w, np.zeros(1), np.zeros(1, np.uint8), 1e-2, R, p,
+                               per_job=True, d=D)
+        pd = D[0] * p
+        t_star, v_star = brute.job_golden(T[0], pd, LOG, w[0], 0.0, 1e-2)
+        assert res.jobs["t"][0] == pytest.approx(t_star, abs=1e-5)
+        assert res.jobs["v"][0] == pytest.approx(v_star, abs=1e-7)
+
+
+def test_demand_vectors_strong_duality():
+    """Three log jobs with demand vectors: the minimum of the oracle's dual
+    function (found by a derivative-free search over p >= 0) equals the
+    primal optimum with sum_i d_ij x_ij <= R_j for every j, found by a
+    general nonlinear solver on the allocation itself (§3, strong duality).
+    (Tiny instances put the dual optimum on a kink, which the price loop
+    approaches slowly; the search here only needs function values.)"""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(50)
+    for k in range(3):
+        n, m = 3, 3
+        T = 0.3 + rng.random((n, m))
+        w = 0.5 + rng.random(n)
+        D = 0.4 + rng.random((n, m)) * 2.5
+        R = 0.4 + rng.random(m) * 0.6
+        eps, z, kind = 0.05, np.zeros(n), np.zeros(n, np.uint8)
+        Us = brute.problem_slsqp_log(T, w, eps, R, d=D, seed=k)
+        assert abs(Us - brute.problem_slsqp_log(T, w, eps, R, seed=k)) > 1e-2
+        g = lambda q: oracle.dual_eval(T, w, z, kind, eps, R, np.abs(q), d=D).g
+        best = min(minimize(g, 0.5 + rng.random(m), method="Nelder-Mead",
+                            options={"xatol": 1e-12, "fatol": 1e-14, "maxfev": 40000}).fun
+                   for _ in range(2))
+        assert best == pytest.approx(Us, abs=1e-8)
+
+
+def test_demand_vectors_kkt_at_optimum():
+    """Mixed jobs with demand vectors: at the solution the usage
+    sum_i d_ij x_ij respects R up to the gap and prices vanish on slack
+    resources; a demand-blind usage would not balance."""
+    I = _inst(2000, 3, 51)
+    D = 0.5 + np.random.default_rng(52).random((I.n, I.m)) * 2
+    p, info = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=1e-9, max_iter=400, d=D)
+    # the recovery's floor: a capped job flipping at a tie moves r_j by up to
+    # d_ij, so the floor is a few times that of unit demands
+    assert info["rel_gap"] <= 5e-4
+    r = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, d=D).r
+    assert np.all(r <= I.R * (1 + 5e-3))
+    assert np.all(p * np.abs(I.R - r) <= 5e-3 * np.abs(p @ I.R) + 1e-9)
+    r1 = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p).r
+    assert np.max(np.abs(r1 - I.R) / I.R) > 0.01
+
+
+def test_demand_vectors_init_prices():
+    """The data-dependent start with demands divides job i's term for
+    resource j by d_ij: equal columns give the start of the weights w_i / d_i,
+    and scaling column j of every demand vector by lam scales p_j by 1/lam
+    and leaves the other prices unchanged."""
+    I = _inst(500, 4, 53)
+    rng = np.random.default_rng(54)
+    d = 0.5 + rng.random(I.n) * 2
+    D = np.repeat(d[:, None], I.m, axis=1)
+    a = oracle.init_prices(I.T, I.w, I.c, I.kind, I.eps, I.R, d=D)
+    b = oracle.init_prices(I.T, I.w / d, I.c, I.kind, I.eps, I.R)
+    assert np.allclose(a, b, rtol=1e-12)
+    D = 0.5 + rng.random((I.n, I.m)) * 2
+    p0 = oracle.init_prices(I.T, I.w, I.c, I.kind, I.eps, I.R, d=D)
+    D2 = D.copy()
+    D2[:, 2] *= 4.0
+    p1 = oracle.init_prices(I.T, I.w, I.c, I.kind, I.eps, I.R, d=D2)
+    assert p1[2] == pytest.approx(p0[2] / 4, rel=1e-12)
+    for j in (0, 1, 3):
+        assert p1[j] == pytest.approx(p0[j], rel=1e-12)
