@@ -415,6 +415,68 @@ def bench_e1(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_demand_vectors(args):
+    """Per-job demand vectors (§7 extensions) on the roofline shape: n = 1e7,
+    m = 64, FP32, D_ij ~ U[0.5, 2].  Solver steps timed as in the default
+    workload (each evaluation also reads D: 2 n m 4 + 8 n bytes), the same
+    instance's steps without demands for comparison, and a cold solve to a
+    1e-4 relative gap."""
+    import torch
+    import synth
+    import paper_2104_00282_amd as ra
+
+    n, m = args.n, 64
+    log("generating demand-vector instance n=%d m=%d on the device" % (n, m))
+    I = synth.demand_vectors_device(n=n, m=m)
+    ctx = ra.Context(0)
+    prob = ra.Problem(ctx, I["T"], I["w"], I["c"], I["kind"], I["R"], I["eps"], validate=False)
+
+    def timed_steps(label):
+        p, _, _ = prob.solve(tol_rel=0.0, max_iter=args.warmup, max_evals=args.warmup)
+        ra.ra_set_kernel_timing(ctx.handle, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, _ = prob.solve(p0=p, tol_rel=0.0, max_iter=args.steps, max_evals=args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kms, launches = ra.ra_get_kernel_timing(ctx.handle)
+        ra.ra_set_kernel_timing(ctx.handle, False)
+        steps = info["dual_evals"]
+        log("%s: %d steps, %.4f ms per step, kernel %.4f ms" %
+            (label, steps, dt * 1e3 / steps, kms / max(launches, 1)))
+        return dt * 1e3 / steps, kms / max(launches, 1), launches, steps
+
+    plain_ms, plain_kms, _, _ = timed_steps("without demands")
+    prob.set_demand_vectors(I["D"])
+    ms, kms, launches, steps = timed_steps("with demand vectors")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, sinfo, _ = prob.solve(tol_rel=1e-4, max_iter=500)
+    solve_s = time.perf_counter() - t0
+    bytes_per_launch = 2 * n * m * 4 + n * 8
+    achieved = bytes_per_launch / (kms / 1e3) / 1e9
+    out = {"metric": "job·resource entries/s in the dual evaluation with per-job demand vectors",
+           "value": n * m / (ms / 1e3), "unit": "job·resource entries/s", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "demand vectors: n=%d jobs, m=%d resources, FP32 T_ij = "
+                                  "s_j exp(Z_ij), D_ij ~ U[0.5, 2], half log / half "
+                                  "capped-linear utilities, R_j = 0.125 n/m" % (n, m),
+                      "step": "one solver evaluation: dual function + gradient + lower bound "
+                              "+ L-BFGS update",
+                      "dual_kernel_ms": kms,
+                      "without_demands": {"ms_per_step": plain_ms, "dual_kernel_ms": plain_kms},
+                      "solve_to_1e-4": {"seconds": solve_s, "dual_evals": sinfo["dual_evals"],
+                                        "rel_gap": sinfo["rel_gap"]}},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "dual evaluation with demand vectors (k_dual_vec<64, false, true>)",
+                        "bytes_per_launch": bytes_per_launch, "launches": launches}}
+    prob.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def synth_seed(offset):
     import synth
     return synth.BASE_SEED + offset
@@ -430,7 +492,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale the HBM counters")
     ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
-                                           "batch-rounds", "e1"],
+                                           "batch-rounds", "e1", "demand-vectors"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
@@ -450,13 +512,14 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
-    if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1"):
+    if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1",
+                         "demand-vectors"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batched": bench_batched, "warmstart": bench_warmstart,
          "solves": bench_solves, "batch-rounds": bench_batch_rounds,
-         "e1": bench_e1}[args.workload](args)
+         "e1": bench_e1, "demand-vectors": bench_demand_vectors}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -179,8 +179,28 @@ void ra_solve_opts_default(ra_solve_opts *opts);
  * as the job's weight (every utility here is linear in w), so the warm-start
  * features and the data-dependent start see w_i / d_i.  Invalidates the
  * problem's captured evaluation graph.  On a bad value returns RA_EINVAL and
- * leaves the problem without demands.  Errors: RA_EINVAL, RA_EDEVICE. */
+ * leaves the problem without demands.  RA_EINVAL also when the problem has
+ * demand vectors (the two kinds exclude each other).
+ * Errors: RA_EINVAL, RA_EDEVICE. */
 ra_status ra_problem_set_demands(ra_ctx *ctx, ra_problem *prob, const void *d);
+
+/* Per-job demand vectors (§7, "Extensions and variations": jobs that demand
+ * different amounts of different resources): job i uses d_ij units of
+ * resource j per unit of time on it, so the usage limit becomes
+ * sum_i d_ij x_ij <= R_j, job i's subproblem (eq. e-subproblem) is solved at
+ * the prices d_i * p (elementwise), and r_j = sum_i d_ij x_ij (g, the gradient
+ * R - r, the certificate's column scaling and the data-dependent start, whose
+ * job terms become u_i' a_ij / d_ij, all follow).  x stays the jobs' time
+ * fractions.  D: device, n x m of the problem's dtype, row-major like T
+ * (16-byte aligned for the vectorised FP32 kernels, else the generic kernel
+ * runs), each entry > 0 and finite (checked in one pass); BORROWED: the
+ * caller keeps it alive and unchanged until it is removed (D = NULL) or the
+ * problem is destroyed.  Each evaluation then reads n m more values.  Not
+ * with scalar demands (RA_EINVAL), nor in ra_batch_solve (RA_EUNSUPPORTED);
+ * the learned start's features do not see D.  Invalidates the problem's
+ * captured evaluation graph.  On a bad value returns RA_EINVAL and leaves the
+ * previous demand vectors in place.  Errors: RA_EINVAL, RA_EDEVICE. */
+ra_status ra_problem_set_demand_vectors(ra_ctx *ctx, ra_problem *prob, const void *D);
 
 /* The paper's data-dependent starting prices (§5, "Initialization", eq.
  * e-initialization): every job gets the uniform share x = R/n of the limits

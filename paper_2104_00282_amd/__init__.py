@@ -186,6 +186,19 @@ class Problem:
         _capi.check(self.ctx.handle, _capi.lib().ra_problem_set_demands(
             self.ctx.handle, self.handle, _dptr(d) if d is not None else None))
 
+    def set_demand_vectors(self, D):
+        """Per-job demand vectors D (device tensor of the problem's dtype,
+        n x m, entries > 0), or None to remove them
+        (ra_problem_set_demand_vectors).  The library borrows D: the problem
+        keeps a reference to it until it is replaced or removed."""
+        if D is not None:
+            D = D.to(self.dtype).contiguous()
+            if tuple(D.shape) != (self.n, self.m):
+                raise ValueError("demand vectors must have shape (n, m)")
+        _capi.check(self.ctx.handle, _capi.lib().ra_problem_set_demand_vectors(
+            self.ctx.handle, self.handle, _dptr(D) if D is not None else None))
+        self._demand_vectors = D
+
     def init_prices(self):
         """The paper's data-dependent starting prices (ra_init_prices)."""
         p = np.zeros(self.m)

@@ -66,6 +66,7 @@ PROTOTYPES = {
     "ra_predict_prices": (_st, [_vp, _vp, _vp, _vp]),
     "ra_init_prices": (_st, [_vp, _vp, _vp]),
     "ra_problem_set_demands": (_st, [_vp, _vp, _vp]),
+    "ra_problem_set_demand_vectors": (_st, [_vp, _vp, _vp]),
     "ra_stream_read_ms": (_st, [_vp, _vp, _i64, _i32, ctypes.POINTER(_d)]),
     "ra_mlp_create": (_st, [_vp, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "ra_mlp_destroy": (_st, [_vp]),

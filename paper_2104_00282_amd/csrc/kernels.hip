@@ -79,24 +79,53 @@ struct Job {
     F v;               // net utility u(t) - p^T x
 };
 
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+
+// The prices one job pays per unit of each resource.  SharedPrices: the price
+// vector p, alike for every job; P and IP (= 1/p) are read with wave-uniform
+// indices in unrolled scans, Pdyn with a per-lane index.
+template <typename F>
+struct SharedPrices {
+    const F* __restrict__ P;
+    const F* __restrict__ IP;
+    const F* Pdyn;
+    __device__ __forceinline__ F get(int j) const { return P[j]; }
+    __device__ __forceinline__ F inv(int j) const { return IP[j]; }
+    __device__ __forceinline__ F at(int j) const { return Pdyn[j]; }
+};
+
+// A job with a demand vector d (§7, extensions) pays d_j p_j per unit of x_j;
+// D reads the job's demands as Row reads its throughputs.
+template <typename F, class D>
+struct DemandPrices {
+    const F* __restrict__ P;
+    const F* __restrict__ IP;
+    const F* Pdyn;
+    D d;
+    __device__ __forceinline__ F get(int j) const { return P[j] * d.get(j); }
+    __device__ __forceinline__ F inv(int j) const { return IP[j] * frcp(d.get(j)); }
+    __device__ __forceinline__ F at(int j) const { return Pdyn[j] * d.at(j); }
+};
+
 // First envelope vertex: largest key a_j * (1/p_j); lowest j on exact ties;
 // a_j = 0 never wins (key 0, or NaN when p_j = 0).
-template <typename F, int M, class Row>
-__device__ __forceinline__ int scan_first(const Row& a, int mm, const F* __restrict__ IP)
+template <typename F, int M, class Row, class Px>
+__device__ __forceinline__ int scan_first(const Row& a, int mm, const Px& px)
 {
     F best = F(0);
     int j1 = -1;
     if constexpr (M > 0) {
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const F key = a.get(j) * IP[j];
+            const F key = a.get(j) * px.inv(j);
             const bool b = key > best;
             best = b ? key : best;
             j1 = b ? j : j1;
         }
     } else {
         for (int j = 0; j < mm; ++j) {
-            const F key = a.get(j) * IP[j];
+            const F key = a.get(j) * px.inv(j);
             const bool b = key > best;
             best = b ? key : best;
             j1 = b ? j : j1;
@@ -108,9 +137,8 @@ __device__ __forceinline__ int scan_first(const Row& a, int mm, const F* __restr
 // Next envelope vertex after (ac, pc): smallest slope (p_j - pc)/(a_j - ac)
 // over a_j > ac, compared by cross-multiplication; lowest j on ties; -1 if
 // no resource is more efficient than the current vertex.
-template <typename F, int M, class Row>
-__device__ __forceinline__ int scan_next(const Row& a, int mm, const F* __restrict__ P, F ac,
-                                         F pc)
+template <typename F, int M, class Row, class Px>
+__device__ __forceinline__ int scan_next(const Row& a, int mm, const Px& px, F ac, F pc)
 {
     F bn = F(1), bd = F(0);
     int jn = -1;
@@ -118,7 +146,7 @@ __device__ __forceinline__ int scan_next(const Row& a, int mm, const F* __restri
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const F d = a.get(j) - ac;
-            const F nm = P[j] - pc;
+            const F nm = px.get(j) - pc;
             const bool b = (d > F(0)) & (nm * bd < bn * d);
             bn = b ? nm : bn;
             bd = b ? d : bd;
@@ -127,7 +155,7 @@ __device__ __forceinline__ int scan_next(const Row& a, int mm, const F* __restri
     } else {
         for (int j = 0; j < mm; ++j) {
             const F d = a.get(j) - ac;
-            const F nm = P[j] - pc;
+            const F nm = px.get(j) - pc;
             const bool b = (d > F(0)) & (nm * bd < bn * d);
             bn = b ? nm : bn;
             bd = b ? d : bd;
@@ -139,20 +167,18 @@ __device__ __forceinline__ int scan_next(const Row& a, int mm, const F* __restri
 
 // One job's subproblem (Algorithm 1 of §4.2 as an envelope walk).
 // a.get(j): entry j in an unrolled scan; a.at(j): entry j for a per-lane j;
-// P, IP: prices and reciprocals (wave-uniform); Pdyn: prices for a per-lane
-// index.
-template <typename F, int M, class Row, bool AF = true>
-__device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restrict__ P,
-                                          const F* __restrict__ IP, const F* Pdyn, F w, F c,
+// px: the job's prices (SharedPrices or DemandPrices).
+template <typename F, int M, bool AF = true, class Row, class Px>
+__device__ __forceinline__ void solve_job(const Row& a, int mm, const Px& px, F w, F c,
                                           bool caplin, F eps, Job<F>& J)
 {
-    const int j1 = scan_first<F, M>(a, mm, IP);
+    const int j1 = scan_first<F, M>(a, mm, px);
     // An all-zero row (j1 < 0) buys nothing: t = 0.  It runs through the same
     // code with an empty segment so that every result has one definition.
     const bool any = j1 >= 0;
     int lo = -1, hi = any ? j1 : -1;
     F alo = F(0), plo = F(0);
-    F ahi = any ? a.at(j1) : F(1), phi = any ? Pdyn[j1] : F(0);
+    F ahi = any ? a.at(j1) : F(1), phi = any ? px.at(j1) : F(0);
     F t = F(0);
     bool walk = any;
     while (walk) {
@@ -183,7 +209,7 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
             walk = c >= ahi;
         }
         if (walk) {
-            const int jn = scan_next<F, M>(a, mm, P, ahi, phi);
+            const int jn = scan_next<F, M>(a, mm, px, ahi, phi);
             if (jn < 0) {  // right end of the curve, t = max_j a_j
                 t = ahi;
                 walk = false;
@@ -193,7 +219,7 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const F* __restr
                 plo = phi;
                 hi = jn;
                 ahi = a.at(jn);
-                phi = Pdyn[jn];
+                phi = px.at(jn);
             }
         }
     }
@@ -280,6 +306,13 @@ struct RegRow {
     __device__ __forceinline__ float at(int j) const { return lds[j]; }
 };
 
+// A job's row of a staged tile, read from LDS on every use (demand vectors).
+struct LdsRow {
+    const float* lds;
+    __device__ __forceinline__ float get(int j) const { return lds[j]; }
+    __device__ __forceinline__ float at(int j) const { return lds[j]; }
+};
+
 template <typename F>
 struct GlobalRow {
     const F* __restrict__ r;
@@ -290,20 +323,23 @@ struct GlobalRow {
 // ------------------------------------------------------------------------
 // Dual kernel, FP32, m = M in {4, 8, 16, 32, 64}, T 16-byte aligned.
 // ------------------------------------------------------------------------
-template <int M, bool DEM>
+template <int M, bool DEM, bool DV>
 __global__ void __launch_bounds__(256) k_dual_vec(
     const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
     const PriceBlock<float>* __restrict__ pb, float eps, double* __restrict__ partial,
     int* __restrict__ jpair, float2* __restrict__ xpair, float2* __restrict__ tpair,
-    int16_t* __restrict__ j1out, const float* __restrict__ dem)
+    int16_t* __restrict__ j1out, const float* __restrict__ dem, const float* __restrict__ dvec)
 {
-    // dem (optional): per-job demands d_i; prm then holds w_i / d_i, so each
-    // job is solved at prices p unchanged, and its net value, usage and
-    // certificate terms are scaled by d_i (the subproblem at prices d_i p)
+    // dem (DEM, optional): per-job demands d_i; prm then holds w_i / d_i, so
+    // each job is solved at prices p unchanged, and its net value, usage and
+    // certificate terms are scaled by d_i (the subproblem at prices d_i p).
+    // dvec (DV): per-job demand vectors, n x M like T, staged through LDS
+    // with T; job i is solved at the prices d_i * p and adds d_ij x_ij to r_j.
     constexpr int Q = M / 4;                    // 16-byte chunks per row
     constexpr int S = M + ((Q & 1) ? 0 : 4);    // LDS row stride in words
     constexpr int TR = 64;                      // rows per wave tile
     __shared__ __attribute__((aligned(16))) float tile[4][TR * S];
+    __shared__ __attribute__((aligned(16))) float dtile[DV ? 4 : 1][DV ? TR * S : 4];
     __shared__ float hist[4][M];
     __shared__ float ptab[M], qtab[M], stab[M], sctab[M];
 
@@ -328,7 +364,9 @@ __global__ void __launch_bounds__(256) k_dual_vec(
     const int64_t nw = (int64_t)gridDim.x * 4;
     int64_t ti = (int64_t)blockIdx.x * 4 + wv;
     float* tl = tile[wv];
+    float* dtl = dtile[DV ? wv : 0];
     float4 pre[Q];
+    float4 dpre[DV ? Q : 1];
     float2 wcn = make_float2(0.f, 0.f);
     float dn = 1.f;
 
@@ -336,17 +374,26 @@ __global__ void __launch_bounds__(256) k_dual_vec(
         const int64_t row0 = tix * TR;
         const int64_t rows = (n - row0) < TR ? (n - row0) : TR;
         const float4* src = reinterpret_cast<const float4*>(T + row0 * M);
+        const float4* dsrc = DV ? reinterpret_cast<const float4*>(dvec + row0 * M) : nullptr;
         if (rows == TR) {
 #pragma unroll
             for (int k = 0; k < Q; ++k) pre[k] = stream_load(src + lane + 64 * k);
+            if constexpr (DV) {
+#pragma unroll
+                for (int k = 0; k < Q; ++k) dpre[k] = stream_load(dsrc + lane + 64 * k);
+            }
             wcn = prm[row0 + lane];
             if constexpr (DEM) dn = dem[row0 + lane];
         } else {
+            // rows past n: zero throughputs, unit demands (never used)
             const int valid = (int)rows * Q;
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 const int ch = lane + 64 * k;
                 pre[k] = (ch < valid) ? stream_load(src + ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+                if constexpr (DV)
+                    dpre[k] =
+                        (ch < valid) ? stream_load(dsrc + ch) : make_float4(1.f, 1.f, 1.f, 1.f);
             }
             wcn = (lane < rows) ? prm[row0 + lane] : make_float2(1.f, -1.f);
             if constexpr (DEM) dn = (lane < rows) ? dem[row0 + lane] : 1.f;
@@ -377,6 +424,7 @@ __global__ void __launch_bounds__(256) k_dual_vec(
             const int ch = lane + 64 * k;
             const int r = ch / Q, q = ch % Q;
             *reinterpret_cast<float4*>(tl + r * S + 4 * q) = pre[k];
+            if constexpr (DV) *reinterpret_cast<float4*>(dtl + r * S + 4 * q) = dpre[k];
         }
         const float2 wc = wcn;
         const float dj = DEM ? dn : 1.f;
@@ -397,15 +445,24 @@ __global__ void __launch_bounds__(256) k_dual_vec(
                 row.v[4 * q + 2] = v.z;
                 row.v[4 * q + 3] = v.w;
             }
-            Job<float> J;
+            const LdsRow drow{dtl + lane * S};
             const bool caplin = wc.y >= 0.f;
-            solve_job<float, M>(row, M, P, IP, ptab, wc.x, wc.y, caplin, eps, J);
-            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], dj * J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], dj * J.xhi);
+            auto solve = [&](const float* Pp, const float* IPp, const float* tab, Job<float>& out) {
+                if constexpr (DV)
+                    solve_job<float, M>(row, M, DemandPrices<float, LdsRow>{Pp, IPp, tab, drow},
+                                        wc.x, wc.y, caplin, eps, out);
+                else
+                    solve_job<float, M>(row, M, SharedPrices<float>{Pp, IPp, tab}, wc.x, wc.y,
+                                        caplin, eps, out);
+            };
+            Job<float> J;
+            solve(P, IP, ptab, J);
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? drow.at(J.jlo) : dj) * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? drow.at(J.jhi) : dj) * J.xhi);
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<float> K;
-                solve_job<float, M>(row, M, Qp, IQ, qtab, wc.x, wc.y, caplin, eps, K);
+                solve(Qp, IQ, qtab, K);
                 float u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab,
                                u, loss);
@@ -453,14 +510,15 @@ __global__ void __launch_bounds__(256) k_dual_vec(
 // ------------------------------------------------------------------------
 // Dual kernel, any m <= 256, FP32 or FP64: one lane per job reading its row
 // straight from global memory (used for FP64 and for m outside the
-// vectorised classes).
+// vectorised classes).  DV: per-job demand vectors dvec (n x m, like T), read
+// the same way; job i is solved at the prices d_i * p and adds d_ij x_ij.
 // ------------------------------------------------------------------------
-template <typename F>
+template <typename F, bool DV>
 __global__ void __launch_bounds__(256) k_dual_gen(
     const F* __restrict__ T, const V2<F>* __restrict__ prm, int64_t n, int m,
     const PriceBlock<F>* __restrict__ pb, F eps, double* __restrict__ partial,
     int* __restrict__ jpair, V2<F>* __restrict__ xpair, V2<F>* __restrict__ tpair,
-    int16_t* __restrict__ j1out, const F* __restrict__ dem)
+    int16_t* __restrict__ j1out, const F* __restrict__ dem, const F* __restrict__ dvec)
 {
     constexpr int TR = 64;
     __shared__ F hist[4][256];
@@ -485,13 +543,22 @@ __global__ void __launch_bounds__(256) k_dual_gen(
             Job<F> J;
             const bool caplin = wc.y >= F(0);
             const F dj = dem ? dem[i] : F(1);
-            solve_job<F, 0>(row, m, P, IP, P, wc.x, wc.y, caplin, eps, J);
-            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], dj * J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], dj * J.xhi);
+            const GlobalRow<F> drow{DV ? dvec + i * m : nullptr};
+            auto solve = [&](const F* Pp, const F* IPp, Job<F>& out) {
+                if constexpr (DV)
+                    solve_job<F, 0>(row, m, DemandPrices<F, GlobalRow<F>>{Pp, IPp, Pp, drow}, wc.x,
+                                    wc.y, caplin, eps, out);
+                else
+                    solve_job<F, 0>(row, m, SharedPrices<F>{Pp, IPp, Pp}, wc.x, wc.y, caplin, eps,
+                                    out);
+            };
+            solve(P, IP, J);
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? drow.at(J.jlo) : dj) * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? drow.at(J.jhi) : dj) * J.xhi);
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<F> K;
-                solve_job<F, 0>(row, m, pb->q, pb->invq, pb->q, wc.x, wc.y, caplin, eps, K);
+                solve(pb->q, pb->invq, K);
                 F u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, pb->s, pb->sc,
                                u, loss);
@@ -585,15 +652,15 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
             }
             const bool caplin = wc[k].y >= 0.f;
             Job<float> J;
-            solve_job<float, M, RegRow<M>, AF>(row, M, P, IP, ptab, wc[k].x, wc[k].y, caplin,
-                                               eps, J);
+            solve_job<float, M, AF>(row, M, SharedPrices<float>{P, IP, ptab}, wc[k].x, wc[k].y,
+                                    caplin, eps, J);
             if (J.jlo >= 0) atomicAdd(&hist[J.jlo], dm[k] * J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[J.jhi], dm[k] * J.xhi);
             vacc += (double)J.v * (double)dm[k];
             if (prev) {
                 Job<float> K;
-                solve_job<float, M, RegRow<M>, AF>(row, M, Qp, IQ, qtab, wc[k].x, wc[k].y, caplin,
-                                                   eps, K);
+                solve_job<float, M, AF>(row, M, SharedPrices<float>{Qp, IQ, qtab}, wc[k].x,
+                                        wc[k].y, caplin, eps, K);
                 float u, loss;
                 scaled_utility<float, AF>(caplin, wc[k].x, wc[k].y, eps, K.jlo, K.jhi, K.tlo,
                                           K.thi, stab, sctab, u, loss);
@@ -894,12 +961,15 @@ __global__ void __launch_bounds__(256) k_init_vec(const float* __restrict__ T,
 }
 
 // Any m <= 256, FP32 or FP64: one lane per job reading its row from global
-// memory; d_i a_ij added into a per-wave LDS row, flushed per tile.
+// memory; d_i a_ij added into a per-wave LDS row, flushed per tile.  With
+// demand vectors (dvec, n x m) job i adds d_i a_ij / dvec_ij: its
+// willingness to pay per unit of resource j it demands.
 template <typename F>
 __global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
                                                   const V2<F>* __restrict__ prm, int64_t n,
                                                   int m, const PriceBlock<F>* __restrict__ pb,
-                                                  F eps, double* __restrict__ partial)
+                                                  F eps, double* __restrict__ partial,
+                                                  const F* __restrict__ dvec)
 {
     constexpr int TR = 64;
     __shared__ F hist[4][256];
@@ -926,8 +996,12 @@ __global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
                 d = wc.x / (t + eps);
             else
                 d = wc.x * dpow(t + eps, -afair_exponent(wc.y));
-            if (d != F(0))
+            if (d != F(0) && dvec) {
+                const F* dr = dvec + i * m;
+                for (int j = 0; j < m; ++j) atomicAdd(&hist[wv][j], d * a[j] / dr[j]);
+            } else if (d != F(0)) {
                 for (int j = 0; j < m; ++j) atomicAdd(&hist[wv][j], d * a[j]);
+            }
         }
         wave_sync();
         for (int k = 0; k < 4; ++k) {
@@ -1070,13 +1144,14 @@ __global__ void k_pack(const F* __restrict__ w, const F* __restrict__ c,
 }
 
 template <typename F>
-__global__ void k_validate_T(const F* __restrict__ T, int64_t count, int* __restrict__ bad)
+__global__ void k_validate_T(const F* __restrict__ T, int64_t count, int* __restrict__ bad,
+                             bool positive)
 {
     int flags = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) {
         const F v = T[e];
-        if (!(v >= F(0)) || !isfinite(v)) flags |= 8;
+        if (!(positive ? v > F(0) : v >= F(0)) || !isfinite(v)) flags |= 8;
     }
     if (flags) atomicOr(bad, flags);
 }
@@ -1119,24 +1194,39 @@ static int occupancy_blocks(K kernel)
 
 static bool vec_class(int m) { return m == 4 || m == 8 || m == 16 || m == 32 || m == 64; }
 
-int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok)
+template <int M>
+static int vec_occupancy(bool dv)
 {
-    static int occ[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    return dv ? occupancy_blocks(k_dual_vec<M, false, true>)
+              : occupancy_blocks(k_dual_vec<M, false, false>);
+}
+
+int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok, bool dv)
+{
+    // occupancy per kernel: vectorised classes 0-4 (+5 with demand vectors),
+    // generic FP32 / FP64 10-11 (+2 with demand vectors)
+    static int occ[14] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     int slot;
     if (dtype == 0 && vec_ok && vec_class(m)) {
-        slot = m == 4 ? 0 : m == 8 ? 1 : m == 16 ? 2 : m == 32 ? 3 : 4;
+        slot = (m == 4 ? 0 : m == 8 ? 1 : m == 16 ? 2 : m == 32 ? 3 : 4) + (dv ? 5 : 0);
     } else {
-        slot = dtype == 0 ? 5 : 6;
+        slot = (dtype == 0 ? 10 : 11) + (dv ? 2 : 0);
     }
     if (occ[slot] == 0) {
-        switch (slot) {
-        case 0: occ[slot] = occupancy_blocks(k_dual_vec<4, false>); break;
-        case 1: occ[slot] = occupancy_blocks(k_dual_vec<8, false>); break;
-        case 2: occ[slot] = occupancy_blocks(k_dual_vec<16, false>); break;
-        case 3: occ[slot] = occupancy_blocks(k_dual_vec<32, false>); break;
-        case 4: occ[slot] = occupancy_blocks(k_dual_vec<64, false>); break;
-        case 5: occ[slot] = occupancy_blocks(k_dual_gen<float>); break;
-        default: occ[slot] = occupancy_blocks(k_dual_gen<double>); break;
+        switch (slot % 5 + (slot >= 10 ? 5 : 0)) {
+        case 0: occ[slot] = vec_occupancy<4>(dv); break;
+        case 1: occ[slot] = vec_occupancy<8>(dv); break;
+        case 2: occ[slot] = vec_occupancy<16>(dv); break;
+        case 3: occ[slot] = vec_occupancy<32>(dv); break;
+        case 4: occ[slot] = vec_occupancy<64>(dv); break;
+        default:
+            if (dtype == 0)
+                occ[slot] = dv ? occupancy_blocks(k_dual_gen<float, true>)
+                               : occupancy_blocks(k_dual_gen<float, false>);
+            else
+                occ[slot] = dv ? occupancy_blocks(k_dual_gen<double, true>)
+                               : occupancy_blocks(k_dual_gen<double, false>);
+            break;
         }
     }
     const int64_t ntiles = (n + 63) / 64;
@@ -1149,7 +1239,7 @@ int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok)
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
                        const void* prm, int64_t n, const void* prices, double eps,
                        double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1,
-                       const void* dem)
+                       const void* dem, const void* dvec)
 {
     int* jp = reinterpret_cast<int*>(jpair);
     if (dtype == 0) {
@@ -1160,14 +1250,18 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
         float2* tp = static_cast<float2*>(tpair);
         const float e = (float)eps;
         const float* df = static_cast<const float*>(dem);
+        const float* dv = static_cast<const float*>(dvec);
 #define DUAL_VEC(MM)                                                                        \
     do {                                                                                    \
-        if (df)                                                                             \
-            k_dual_vec<MM, true><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp, tp, \
-                                                       j1, df);                             \
+        if (dv)                                                                             \
+            k_dual_vec<MM, false, true><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp,  \
+                                                              xp, tp, j1, nullptr, dv);     \
+        else if (df)                                                                        \
+            k_dual_vec<MM, true, false><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp,  \
+                                                              xp, tp, j1, df, nullptr);     \
         else                                                                                \
-            k_dual_vec<MM, false><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, xp,    \
-                                                        tp, j1, nullptr);                   \
+            k_dual_vec<MM, false, false><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, \
+                                                               xp, tp, j1, nullptr, nullptr); \
     } while (0)
         if (vec_ok && vec_class(m)) {
             switch (m) {
@@ -1177,31 +1271,43 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
             case 32: DUAL_VEC(32); break;
             default: DUAL_VEC(64); break;
             }
+        } else if (dv) {
+            k_dual_gen<float, true><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp, tp,
+                                                          j1, nullptr, dv);
         } else {
-            k_dual_gen<float><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp, tp, j1,
-                                                    df);
+            k_dual_gen<float, false><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp,
+                                                           tp, j1, df, nullptr);
         }
 #undef DUAL_VEC
     } else {
-        k_dual_gen<double><<<grid, 256, 0, st>>>(
-            static_cast<const double*>(T), static_cast<const double2*>(prm), n, m,
-            static_cast<const PriceBlock<double>*>(prices), eps, partial, jp,
-            static_cast<double2*>(xpair), static_cast<double2*>(tpair), j1,
-            static_cast<const double*>(dem));
+        const double* Td = static_cast<const double*>(T);
+        const double2* pr = static_cast<const double2*>(prm);
+        const auto* pb = static_cast<const PriceBlock<double>*>(prices);
+        double2* xp = static_cast<double2*>(xpair);
+        double2* tp = static_cast<double2*>(tpair);
+        const double* dv = static_cast<const double*>(dvec);
+        if (dv)
+            k_dual_gen<double, true><<<grid, 256, 0, st>>>(Td, pr, n, m, pb, eps, partial, jp, xp,
+                                                           tp, j1, nullptr, dv);
+        else
+            k_dual_gen<double, false><<<grid, 256, 0, st>>>(Td, pr, n, m, pb, eps, partial, jp,
+                                                            xp, tp, j1,
+                                                            static_cast<const double*>(dem),
+                                                            nullptr);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
                        const void* prm, int64_t n, const void* prices, double eps,
-                       double* partial)
+                       double* partial, const void* dvec)
 {
     if (dtype == 0) {
         const float* Tf = static_cast<const float*>(T);
         const float2* pr = static_cast<const float2*>(prm);
         const auto* pb = static_cast<const PriceBlock<float>*>(prices);
         const float e = (float)eps;
-        if (vec_ok && vec_class(m)) {
+        if (vec_ok && vec_class(m) && !dvec) {
             switch (m) {
             case 4: k_init_vec<4><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial); break;
             case 8: k_init_vec<8><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial); break;
@@ -1210,12 +1316,14 @@ hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
             default: k_init_vec<64><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial); break;
             }
         } else {
-            k_init_gen<float><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial);
+            k_init_gen<float><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial,
+                                                    static_cast<const float*>(dvec));
         }
     } else {
         k_init_gen<double><<<grid, 256, 0, st>>>(
             static_cast<const double*>(T), static_cast<const double2*>(prm), n, m,
-            static_cast<const PriceBlock<double>*>(prices), eps, partial);
+            static_cast<const PriceBlock<double>*>(prices), eps, partial,
+            static_cast<const double*>(dvec));
     }
     return hipGetLastError();
 }
@@ -1361,14 +1469,17 @@ hipError_t launch_pack(int dtype, hipStream_t st, const void* w, const void* c,
     return hipGetLastError();
 }
 
-hipError_t launch_validate_T(int dtype, hipStream_t st, const void* T, int64_t count, int* bad)
+hipError_t launch_validate_T(int dtype, hipStream_t st, const void* T, int64_t count, int* bad,
+                             bool positive)
 {
     const int64_t want = (count + 255) / 256;
     const int grid = (int)(want < 8192 ? (want < 1 ? 1 : want) : 8192);
     if (dtype == 0)
-        k_validate_T<float><<<grid, 256, 0, st>>>(static_cast<const float*>(T), count, bad);
+        k_validate_T<float><<<grid, 256, 0, st>>>(static_cast<const float*>(T), count, bad,
+                                                  positive);
     else
-        k_validate_T<double><<<grid, 256, 0, st>>>(static_cast<const double*>(T), count, bad);
+        k_validate_T<double><<<grid, 256, 0, st>>>(static_cast<const double*>(T), count, bad,
+                                                   positive);
     return hipGetLastError();
 }
 

@@ -51,6 +51,8 @@ struct ra_problem {
     unsigned* ticket = nullptr; // device block counter of that reduction
     bool alpha_fair = false;    // some job has an alpha-fair utility other than log
     void* dem = nullptr;        // per-job demands (dtype, n), or NULL
+    const void* dvec = nullptr; // per-job demand vectors (dtype, n x m, borrowed), or NULL
+    int grid_cap = 1;           // block rows `partial` holds
     void* w0 = nullptr;         // the weights as packed before demands were applied
     int16_t* jpair_ws = nullptr;
     void* tpair_ws = nullptr;

@@ -58,23 +58,28 @@ hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem
                         unsigned* ticket = nullptr, unsigned* flag = nullptr,
                         bool demands = false, bool alpha_fair = true);
 
-// Number of blocks one dual-kernel launch uses for n jobs with m resources.
-int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok);
+// Number of blocks one dual-kernel launch uses for n jobs with m resources
+// (dv: with per-job demand vectors).
+int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok, bool dv = false);
 
 // Dual evaluation (Algorithm 1 per job, sums into block partials).
 // partial: [grid][partial_cols(m)] doubles.
 // Optional outputs may be null: jpair (n x 2 int16), xpair (n x 2 F),
 // tpair (n x 2 F, a_lo x_lo and a_hi x_hi), j1 (n int16).
+// dem: per-job scalar demands (n, with w_i / d_i packed in prm); dvec:
+// per-job demand vectors (n x m, like T; 16-byte aligned when vec_ok);
+// at most one of the two.
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
                        const void* prm, int64_t n, const void* prices, double eps,
                        double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1,
-                       const void* dem = nullptr);
+                       const void* dem = nullptr, const void* dvec = nullptr);
 
 // Data-dependent starting prices: partial [grid][m] gets, per block, the sums
-// of u_i'(a_i^T x) a_ij with x = prices->p (the uniform share of R).
+// of u_i'(a_i^T x) a_ij with x = prices->p (the uniform share of R), each
+// term divided by the job's demand for j when dvec (n x m) is given.
 hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
                        const void* prm, int64_t n, const void* prices, double eps,
-                       double* partial);
+                       double* partial, const void* dvec = nullptr);
 
 // out[j] = sum_b partial[b * ncols + j], j < ncols (fixed order).  With flag
 // (host memory, fine-grained) and ticket (device counter, zero between
@@ -101,8 +106,10 @@ hipError_t launch_demands(int dtype, hipStream_t st, int op, const void* d, void
 hipError_t launch_pack(int dtype, hipStream_t st, const void* w, const void* c,
                        const uint8_t* kind, int64_t n, void* prm, int* bad);
 
-// bad gets bit 8 if any T entry is negative or non-finite.
-hipError_t launch_validate_T(int dtype, hipStream_t st, const void* T, int64_t count, int* bad);
+// bad gets bit 8 if any entry is negative (with positive: not > 0) or
+// non-finite.
+hipError_t launch_validate_T(int dtype, hipStream_t st, const void* T, int64_t count, int* bad,
+                             bool positive = false);
 
 // Dense X~ (n x m, element type F) from the support and column scales.
 hipError_t launch_materialize(int dtype, hipStream_t st, const int16_t* jpair, const void* xpair,

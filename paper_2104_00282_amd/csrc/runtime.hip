@@ -93,6 +93,13 @@ void fill_prev(ra_problem* P, const std::vector<double>& q, const std::vector<do
         fill_prev_t<double>(P, q, r);
 }
 
+// The vectorised dual kernels need T, and demand vectors when set, 16-byte
+// aligned.
+bool dual_vec(const ra_problem* P)
+{
+    return P->vec_ok && (!P->dvec || reinterpret_cast<uintptr_t>(P->dvec) % 16 == 0);
+}
+
 ra_status ensure_support_ws(ra_problem* P)
 {
     ra_ctx* ctx = P->ctx;
@@ -115,9 +122,9 @@ ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_
     int16_t* jp = jpair_user ? jpair_user : (lb ? P->jpair_ws : nullptr);
     void* tp = lb ? P->tpair_ws : nullptr;
     if (ctx->timing) RA_HIP(ctx, hipEventRecord(ctx->ev0, st));
-    RA_HIP(ctx, ra::launch_dual(P->dt, P->m, P->vec_ok, P->grid, st, P->T, P->prm, P->n,
+    RA_HIP(ctx, ra::launch_dual(P->dt, P->m, dual_vec(P), P->grid, st, P->T, P->prm, P->n,
                                 P->pblock, P->eps, P->partial, jp, jpair_user ? xpair_user : nullptr,
-                                tp, j1_user, P->dem));
+                                tp, j1_user, P->dem, P->dvec));
     if (ctx->timing) {
         RA_HIP(ctx, hipEventRecord(ctx->ev1, st));
         ctx->timed_pending = true;
@@ -191,8 +198,8 @@ ra_status init_prices(ra_problem* P, double* p)
     (void)fill_prices(P, x.data(), nullptr);
     RA_HIP(ctx, hipMemcpyAsync(P->pblock, P->h_pblock, price_block_bytes(P->dt),
                                hipMemcpyHostToDevice, st));
-    RA_HIP(ctx, ra::launch_init(P->dt, m, P->vec_ok, P->grid, st, P->T, P->prm, P->n, P->pblock,
-                                P->eps, P->partial));
+    RA_HIP(ctx, ra::launch_init(P->dt, m, dual_vec(P), P->grid, st, P->T, P->prm, P->n,
+                                P->pblock, P->eps, P->partial, P->dvec));
     RA_HIP(ctx, ra::launch_reduce_cols(st, P->partial, P->grid, m, P->dout));
     RA_HIP(ctx, hipMemcpyAsync(P->h_out, P->dout, sizeof(double) * m, hipMemcpyDeviceToHost, st));
     RA_HIP(ctx, hipStreamSynchronize(st));
@@ -389,6 +396,7 @@ ra_status ra_problem_create(ra_ctx* ctx, ra_problem** out, int64_t n, int32_t m,
     P->eps = eps;
     P->vec_ok = (dt == RA_F32) && (reinterpret_cast<uintptr_t>(T) % 16 == 0);
     P->grid = ra::dual_grid(ctx->cus, m, P->dt, n, P->vec_ok);
+    P->grid_cap = P->grid;
     P->lgrid = ra::lower_grid(ctx->cus, n);
 
     auto cleanup = [&](ra_status st) {
@@ -591,6 +599,8 @@ ra_status ra_problem_set_demands(ra_ctx* ctx, ra_problem* P, const void* d)
         (void)hipGraphDestroy(P->graph);
         P->graph = nullptr;
     }
+    if (d && P->dvec)
+        return fail(ctx, RA_EINVAL, "the problem has demand vectors; remove them first");
     if (!d) {
         if (!P->dem) return RA_OK;
         RA_HIP(ctx, ra::launch_demands(P->dt, st, 2, nullptr, P->w0, P->n, P->prm, nullptr, nullptr));
@@ -622,6 +632,51 @@ ra_status ra_problem_set_demands(ra_ctx* ctx, ra_problem* P, const void* d)
         P->dem = nullptr;
         return fail(ctx, RA_EINVAL, "demands must be positive and finite");
     }
+    return RA_OK;
+}
+
+ra_status ra_problem_set_demand_vectors(ra_ctx* ctx, ra_problem* P, const void* D)
+{
+    if (!ctx || ctx->closed) return RA_EINVAL;
+    if (!P || P->ctx != ctx) return fail(ctx, RA_EINVAL, "problem is NULL or from another context");
+    if (D && P->dem)
+        return fail(ctx, RA_EINVAL, "the problem has scalar demands; remove them first");
+    RA_HIP(ctx, hipSetDevice(ctx->dev));
+    hipStream_t st = ctx->stream;
+    if (D) {
+        int* dbad = nullptr;
+        RA_HIP(ctx, hipMalloc((void**)&dbad, sizeof(int)));
+        int zero = 0, bad = 0;
+        hipError_t e = hipMemcpyAsync(dbad, &zero, sizeof(int), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = ra::launch_validate_T(P->dt, st, D, P->n * (int64_t)P->m, dbad, true);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, dbad, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        (void)hipFree(dbad);
+        if (e != hipSuccess)
+            return fail(ctx, RA_EDEVICE, "set demand vectors: %s", hipGetErrorString(e));
+        if (bad) return fail(ctx, RA_EINVAL, "demand vectors must be positive and finite");
+    }
+    // captured graphs hold the previous kernel and its arguments
+    if (P->gexec) {
+        (void)hipGraphExecDestroy(P->gexec);
+        P->gexec = nullptr;
+    }
+    if (P->graph) {
+        (void)hipGraphDestroy(P->graph);
+        P->graph = nullptr;
+    }
+    P->dvec = D;
+    const int g = ra::dual_grid(ctx->cus, P->m, P->dt, P->n, dual_vec(P), D != nullptr);
+    if (g > P->grid_cap) {
+        RA_HIP(ctx, hipStreamSynchronize(st));
+        (void)hipFree(P->partial);
+        P->partial = nullptr;
+        P->grid_cap = 0;
+        RA_HIP(ctx, hipMalloc(&P->partial, sizeof(double) * (size_t)g * ra::partial_cols(P->m)));
+        P->grid_cap = g;
+    }
+    P->grid = g;
     return RA_OK;
 }
 
@@ -1076,6 +1131,10 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
             return fail(ctx, RA_EUNSUPPORTED,
                         "problem %d: the batched kernel takes FP32, 16-byte aligned T with m in "
                         "{4, 8, 16, 32}", b);
+        if (P[b]->dvec)
+            return fail(ctx, RA_EUNSUPPORTED,
+                        "problem %d: demand vectors are not supported by the batched kernel "
+                        "(use ra_solve)", b);
         if (P[b]->n > ((int64_t)1 << 36))
             return fail(ctx, RA_EUNSUPPORTED, "problem %d too large for the batched kernel", b);
         if (tol_each && !(tol_each[b] >= 0.0))

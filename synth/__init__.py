@@ -292,3 +292,28 @@ def warmstart_device(n, m=16, seed=BASE_SEED + 100000, device="cuda"):
     c = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
     R = (rho * n / m).cpu().numpy()
     return T.contiguous(), w, c, kind, R
+
+
+def demand_vectors_device(n=10_000_000, m=64, seed=BASE_SEED + 6, device="cuda"):
+    """Jobs with demand vectors, drawn on the GPU with torch's seeded
+    generator: T_ij = s_j exp(Z_ij), s_j ~ U[0.2, 5] (the roofline-64
+    recipe), kind ~ Bernoulli(1/2) (log / capped linear), w, c ~ U[0.5, 2],
+    demands D_ij ~ U[0.5, 2] (units of resource j a job uses while running
+    on it), R_j = 0.125 n/m (the roofline-64 limits times the mean demand),
+    eps = 1e-3.  Also a seeded price vector p ~ U[0.5, 1.5]^m for evaluations
+    at fixed prices.  Returns a dict of device tensors (T, D, w, c, kind) and
+    host values (R, p, eps, n, m)."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    colscale = 0.2 + 4.8 * torch.rand(m, generator=g, device=device, dtype=torch.float64)
+    T = torch.randn((n, m), generator=g, device=device, dtype=torch.float32)
+    T.exp_().mul_(colscale.to(torch.float32)[None, :])
+    kind = (torch.rand(n, generator=g, device=device) < 0.5).to(torch.uint8)
+    w = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
+    c = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
+    D = 0.5 + 1.5 * torch.rand((n, m), generator=g, device=device)
+    p = (0.5 + torch.rand(m, generator=g, device=device, dtype=torch.float64)).cpu().numpy()
+    return {"T": T.contiguous(), "D": D.contiguous(), "w": w, "c": c, "kind": kind,
+            "R": np.full(m, 0.125 * n / m), "p": p, "eps": 1e-3, "n": n, "m": m}
