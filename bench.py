@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SRC = os.path.join(ROOT, "paper_2104_00282_amd", "csrc", "kernels.hip")
 COUNTERS = os.path.join(ROOT, "profiles", "dual_eval_roofline64_counters.json")
+COUNTERS_DV = os.path.join(ROOT, "profiles", "dual_eval_demand_vectors64_counters.json")
 COPY_BYTES = 2_560_000_000  # bytes read (and written) by one calibration copy
 
 
@@ -48,12 +49,12 @@ def kernel_source_hash():
     return hashlib.sha256(src[:src.index(DUAL_SECTION_END)]).hexdigest()
 
 
-def traffic_from_counters():
-    """HBM bytes per dual-kernel launch from the committed rocprofv3 counter
+def traffic_from_counters(path=None):
+    """HBM bytes per dual-kernel launch from a committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or
     None when the kernel source changed after the counters were taken."""
     try:
-        with open(COUNTERS) as f:
+        with open(path or COUNTERS) as f:
             C = json.load(f)
     except (OSError, ValueError):
         return None
@@ -469,7 +470,8 @@ def bench_demand_vectors(args):
                       "solve_to_1e-4": {"seconds": solve_s, "dual_evals": sinfo["dual_evals"],
                                         "rel_gap": sinfo["rel_gap"]}},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                        "traffic": traffic_from_counters(COUNTERS_DV),
                         "kernel": "dual evaluation with demand vectors (k_dual_vec<64, false, true>)",
                         "bytes_per_launch": bytes_per_launch, "launches": launches}}
     prob.close()
