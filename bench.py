@@ -416,23 +416,53 @@ def bench_e1(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_demand_vectors(args):
-    """Per-job demand vectors (§7 extensions) on the roofline shape: n = 1e7,
-    m = 64, FP32, D_ij ~ U[0.5, 2].  Solver steps timed as in the default
-    workload (each evaluation also reads D: 2 n m 4 + 8 n bytes), the same
-    instance's steps without demands for comparison, and a cold solve to a
-    1e-4 relative gap."""
+EXTENSIONS = {
+    "demand-vectors": {
+        "metric": "job·resource entries/s in the dual evaluation with per-job demand vectors",
+        "workload": "demand vectors: n=%d jobs, m=%d resources, FP32 T_ij = s_j exp(Z_ij), "
+                    "D_ij ~ U[0.5, 2], half log / half capped-linear utilities, R_j = 0.125 n/m",
+        "kernel": "dual evaluation with demand vectors (k_dual_vec<64, false, true>)",
+        "counters": "COUNTERS_DV",
+    },
+    "demands": {
+        "metric": "job·resource entries/s in the dual evaluation with per-job demands",
+        "workload": "scalar demands: n=%d jobs, m=%d resources, FP32 T_ij = s_j exp(Z_ij), "
+                    "d_i ~ U[0.5, 2], half log / half capped-linear utilities, R_j = 0.125 n/m",
+        "kernel": "dual evaluation with per-job demands (k_dual_vec<64, true, false>)",
+        "counters": None,
+    },
+    "alpha-fair": {
+        "metric": "job·resource entries/s in the dual evaluation with alpha-fair utilities",
+        "workload": "alpha-fair: n=%d jobs, m=%d resources, FP32 T_ij = s_j exp(Z_ij), a third "
+                    "each of log, capped-linear and alpha-fair (exponent ~ U[0, 3]) utilities, "
+                    "R_j = 0.1 n/m",
+        "kernel": "dual evaluation (k_dual_vec<64, false, false>)",
+        "counters": None,
+    },
+}
+
+
+def bench_extension(args):
+    """The §7 extensions and the alpha-fair family on the roofline shape
+    (n = 1e7, m = 64, FP32): solver steps timed as in the default workload,
+    first on the instance without the extension (log / capped-linear
+    utilities, no demands), then with it, and a cold solve to a 1e-4
+    relative gap.  Bytes per pass: T and the packed (w, c) as always, plus D
+    (4 n m) for demand vectors or d (4 n) for scalar demands."""
     import torch
     import synth
     import paper_2104_00282_amd as ra
 
+    variant = args.workload
+    E = EXTENSIONS[variant]
     n, m = args.n, 64
-    log("generating demand-vector instance n=%d m=%d on the device" % (n, m))
-    I = synth.demand_vectors_device(n=n, m=m)
+    log("generating %s instance n=%d m=%d on the device" % (variant, n, m))
+    I = synth.extension_device(variant, n=n, m=m)
     ctx = ra.Context(0)
-    prob = ra.Problem(ctx, I["T"], I["w"], I["c"], I["kind"], I["R"], I["eps"], validate=False)
+    base_kind = I["kind"].clamp(max=1) if variant == "alpha-fair" else I["kind"]
+    base_c = torch.where(I["kind"] == 2, torch.ones_like(I["c"]), I["c"])
 
-    def timed_steps(label):
+    def timed_steps(prob, label):
         p, _, _ = prob.solve(tol_rel=0.0, max_iter=args.warmup, max_evals=args.warmup)
         ra.ra_set_kernel_timing(ctx.handle, True)
         torch.cuda.synchronize()
@@ -447,32 +477,40 @@ def bench_demand_vectors(args):
             (label, steps, dt * 1e3 / steps, kms / max(launches, 1)))
         return dt * 1e3 / steps, kms / max(launches, 1), launches, steps
 
-    plain_ms, plain_kms, _, _ = timed_steps("without demands")
-    prob.set_demand_vectors(I["D"])
-    ms, kms, launches, steps = timed_steps("with demand vectors")
+    base = ra.Problem(ctx, I["T"], I["w"], base_c, base_kind, I["R"], I["eps"], validate=False)
+    plain_ms, plain_kms, _, _ = timed_steps(base, "without the extension")
+    base.close()
+    prob = ra.Problem(ctx, I["T"], I["w"], I["c"], I["kind"], I["R"], I["eps"], validate=False)
+    extra = 0
+    if variant == "demand-vectors":
+        prob.set_demand_vectors(I["D"])
+        extra = n * m * 4
+    elif variant == "demands":
+        prob.set_demands(I["d"])
+        extra = n * 4
+    ms, kms, launches, steps = timed_steps(prob, "with " + variant)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, sinfo, _ = prob.solve(tol_rel=1e-4, max_iter=500)
     solve_s = time.perf_counter() - t0
-    bytes_per_launch = 2 * n * m * 4 + n * 8
+    bytes_per_launch = n * m * 4 + n * 8 + extra
     achieved = bytes_per_launch / (kms / 1e3) / 1e9
-    out = {"metric": "job·resource entries/s in the dual evaluation with per-job demand vectors",
+    counters = globals()[E["counters"]] if E["counters"] else None
+    out = {"metric": E["metric"],
            "value": n * m / (ms / 1e3), "unit": "job·resource entries/s", "n_gpus": 1,
            "steps": steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "demand vectors: n=%d jobs, m=%d resources, FP32 T_ij = "
-                                  "s_j exp(Z_ij), D_ij ~ U[0.5, 2], half log / half "
-                                  "capped-linear utilities, R_j = 0.125 n/m" % (n, m),
+           "config": {"workload": E["workload"] % (n, m),
                       "step": "one solver evaluation: dual function + gradient + lower bound "
                               "+ L-BFGS update",
                       "dual_kernel_ms": kms,
-                      "without_demands": {"ms_per_step": plain_ms, "dual_kernel_ms": plain_kms},
+                      "without_extension": {"ms_per_step": plain_ms, "dual_kernel_ms": plain_kms},
                       "solve_to_1e-4": {"seconds": solve_s, "dual_evals": sinfo["dual_evals"],
                                         "rel_gap": sinfo["rel_gap"]}},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                        "traffic": traffic_from_counters(COUNTERS_DV),
-                        "kernel": "dual evaluation with demand vectors (k_dual_vec<64, false, true>)",
+                        "traffic": traffic_from_counters(counters) if counters else None,
+                        "kernel": E["kernel"],
                         "bytes_per_launch": bytes_per_launch, "launches": launches}}
     prob.close()
     ctx.close()
@@ -494,7 +532,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale the HBM counters")
     ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
-                                           "batch-rounds", "e1", "demand-vectors"],
+                                           "batch-rounds", "e1", "demand-vectors", "demands",
+                                           "alpha-fair"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
@@ -515,13 +554,14 @@ def main():
         calibrate_copy()
         return
     if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1",
-                         "demand-vectors"):
+                         "demand-vectors", "demands", "alpha-fair"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batched": bench_batched, "warmstart": bench_warmstart,
          "solves": bench_solves, "batch-rounds": bench_batch_rounds,
-         "e1": bench_e1, "demand-vectors": bench_demand_vectors}[args.workload](args)
+         "e1": bench_e1, "demand-vectors": bench_extension, "demands": bench_extension,
+         "alpha-fair": bench_extension}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

@@ -41,17 +41,28 @@ template <typename F> using V2 = typename Vec2<F>::type;
 
 __device__ __forceinline__ float dlog(float x) { return logf(x); }
 __device__ __forceinline__ double dlog(double x) { return log(x); }
-__device__ __forceinline__ float dpow(float x, float y) { return powf(x, y); }
+// x^y for x >= 0 and y != 0 (every use here: a base t + eps or w / alpha,
+// an exponent 1 - a or 1 / a), as 2^(y log2 x) with the hardware's base-2
+// logarithm and exponential: relative error about (|y log2 x| + 1) 2^-23,
+// below 3e-6 for the magnitudes met here, at a fraction of powf's cost.
+__device__ __forceinline__ float dpow(float x, float y)
+{
+    return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+}
 __device__ __forceinline__ double dpow(double x, double y) { return pow(x, y); }
 __device__ __forceinline__ float dexpm1(float x) { return expm1f(x); }
 __device__ __forceinline__ double dexpm1(double x) { return expm1(x); }
 
-// Packed utility code c of a job (second field of prm): c >= 0 capped linear
-// w min(t, c) (the target-priority utility plus a constant); c = -1 log
-// w log(t + eps); c <= -2 alpha-fair with exponent a = -c - 2 (a != 1),
-// w (t + eps)^(1 - a) / (1 - a) (a = 0: linear), the family of §2.2.
+// Packed utility code c of a job (second field of prm), told apart by its
+// sign bit: clear (c >= +0) capped linear w min(t, c) (the target-priority
+// utility plus a constant); set: the alpha-fair family of §2.2 with exponent
+// a = -c, kept at full precision: c = -1 (a = 1) is the log utility
+// w log(t + eps), any other a gives w (t + eps)^(1 - a) / (1 - a) (c = -0,
+// a = 0: linear).
 template <typename F>
-__device__ __forceinline__ F afair_exponent(F c) { return -c - F(2); }
+__device__ __forceinline__ bool is_capped(F c) { return !__builtin_signbit(c); }
+template <typename F>
+__device__ __forceinline__ F afair_exponent(F c) { return -c; }
 
 // u(t) of §2.2: log utility w log(t + eps) or capped linear w min(t, c).
 // AF = false compiles the alpha-fair branches out (for problems without such jobs).
@@ -446,7 +457,7 @@ __global__ void __launch_bounds__(256) k_dual_vec(
                 row.v[4 * q + 3] = v.w;
             }
             const LdsRow drow{dtl + lane * S};
-            const bool caplin = wc.y >= 0.f;
+            const bool caplin = is_capped(wc.y);
             auto solve = [&](const float* Pp, const float* IPp, const float* tab, Job<float>& out) {
                 if constexpr (DV)
                     solve_job<float, M>(row, M, DemandPrices<float, LdsRow>{Pp, IPp, tab, drow},
@@ -541,7 +552,7 @@ __global__ void __launch_bounds__(256) k_dual_gen(
             GlobalRow<F> row{T + i * m};
             const V2<F> wc = prm[i];
             Job<F> J;
-            const bool caplin = wc.y >= F(0);
+            const bool caplin = is_capped(wc.y);
             const F dj = dem ? dem[i] : F(1);
             const GlobalRow<F> drow{DV ? dvec + i * m : nullptr};
             auto solve = [&](const F* Pp, const F* IPp, Job<F>& out) {
@@ -650,7 +661,7 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
                 row.v[4 * q + 2] = v.z;
                 row.v[4 * q + 3] = v.w;
             }
-            const bool caplin = wc[k].y >= 0.f;
+            const bool caplin = is_capped(wc[k].y);
             Job<float> J;
             solve_job<float, M, AF>(row, M, SharedPrices<float>{P, IP, ptab}, wc[k].x, wc[k].y,
                                     caplin, eps, J);
@@ -935,7 +946,7 @@ __global__ void __launch_bounds__(256) k_init_vec(const float* __restrict__ T,
             t += v.x * xtab[4 * q] + v.y * xtab[4 * q + 1] + v.z * xtab[4 * q + 2] +
                  v.w * xtab[4 * q + 3];
         }
-        const bool caplin = wc.y >= 0.f;
+        const bool caplin = is_capped(wc.y);
         float d;
         if (caplin)
             d = t < wc.y ? wc.x : 0.f;
@@ -990,7 +1001,7 @@ __global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
             for (int j = 0; j < m; ++j) t += a[j] * x[j];
             const V2<F> wc = prm[i];
             F d;
-            if (wc.y >= F(0))
+            if (is_capped(wc.y))
                 d = t < wc.y ? wc.x : F(0);
             else if (wc.y == F(-1))
                 d = wc.x / (t + eps);
@@ -1090,7 +1101,7 @@ __global__ void __launch_bounds__(256) k_lower(const int* __restrict__ jpair,
         const V2<F> tp = tpair[i];
         const V2<F> wc = prm[i];
         F u, loss;
-        scaled_utility(wc.y >= F(0), wc.x, wc.y, eps, jlo, jhi, tp.x, tp.y, s, sc, u, loss);
+        scaled_utility(is_capped(wc.y), wc.x, wc.y, eps, jlo, jhi, tp.x, tp.y, s, sc, u, loss);
         const double dj = dem ? (double)dem[i] : 1.0;
         U += (double)u * dj;
         du += (double)loss * dj;
@@ -1129,11 +1140,12 @@ __global__ void k_pack(const F* __restrict__ w, const F* __restrict__ c,
         if (k == 1) {
             ci = c[i];
             if (!(ci >= F(0)) || !isfinite(ci)) flags |= 2;
+            ci = (ci == F(0)) ? F(0) : ci;  // a cap of -0 is stored as +0 (sign bit clear)
         } else if (k == 2) {
             // alpha-fair exponent a >= 0; a = 1 is the log utility
             const F a = c[i];
             if (!(a >= F(0)) || !isfinite(a)) flags |= 2;
-            ci = (a == F(1)) ? F(-1) : -(F(2) + a);
+            ci = (a == F(1)) ? F(-1) : -a;  // -0 for a = 0: the sign bit marks the family
             if (a != F(1)) flags |= 16;  // the problem has alpha-fair jobs (not an error)
         } else if (k > 2) {
             flags |= 4;

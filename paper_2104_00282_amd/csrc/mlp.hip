@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
         for (int k = tid; k < S; k += 1024) {
             const int64_t i = ((int64_t)k * n) / S;
             const float2 wc = prm[i];
-            const int kind = wc.y >= 0.f ? 1 : 0;
+            const int kind = __builtin_signbit(wc.y) ? 0 : 1;
             int bin = (int)floorf((wc.x - 0.5f) / 0.1875f);
             bin = bin < 0 ? 0 : (bin > 7 ? 7 : bin);
             atomicAdd(&cnt[kind * 8 + bin], 1);
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
     for (int k = tid; k < S; k += 1024) {
         const int64_t i = ((int64_t)k * n) / S;
         const float v = T[i * m + j];
-        const unsigned kind = prm[i].y >= 0.f ? 1u : 0u;
+        const unsigned kind = __builtin_signbit(prm[i].y) ? 0u : 1u;
         // -0 and +0 share a key
         const unsigned bits = v == 0.f ? 0u : __float_as_uint(v);
         key[k] = (kind << 31) | (bits & 0x7fffffffu);

@@ -294,26 +294,50 @@ def warmstart_device(n, m=16, seed=BASE_SEED + 100000, device="cuda"):
     return T.contiguous(), w, c, kind, R
 
 
-def demand_vectors_device(n=10_000_000, m=64, seed=BASE_SEED + 6, device="cuda"):
-    """Jobs with demand vectors, drawn on the GPU with torch's seeded
-    generator: T_ij = s_j exp(Z_ij), s_j ~ U[0.2, 5] (the roofline-64
-    recipe), kind ~ Bernoulli(1/2) (log / capped linear), w, c ~ U[0.5, 2],
-    demands D_ij ~ U[0.5, 2] (units of resource j a job uses while running
-    on it), R_j = 0.125 n/m (the roofline-64 limits times the mean demand),
-    eps = 1e-3.  Also a seeded price vector p ~ U[0.5, 1.5]^m for evaluations
-    at fixed prices.  Returns a dict of device tensors (T, D, w, c, kind) and
-    host values (R, p, eps, n, m)."""
+def extension_device(variant, n=10_000_000, m=64, device="cuda"):
+    """Instances of the roofline-64 shape for the §7 extensions and the
+    alpha-fair family, drawn on the GPU with torch's seeded generator:
+    T_ij = s_j exp(Z_ij), s_j ~ U[0.2, 5]; w ~ U[0.5, 2]; eps = 1e-3; and a
+    seeded price vector p ~ U[0.5, 1.5]^m for evaluations at fixed prices.
+    - "demand-vectors" (seed offset 6): kind ~ Bernoulli(1/2) (log / capped
+      linear, c ~ U[0.5, 2]); demands D_ij ~ U[0.5, 2] (units of resource j a
+      job uses while running on it); R_j = 0.125 n/m (the roofline-64 limits
+      times the mean demand).
+    - "demands" (offset 7): the same utilities; one demand per job,
+      d_i ~ U[0.5, 2]; R_j = 0.125 n/m.
+    - "alpha-fair" (offset 8): a third each of log, capped-linear
+      (c ~ U[0.5, 2]) and alpha-fair jobs with exponent a ~ U[0, 3] in c;
+      R_j = 0.1 n/m.
+    Returns a dict of device tensors (T, w, c, kind, and D or d) and host
+    values (R, p, eps, n, m)."""
     import torch
 
+    offset = {"demand-vectors": 6, "demands": 7, "alpha-fair": 8}[variant]
     g = torch.Generator(device=device)
-    g.manual_seed(int(seed) & 0x7FFFFFFFFFFFFFFF)
+    g.manual_seed(int(BASE_SEED + offset) & 0x7FFFFFFFFFFFFFFF)
     colscale = 0.2 + 4.8 * torch.rand(m, generator=g, device=device, dtype=torch.float64)
     T = torch.randn((n, m), generator=g, device=device, dtype=torch.float32)
     T.exp_().mul_(colscale.to(torch.float32)[None, :])
-    kind = (torch.rand(n, generator=g, device=device) < 0.5).to(torch.uint8)
+    if variant == "alpha-fair":
+        kind = torch.randint(0, 3, (n,), generator=g, device=device).to(torch.uint8)
+    else:
+        kind = (torch.rand(n, generator=g, device=device) < 0.5).to(torch.uint8)
     w = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
     c = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
-    D = 0.5 + 1.5 * torch.rand((n, m), generator=g, device=device)
-    p = (0.5 + torch.rand(m, generator=g, device=device, dtype=torch.float64)).cpu().numpy()
-    return {"T": T.contiguous(), "D": D.contiguous(), "w": w, "c": c, "kind": kind,
-            "R": np.full(m, 0.125 * n / m), "p": p, "eps": 1e-3, "n": n, "m": m}
+    out = {"T": T.contiguous(), "w": w, "kind": kind, "eps": 1e-3, "n": n, "m": m}
+    if variant == "demand-vectors":
+        out["D"] = (0.5 + 1.5 * torch.rand((n, m), generator=g, device=device)).contiguous()
+    elif variant == "demands":
+        out["d"] = 0.5 + 1.5 * torch.rand(n, generator=g, device=device)
+    else:
+        a = 3.0 * torch.rand(n, generator=g, device=device)
+        c = torch.where(kind == 2, a, c)
+    out["c"] = c
+    out["p"] = (0.5 + torch.rand(m, generator=g, device=device, dtype=torch.float64)).cpu().numpy()
+    out["R"] = np.full(m, (0.1 if variant == "alpha-fair" else 0.125) * n / m)
+    return out
+
+
+def demand_vectors_device(n=10_000_000, m=64, device="cuda"):
+    """extension_device("demand-vectors")."""
+    return extension_device("demand-vectors", n=n, m=m, device=device)

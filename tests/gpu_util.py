@@ -88,8 +88,14 @@ def compare_dual(I, p, out, tol, max_mismatch_frac=1e-3):
     scale_g = abs(float(p @ I.R)) + np.abs(J["v"]).sum()
     assert abs(out["g"] - ref.g) <= tol * scale_g, (out["g"], ref.g)
     if "lower_bound" in out:
-        uabs = np.abs(job_values(I.T, np.zeros(m), I.kind, I.w.astype(np.float64),
-                                 I.c.astype(np.float64), I.eps, Xo)[0]).sum()
+        # rounding of the bound scales with the summed terms: the utilities at
+        # the scaled allocation (steep for alpha-fair exponents > 1 when the
+        # scales cut throughput) as well as at the unscaled one
+        rg = Xg.sum(0)
+        s = np.where(rg > I.R, I.R / np.maximum(rg, 1e-300), 1.0)
+        uabs = sum(np.abs(job_values(I.T, np.zeros(m), I.kind, I.w.astype(np.float64),
+                                     I.c.astype(np.float64), I.eps, X)[0]).sum()
+                   for X in (Xo, Xg * s[None, :]))
         # recovery of the GPU's own allocation, recomputed by the oracle
         G = {"jlo": jp[:, 0].astype(np.int32), "jhi": jp[:, 1].astype(np.int32),
              "xlo": xp[:, 0].copy(), "xhi": xp[:, 1].copy()}

@@ -246,3 +246,24 @@ def test_alpha_fair_exponent_one_is_log(ctx, torch):
     b = _problem(ctx, torch, I).dual_eval(p, lower_bound=True)
     assert a["g"] == b["g"] and a["lower_bound"] == b["lower_bound"]
     assert np.array_equal(a["grad"], b["grad"])
+
+
+def test_alpha_fair_exponents_near_one_and_zero(ctx, torch):
+    """Exponents one float step either side of 1, within 2^-20 of 1, exactly
+    1 (the log utility) and exactly 0 (linear, packed with the sign bit as
+    -0): finite results and parity with the oracle."""
+    I = synth.random_small(N_SMALL, 8, seed=470, dtype=np.float32)
+    one = np.float32(1.0)
+    exps = np.array([np.nextafter(one, np.float32(0)), np.nextafter(one, np.float32(2)),
+                     one - np.float32(2.0 ** -20), one + np.float32(2.0 ** -20), one,
+                     np.float32(0.0)], dtype=np.float32)
+    sel = np.arange(I.n) % 3 != 0
+    I.kind = np.where(sel, 2, I.kind).astype(np.uint8)
+    I.c = np.where(sel, exps[np.arange(I.n) % len(exps)], I.c).astype(np.float32)
+    pr = _problem(ctx, torch, I)
+    for p in (np.ones(8), 0.3 + np.random.default_rng(471).random(8) * 2):
+        p = round_prices(p, np.float32)
+        out = pr.dual_eval(p, lower_bound=True, support=True, j1=True)
+        assert np.isfinite(out["g"]) and np.isfinite(out["lower_bound"])
+        compare_dual(I, p, out, 1e-5)
+    pr.close()
