@@ -79,9 +79,11 @@ def cpu_baseline(p, target_s=15.0, max_rows=10_000_000):
     """The FP64 oracle's dual evaluation on rows [0, S) of the same instance."""
     import oracle
     import synth
-    cal = 65536
+    cal = 131072
     T, kind, w, c = synth.roofline_rows(0, cal)
     R = np.full(64, 0.1 * 1e7 / 64)
+    # start the thread pool and touch the pages before timing the calibration
+    oracle.dual_eval(T[:8192], w[:8192], c[:8192], kind[:8192], 1e-3, R, p)
     t0 = time.perf_counter()
     oracle.dual_eval(T, w, c, kind, 1e-3, R, p)
     per_row = (time.perf_counter() - t0) / cal
