@@ -87,6 +87,8 @@ def lib():
         L.orc_solve_d.argtypes = L.orc_solve.argtypes + [_p, ctypes.c_int]
         L.orc_init_prices.restype = ctypes.c_int
         L.orc_init_prices.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p, _p, _d, _p, _p]
+        L.orc_first_vertex.restype = None
+        L.orc_first_vertex.argtypes = [_i64, ctypes.c_int, ctypes.c_int, _p, _p, _p]
         L.orc_init_prices_d.restype = ctypes.c_int
         L.orc_init_prices_d.argtypes = L.orc_init_prices.argtypes + [_p, ctypes.c_int]
         L.orc_num_threads.restype = ctypes.c_int
@@ -256,6 +258,17 @@ def dense_allocation(n, m, jobs):
     hi = jobs["jhi"] >= 0
     X[idx[hi], jobs["jhi"][hi]] += jobs["xhi"][hi]
     return X
+
+
+def first_vertex(T, p):
+    """Each job's first envelope vertex decided in T's element type (the key
+    a_ij * (1/p_j) rounded to it; lowest index on equal keys; -1 if none)."""
+    T = np.ascontiguousarray(T)
+    n, m = T.shape
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    j1 = np.empty(n, np.int32)
+    lib().orc_first_vertex(n, m, _tdt(T), _ptr(T), _ptr(p), _ptr(j1))
+    return j1
 
 
 def num_threads():

@@ -641,6 +641,47 @@ int orc_init_prices(int64_t n, int m, int tdt, const void *T, const void *w, con
     return orc_init_prices_d(n, m, tdt, T, w, c, kind, eps, R, p, NULL, 0);
 }
 
+/* First lower-envelope vertex of every job (§4.1: the segment from the origin
+ * with the least cost per unit of throughput) decided in the element type of
+ * T: the key a_ij * (1/p_j) is formed with 1/p_j rounded to that type
+ * (+inf for p_j = 0) and the product rounded to it, and the largest key wins
+ * with the lowest index on equal keys (a key of 0 or NaN, from a_ij = 0,
+ * never wins; -1 when no key is positive).  This is the decision a
+ * single-precision implementation takes for FP32 data: it equals the exact
+ * argmax of a_ij / p_j except on near-ties. */
+void orc_first_vertex(int64_t n, int m, int tdt, const void *T, const double *p, int32_t *j1)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        int best_j = -1;
+        if (tdt == 0) {
+            const float *a = (const float *)T + i * m;
+            float best = 0.0f;
+            for (int j = 0; j < m; ++j) {
+                const float pf = (float)p[j];
+                const float ip = pf > 0.0f ? 1.0f / pf : INFINITY;
+                const float key = a[j] * ip;
+                if (key > best) {
+                    best = key;
+                    best_j = j;
+                }
+            }
+        } else {
+            const double *a = (const double *)T + i * m;
+            double best = 0.0;
+            for (int j = 0; j < m; ++j) {
+                const double ip = p[j] > 0.0 ? 1.0 / p[j] : INFINITY;
+                const double key = a[j] * ip;
+                if (key > best) {
+                    best = key;
+                    best_j = j;
+                }
+            }
+        }
+        j1[i] = best_j;
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -65,7 +65,13 @@ def _check_eval(I, D, p, out, tol):
     xp = out["x_pair"].cpu().numpy().astype(np.float64)
     same = (jp[:, 1] == ref.jobs["jhi"]) & np.isclose(xp[:, 1], ref.jobs["xhi"], atol=1e-4)
     assert same.mean() >= 0.999
+    # j1 at the prices d_i * p: the kernel forms 1/(d_ij p_j) with the
+    # hardware reciprocal (about 1 ulp), which no CPU code reproduces bit for
+    # bit, so it is compared with the exact argmax wherever that is not a
+    # near-tie, and nearly everywhere overall
     j1 = out["j1"].cpu().numpy().astype(np.int64)
+    clear = ref.jobs["margin1"] > 1e-5
+    assert np.array_equal(j1[clear], ref.jobs["j1"][clear])
     assert (j1 == ref.jobs["j1"]).mean() >= 0.999
 
 

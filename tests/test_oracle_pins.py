@@ -743,3 +743,42 @@ def test_demand_vectors_init_prices():
     assert p1[2] == pytest.approx(p0[2] / 4, rel=1e-12)
     for j in (0, 1, 3):
         assert p1[j] == pytest.approx(p0[j], rel=1e-12)
+
+
+# ------------------------------- first vertex in the element type -----
+
+def test_first_vertex_matches_exact_argmax_off_ties():
+    """The element-type decision equals the exact argmax of a_ij / p_j (numpy,
+    FP64) wherever the best key beats the runner-up by more than 1e-6."""
+    for dtype in (np.float32, np.float64):
+        I = synth.random_small(4000, 16, seed=90, dtype=dtype, zero_frac=0.1)
+        p = (0.2 + np.random.default_rng(91).random(16) * 2).astype(dtype).astype(np.float64)
+        j1 = oracle.first_vertex(I.T, p)
+        keys = I.T.astype(np.float64) / p[None, :]
+        srt = np.sort(keys, axis=1)
+        clear = (srt[:, -1] - srt[:, -2]) > 1e-6 * srt[:, -1]
+        assert clear.mean() > 0.99
+        assert np.array_equal(j1[clear], np.argmax(keys, axis=1)[clear])
+
+
+def test_first_vertex_ties_zero_prices_and_zero_rows():
+    for dtype in (np.float32, np.float64):
+        T = np.array([[1.0, 2.0, 0.5],     # keys 1, 1, 0.25: equal keys -> lowest index
+                      [0.5, 2.0, 1.0],     # two free resources: the first +inf key wins
+                      [0.0, 0.0, 0.0],     # nothing to buy
+                      [0.0, 3.0, 0.0]],    # zero entries never win
+                     dtype=dtype)
+        p = np.array([1.0, 2.0, 2.0])
+        pz = np.array([0.0, 0.0, 3.0])
+        assert list(oracle.first_vertex(T[[0, 2, 3]], p)) == [0, -1, 1]
+        assert oracle.first_vertex(T[[1]], pz)[0] == 0
+        assert oracle.first_vertex(np.array([[0.0, 2.0, 1.0]], dtype=dtype), pz)[0] == 1
+
+
+def test_first_vertex_decided_in_single_precision():
+    """Keys that differ below FP32 resolution tie in FP32 (lowest index) but
+    not in FP64: the decision is taken in the data's own precision."""
+    T64 = np.array([[1.0, 1.0 + 1e-9]])
+    p = np.array([1.0, 1.0])
+    assert oracle.first_vertex(T64, p)[0] == 1
+    assert oracle.first_vertex(T64.astype(np.float32), p)[0] == 0
