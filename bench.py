@@ -317,6 +317,68 @@ def bench_solves(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_dual_evals(args):
+    """The dual evaluation alone (gradient and value, no lower bound) on the
+    three single-instance configurations at fixed prices p = 1 and p = p*
+    (the certified prices of a long GPU solve, rounded to the data type):
+    3 warm-up and 50 timed evaluations each, the kernel timed with HIP events
+    on the library's stream; median and min, entries/s, GB/s and the
+    fraction of 8 TB/s, plus the wall time of one whole ra_dual_eval call."""
+    import torch
+    import synth
+    import paper_2104_00282_amd as ra
+
+    ctx = ra.Context(0)
+    dev = torch.device("cuda:0")
+    rows = {}
+    for name, gen in (("small-log", synth.small_log), ("mixed-16", synth.mixed_16),
+                      ("roofline-64", synth.roofline_64)):
+        log("%s: generating" % name)
+        I = gen()
+        T = torch.from_numpy(I.T).to(dev)
+        w = torch.from_numpy(I.w).to(dev)
+        c = torch.from_numpy(I.c).to(dev)
+        kind = torch.from_numpy(I.kind).to(dev)
+        prob = ra.Problem(ctx, T, w, c, kind, I.R, I.eps, validate=False)
+        pstar, sinfo, _ = prob.solve(tol_rel=0.0, max_iter=args.floor_iters,
+                                     stall_evals=args.stall_evals)
+        esz = I.T.dtype.itemsize
+        nbytes = I.n * I.m * esz + I.n * 2 * esz
+        row = {"n": I.n, "m": I.m, "dtype": "f64" if esz == 8 else "f32",
+               "bytes_per_evaluation": nbytes, "p_star_rel_gap": sinfo["rel_gap"]}
+        for label, p in (("p=1", np.ones(I.m)), ("p=p*", pstar)):
+            p = np.asarray(p, dtype=I.T.dtype).astype(np.float64)
+            ks, ws = [], []
+            for k in range(53):
+                ra.ra_set_kernel_timing(ctx.handle, True)
+                t0 = time.perf_counter()
+                prob.dual_eval(p)
+                wall = time.perf_counter() - t0
+                kms, launches = ra.ra_get_kernel_timing(ctx.handle)
+                ra.ra_set_kernel_timing(ctx.handle, False)
+                if k >= 3:
+                    ks.append(kms / launches)
+                    ws.append(wall * 1e3)
+            med, mn = float(np.median(ks)), float(np.min(ks))
+            row[label] = {"kernel_median_ms": med, "kernel_min_ms": mn,
+                          "entries_per_s_at_median": I.n * I.m / (med / 1e3),
+                          "GB/s_at_median": nbytes / (med / 1e3) / 1e9,
+                          "frac_of_8TB/s_at_median": nbytes / (med / 1e3) / 1e9 / HBM_PEAK_GBS,
+                          "call_wall_median_ms": float(np.median(ws))}
+        rows[name] = row
+        log("%s: %s" % (name, json.dumps(row)))
+        prob.close()
+        del T, w, c, kind
+    out = {"metric": "dual evaluation kernel time at fixed prices per configuration",
+           "value": rows["mixed-16"]["p=p*"]["kernel_median_ms"], "unit": "ms (mixed-16, p*)",
+           "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "small-log (FP64), mixed-16, roofline-64; gradient and value "
+                                  "only, 50 timed evaluations per price vector"},
+           "evaluations": rows}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch_rounds(args):
     """Throughput of one batched round (all instances active, fixed prices
     path of the solver, 10 rounds timed on the host after 3 untimed) for
@@ -535,7 +597,7 @@ def main():
                     help="only run the plain copy used to scale the HBM counters")
     ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
                                            "batch-rounds", "e1", "demand-vectors", "demands",
-                                           "alpha-fair"],
+                                           "alpha-fair", "dual-evals"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
@@ -556,14 +618,14 @@ def main():
         calibrate_copy()
         return
     if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1",
-                         "demand-vectors", "demands", "alpha-fair"):
+                         "demand-vectors", "demands", "alpha-fair", "dual-evals"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batched": bench_batched, "warmstart": bench_warmstart,
          "solves": bench_solves, "batch-rounds": bench_batch_rounds,
          "e1": bench_e1, "demand-vectors": bench_extension, "demands": bench_extension,
-         "alpha-fair": bench_extension}[args.workload](args)
+         "alpha-fair": bench_extension, "dual-evals": bench_dual_evals}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
