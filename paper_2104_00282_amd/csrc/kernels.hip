@@ -106,17 +106,31 @@ struct SharedPrices {
     __device__ __forceinline__ F at(int j) const { return Pdyn[j]; }
 };
 
-// A job with a demand vector d (§7, extensions) pays d_j p_j per unit of x_j;
-// D reads the job's demands as Row reads its throughputs.
-template <typename F, class D>
+// The prices of a kernel argument block (vectorised kernels): wave-uniform
+// scalar reads from the argument segment (PREV: the previous prices q),
+// per-lane reads from a copy in LDS.
+template <int M>
+using ArgPtr = const __attribute__((address_space(4))) PriceArgs<M>*;
+
+template <int M, bool PREV>
+struct ArgPrices {
+    ArgPtr<M> a;
+    const float* tab;
+    __device__ __forceinline__ float get(int j) const { return PREV ? a->q[j] : a->p[j]; }
+    __device__ __forceinline__ float inv(int j) const { return PREV ? a->invq[j] : a->invp[j]; }
+    __device__ __forceinline__ float at(int j) const { return tab[j]; }
+};
+
+// A job with a demand vector d (§7, extensions) pays d_j p_j per unit of x_j:
+// the base prices B scaled by the job's demands, read by D as Row reads its
+// throughputs.
+template <typename F, class B, class D>
 struct DemandPrices {
-    const F* __restrict__ P;
-    const F* __restrict__ IP;
-    const F* Pdyn;
+    B b;
     D d;
-    __device__ __forceinline__ F get(int j) const { return P[j] * d.get(j); }
-    __device__ __forceinline__ F inv(int j) const { return IP[j] * frcp(d.get(j)); }
-    __device__ __forceinline__ F at(int j) const { return Pdyn[j] * d.at(j); }
+    __device__ __forceinline__ F get(int j) const { return b.get(j) * d.get(j); }
+    __device__ __forceinline__ F inv(int j) const { return b.inv(j) * frcp(d.get(j)); }
+    __device__ __forceinline__ F at(int j) const { return b.at(j) * d.at(j); }
 };
 
 // First envelope vertex: largest key a_j * (1/p_j); lowest j on exact ties;
@@ -334,10 +348,12 @@ struct GlobalRow {
 // ------------------------------------------------------------------------
 // Dual kernel, FP32, m = M in {4, 8, 16, 32, 64}, T 16-byte aligned.
 // ------------------------------------------------------------------------
+// The price block is the first kernel argument, so it starts the argument
+// segment (the AMDGPU kernel ABI lays arguments out in order from offset 0).
 template <int M, bool DEM, bool DV>
 __global__ void __launch_bounds__(256) k_dual_vec(
-    const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
-    const PriceBlock<float>* __restrict__ pb, float eps, double* __restrict__ partial,
+    const PriceArgs<M> pa, const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
+    float eps, double* __restrict__ partial,
     int* __restrict__ jpair, float2* __restrict__ xpair, float2* __restrict__ tpair,
     int16_t* __restrict__ j1out, const float* __restrict__ dem, const float* __restrict__ dvec)
 {
@@ -356,16 +372,12 @@ __global__ void __launch_bounds__(256) k_dual_vec(
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const float* __restrict__ P = pb->p;
-    const float* __restrict__ IP = pb->invp;
-    const float* __restrict__ Qp = pb->q;
-    const float* __restrict__ IQ = pb->invq;
-    const bool prev = pb->has_prev != 0;
+    const bool prev = pa.has_prev != 0;
     if (threadIdx.x < M) {
-        ptab[threadIdx.x] = P[threadIdx.x];
-        qtab[threadIdx.x] = Qp[threadIdx.x];
-        stab[threadIdx.x] = pb->s[threadIdx.x];
-        sctab[threadIdx.x] = pb->sc[threadIdx.x];
+        ptab[threadIdx.x] = pa.p[threadIdx.x];
+        qtab[threadIdx.x] = pa.q[threadIdx.x];
+        stab[threadIdx.x] = pa.s[threadIdx.x];
+        sctab[threadIdx.x] = pa.sc[threadIdx.x];
     }
     if (lane < M) hist[wv][lane] = 0.f;
     __syncthreads();
@@ -458,22 +470,28 @@ __global__ void __launch_bounds__(256) k_dual_vec(
             }
             const LdsRow drow{dtl + lane * S};
             const bool caplin = is_capped(wc.y);
-            auto solve = [&](const float* Pp, const float* IPp, const float* tab, Job<float>& out) {
+            auto solve = [&](auto base, Job<float>& out) {
                 if constexpr (DV)
-                    solve_job<float, M>(row, M, DemandPrices<float, LdsRow>{Pp, IPp, tab, drow},
+                    solve_job<float, M>(row, M,
+                                        DemandPrices<float, decltype(base), LdsRow>{base, drow},
                                         wc.x, wc.y, caplin, eps, out);
                 else
-                    solve_job<float, M>(row, M, SharedPrices<float>{Pp, IPp, tab}, wc.x, wc.y,
-                                        caplin, eps, out);
+                    solve_job<float, M>(row, M, base, wc.x, wc.y, caplin, eps, out);
             };
+            // the price block at the start of the argument segment, its address
+            // made opaque once per tile: the prices are then read again for
+            // every tile instead of being held in scalar registers across the
+            // loop (4 M of them would not fit)
+            ArgPtr<M> pk = (ArgPtr<M>)__builtin_amdgcn_kernarg_segment_ptr();
+            asm volatile("" : "+s"(pk));
             Job<float> J;
-            solve(P, IP, ptab, J);
+            solve(ArgPrices<M, false>{pk, ptab}, J);
             if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? drow.at(J.jlo) : dj) * J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? drow.at(J.jhi) : dj) * J.xhi);
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<float> K;
-                solve(Qp, IQ, qtab, K);
+                solve(ArgPrices<M, true>{pk, qtab}, K);
                 float u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab,
                                u, loss);
@@ -557,8 +575,10 @@ __global__ void __launch_bounds__(256) k_dual_gen(
             const GlobalRow<F> drow{DV ? dvec + i * m : nullptr};
             auto solve = [&](const F* Pp, const F* IPp, Job<F>& out) {
                 if constexpr (DV)
-                    solve_job<F, 0>(row, m, DemandPrices<F, GlobalRow<F>>{Pp, IPp, Pp, drow}, wc.x,
-                                    wc.y, caplin, eps, out);
+                    solve_job<F, 0>(row, m,
+                                    DemandPrices<F, SharedPrices<F>, GlobalRow<F>>{
+                                        SharedPrices<F>{Pp, IPp, Pp}, drow},
+                                    wc.x, wc.y, caplin, eps, out);
                 else
                     solve_job<F, 0>(row, m, SharedPrices<F>{Pp, IPp, Pp}, wc.x, wc.y, caplin, eps,
                                     out);
@@ -1248,10 +1268,45 @@ int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok, bool dv)
     return (int)(g < 1 ? 1 : g);
 }
 
+template <int M>
+static PriceArgs<M> price_args(const PriceBlock<float>& h)
+{
+    PriceArgs<M> a;
+    for (int j = 0; j < M; ++j) {
+        a.p[j] = h.p[j];
+        a.invp[j] = h.invp[j];
+        a.q[j] = h.q[j];
+        a.invq[j] = h.invq[j];
+        a.s[j] = h.s[j];
+        a.sc[j] = h.sc[j];
+    }
+    a.has_prev = h.has_prev;
+    return a;
+}
+
+template <int M>
+static void launch_vec(int grid, hipStream_t st, const float* T, const float2* prm, int64_t n,
+                       const PriceBlock<float>& h, float eps, double* partial, int* jp,
+                       float2* xp, float2* tp, int16_t* j1, const float* dem, const float* dv)
+{
+    const PriceArgs<M> a = price_args<M>(h);
+    if (dv)
+        k_dual_vec<M, false, true><<<grid, 256, 0, st>>>(a, T, prm, n, eps, partial, jp, xp, tp,
+                                                         j1, nullptr, dv);
+    else if (dem)
+        k_dual_vec<M, true, false><<<grid, 256, 0, st>>>(a, T, prm, n, eps, partial, jp, xp, tp,
+                                                         j1, dem, nullptr);
+    else
+        k_dual_vec<M, false, false><<<grid, 256, 0, st>>>(a, T, prm, n, eps, partial, jp, xp,
+                                                          tp, j1, nullptr, nullptr);
+}
+
+bool dual_is_vec(int dtype, int m, bool vec_ok) { return dtype == 0 && vec_ok && vec_class(m); }
+
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
-                       const void* prm, int64_t n, const void* prices, double eps,
-                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1,
-                       const void* dem, const void* dvec)
+                       const void* prm, int64_t n, const void* prices, const void* host_prices,
+                       double eps, double* partial, int16_t* jpair, void* xpair, void* tpair,
+                       int16_t* j1, const void* dem, const void* dvec)
 {
     int* jp = reinterpret_cast<int*>(jpair);
     if (dtype == 0) {
@@ -1263,25 +1318,14 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
         const float e = (float)eps;
         const float* df = static_cast<const float*>(dem);
         const float* dv = static_cast<const float*>(dvec);
-#define DUAL_VEC(MM)                                                                        \
-    do {                                                                                    \
-        if (dv)                                                                             \
-            k_dual_vec<MM, false, true><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp,  \
-                                                              xp, tp, j1, nullptr, dv);     \
-        else if (df)                                                                        \
-            k_dual_vec<MM, true, false><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp,  \
-                                                              xp, tp, j1, df, nullptr);     \
-        else                                                                                \
-            k_dual_vec<MM, false, false><<<grid, 256, 0, st>>>(Tf, pr, n, pb, e, partial, jp, \
-                                                               xp, tp, j1, nullptr, nullptr); \
-    } while (0)
-        if (vec_ok && vec_class(m)) {
+        if (dual_is_vec(dtype, m, vec_ok)) {
+            const auto& h = *static_cast<const PriceBlock<float>*>(host_prices);
             switch (m) {
-            case 4: DUAL_VEC(4); break;
-            case 8: DUAL_VEC(8); break;
-            case 16: DUAL_VEC(16); break;
-            case 32: DUAL_VEC(32); break;
-            default: DUAL_VEC(64); break;
+            case 4: launch_vec<4>(grid, st, Tf, pr, n, h, e, partial, jp, xp, tp, j1, df, dv); break;
+            case 8: launch_vec<8>(grid, st, Tf, pr, n, h, e, partial, jp, xp, tp, j1, df, dv); break;
+            case 16: launch_vec<16>(grid, st, Tf, pr, n, h, e, partial, jp, xp, tp, j1, df, dv); break;
+            case 32: launch_vec<32>(grid, st, Tf, pr, n, h, e, partial, jp, xp, tp, j1, df, dv); break;
+            default: launch_vec<64>(grid, st, Tf, pr, n, h, e, partial, jp, xp, tp, j1, df, dv); break;
             }
         } else if (dv) {
             k_dual_gen<float, true><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp, tp,
@@ -1290,7 +1334,6 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
             k_dual_gen<float, false><<<grid, 256, 0, st>>>(Tf, pr, n, m, pb, e, partial, jp, xp,
                                                            tp, j1, df, nullptr);
         }
-#undef DUAL_VEC
     } else {
         const double* Td = static_cast<const double*>(T);
         const double2* pr = static_cast<const double2*>(prm);

@@ -22,6 +22,14 @@ struct PriceBlock {
     int has_prev;
 };
 
+// The same prices for the vectorised kernels (m = M), passed by value as a
+// kernel argument: no copy to device memory before a pass.
+template <int M>
+struct PriceArgs {
+    float p[M], invp[M], q[M], invq[M], s[M], sc[M];
+    int has_prev;
+};
+
 // Columns of one row of dual-kernel block partials: r_j (m), then the sums of
 // net utilities, of scaled utilities U(X~) and of utility lost by scaling.
 inline int partial_cols(int m) { return m + 3; }
@@ -68,11 +76,17 @@ int dual_grid(int dev_cus, int m, int dtype, int64_t n, bool vec_ok, bool dv = f
 // tpair (n x 2 F, a_lo x_lo and a_hi x_hi), j1 (n int16).
 // dem: per-job scalar demands (n, with w_i / d_i packed in prm); dvec:
 // per-job demand vectors (n x m, like T; 16-byte aligned when vec_ok);
-// at most one of the two.
+// at most one of the two.  prices: the device price block, read by the
+// generic kernels; host_prices: the same block in host memory, from which
+// the vectorised kernels take their prices as a kernel argument (those need
+// no device copy: see dual_is_vec).
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
-                       const void* prm, int64_t n, const void* prices, double eps,
-                       double* partial, int16_t* jpair, void* xpair, void* tpair, int16_t* j1,
-                       const void* dem = nullptr, const void* dvec = nullptr);
+                       const void* prm, int64_t n, const void* prices, const void* host_prices,
+                       double eps, double* partial, int16_t* jpair, void* xpair, void* tpair,
+                       int16_t* j1, const void* dem = nullptr, const void* dvec = nullptr);
+
+// True when launch_dual uses a vectorised kernel (prices as a kernel argument).
+bool dual_is_vec(int dtype, int m, bool vec_ok);
 
 // Data-dependent starting prices: partial [grid][m] gets, per block, the sums
 // of u_i'(a_i^T x) a_ij with x = prices->p (the uniform share of R), each

@@ -117,14 +117,16 @@ ra_status enqueue_eval(ra_problem* P, bool lb, int16_t* jpair_user, void* xpair_
 {
     ra_ctx* ctx = P->ctx;
     hipStream_t st = ctx->stream;
-    RA_HIP(ctx, hipMemcpyAsync(P->pblock, P->h_pblock, price_block_bytes(P->dt),
-                               hipMemcpyHostToDevice, st));
+    // the vectorised kernels take their prices as a kernel argument
+    if (!ra::dual_is_vec(P->dt, P->m, dual_vec(P)))
+        RA_HIP(ctx, hipMemcpyAsync(P->pblock, P->h_pblock, price_block_bytes(P->dt),
+                                   hipMemcpyHostToDevice, st));
     int16_t* jp = jpair_user ? jpair_user : (lb ? P->jpair_ws : nullptr);
     void* tp = lb ? P->tpair_ws : nullptr;
     if (ctx->timing) RA_HIP(ctx, hipEventRecord(ctx->ev0, st));
     RA_HIP(ctx, ra::launch_dual(P->dt, P->m, dual_vec(P), P->grid, st, P->T, P->prm, P->n,
-                                P->pblock, P->eps, P->partial, jp, jpair_user ? xpair_user : nullptr,
-                                tp, j1_user, P->dem, P->dvec));
+                                P->pblock, P->h_pblock, P->eps, P->partial, jp,
+                                jpair_user ? xpair_user : nullptr, tp, j1_user, P->dem, P->dvec));
     if (ctx->timing) {
         RA_HIP(ctx, hipEventRecord(ctx->ev1, st));
         ctx->timed_pending = true;
@@ -243,7 +245,9 @@ ra_status run_pass(ra_problem* P, const std::vector<double>& p, const ra::Point*
     const double pR = fill_prices(P, p.data(), &p_eval);
     if (prev) fill_prev(P, prev->p, prev->r);
     __atomic_store_n(P->h_flag, 0u, __ATOMIC_RELEASE);
-    if (use_graph && !ctx->timing) {
+    // a captured graph would keep the kernel arguments of its capture, so the
+    // vectorised kernels (prices as an argument) are launched directly
+    if (use_graph && !ctx->timing && !ra::dual_is_vec(P->dt, P->m, dual_vec(P))) {
         ra_status st = capture_graph(P);
         if (st != RA_OK) return st;
         RA_HIP(ctx, hipGraphLaunch(P->gexec, ctx->stream));
