@@ -206,3 +206,48 @@ def test_full_size_sampled_parity(ctx, torch):
     same = (jps[:, 1] == ref.jobs["jhi"]) & np.isclose(xps[:, 1], ref.jobs["xhi"], atol=1e-4)
     assert same.mean() >= 0.998
     pr.close()
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (1, 4), (130, 4), (130, 5), (300, 16)])
+def test_demand_vectors_edge_cases(ctx, torch, n, m):
+    """A single job, a single resource, exact zero throughputs (20 %), free
+    resources (p_j = 0) and alpha-fair jobs beside log and capped-linear ones,
+    all with demand vectors: parity with the oracle.  Free resources make
+    many allocations optimal (a capped job can fill its cap from any mix of
+    them), so jobs whose allocation differs from the oracle's must be optimal
+    at d_i * p, and r must be the d-weighted sum of the kernel's own
+    allocations."""
+    from gpu_util import dense_x, job_values
+    print("demand vectors edge n=%d m=%d" % (n, m), flush=True)
+    I = synth.random_small(n, m, seed=870 + n + m, dtype=np.float32, zero_frac=0.2)
+    rng = np.random.default_rng(871 + n + m)
+    af = rng.random(n) < 0.3
+    I.kind = np.where(af, 2, I.kind).astype(np.uint8)
+    I.c = np.where(af, rng.choice([0.0, 0.5, 2.0], n), I.c).astype(np.float32)
+    D = _dvec(n, m, 872 + n + m, np.float32)
+    pr = _problem(ctx, torch, I, D)
+    p0 = 0.3 + rng.random(m) * 2
+    pz = p0.copy()
+    pz[rng.random(m) < 0.4] = 0.0
+    for p in (p0, pz):
+        p = round_prices(p, np.float32)
+        out = pr.dual_eval(p, lower_bound=True, support=True, j1=True)
+        ref = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True, d=D)
+        scale = abs(float(p @ I.R)) + np.abs(ref.jobs["v"]).sum() + 1.0
+        assert abs(out["g"] - ref.g) <= 1e-5 * scale
+        jp = out["j_pair"].cpu().numpy().astype(np.int64)
+        xp = out["x_pair"].cpu().numpy().astype(np.float64)
+        Xg = dense_x(n, m, jp[:, 0], jp[:, 1], xp[:, 0], xp[:, 1])
+        J = ref.jobs
+        Xo = dense_x(n, m, J["jlo"], J["jhi"], J["xlo"], J["xhi"])
+        assert np.all(Xg >= 0) and np.all(Xg.sum(1) <= 1 + 1e-5)
+        u, _ = job_values(I.T, np.zeros(m), I.kind, I.w.astype(np.float64),
+                          I.c.astype(np.float64), I.eps, Xg)
+        vg = u - (Xg * D) @ p
+        assert np.all(vg >= J["v"] - 1e-5 * np.maximum(1.0, np.abs(J["v"])))
+        rg = (Xg * D).sum(0)
+        assert np.allclose(out["r"], rg, rtol=1e-5, atol=1e-5 * max(1.0, np.abs(rg).max()))
+        if np.abs(Xg - Xo).max() <= 1e-5:
+            assert np.allclose(out["r"], ref.r, rtol=1e-5,
+                               atol=1e-5 * max(1.0, np.abs(ref.r).max()))
+    pr.close()
