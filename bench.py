@@ -323,8 +323,12 @@ def bench_dual_evals(args):
     (the certified prices of a long GPU solve, rounded to the data type):
     3 warm-up and 50 timed evaluations each, the kernel timed with HIP events
     on the library's stream; median and min, entries/s, GB/s and the
-    fraction of 8 TB/s, plus the wall time of one whole ra_dual_eval call."""
+    fraction of 8 TB/s, plus the wall time of one whole ra_dual_eval call.
+    The FP64 oracle's evaluation at p* is timed beside it (median of 3) on the
+    two smaller configurations (the roofline one is the default workload's
+    sampled CPU baseline)."""
     import torch
+    import oracle
     import synth
     import paper_2104_00282_amd as ra
 
@@ -365,6 +369,15 @@ def bench_dual_evals(args):
                           "GB/s_at_median": nbytes / (med / 1e3) / 1e9,
                           "frac_of_8TB/s_at_median": nbytes / (med / 1e3) / 1e9 / HBM_PEAK_GBS,
                           "call_wall_median_ms": float(np.median(ws))}
+        if name != "roofline-64":
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p)
+                ts.append(time.perf_counter() - t0)
+            row["cpu_oracle_p*"] = {"median_ms": float(np.median(ts)) * 1e3,
+                                    "cores": oracle.num_threads(),
+                                    "gpu_speedup_vs_kernel": float(np.median(ts)) * 1e3 / med}
         rows[name] = row
         log("%s: %s" % (name, json.dumps(row)))
         prob.close()

@@ -122,8 +122,12 @@ ra_status ra_problem_destroy(ra_problem *prob);
  *   x_pair       device, n x 2 of dt or NULL: the allocation on (j_lo, j_hi)
  *                (eq. e-xixj); written only together with j_pair
  *   j1           device, n int16 or NULL: argmax_j a_ij / p_j, the first
- *                vertex of the job's cost curve (lowest j on exact ties;
- *                -1 for an all-zero row)
+ *                vertex of the job's cost curve, decided in the element type
+ *                with the key a_ij * (1/p_j) (1/p_j rounded to dt, +inf for
+ *                p_j = 0); lowest j on equal keys; -1 when no key is
+ *                positive (an all-zero row).  With demand vectors the prices
+ *                are d_ij p_j and the FP32 kernels form the reciprocal with
+ *                the hardware approximation (about 1 ulp)
  * Errors: RA_EINVAL, RA_EDEVICE, RA_ENUMERIC (non-finite g or grad). */
 ra_status ra_dual_eval(ra_ctx *ctx, const ra_problem *prob, const double *p, double *g,
                        double *grad, double *lower_bound, int16_t *j_pair, void *x_pair,
@@ -138,7 +142,10 @@ typedef struct {
     int32_t init;            /* 0 = p = 1, 1 = use p_inout as given,
                                 2 = the paper's data-dependent prices (ra_init_prices;
                                 one extra pass, included in the reported time)      */
-    int32_t use_graph;       /* 1 = replay one captured HIP graph per evaluation    */
+    int32_t use_graph;       /* 1 = replay one captured HIP graph per evaluation
+                                for the generic kernels; the vectorised FP32
+                                kernels take the prices as a kernel argument and
+                                are always launched directly                      */
     int32_t verbose;         /* 1 = one line per iteration on stderr                */
     int32_t max_evals;       /* > 0: stop after at most this many passes over T      */
     int32_t stall_evals;     /* > 0: stop when the best certified relative gap has
