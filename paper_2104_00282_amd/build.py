@@ -48,5 +48,30 @@ def build(verbose: bool = False, extra=()) -> str:
     return LIB
 
 
+C_DEMO_SRC = os.path.join(ROOT, "tests", "c_consumer", "solve_demo.c")
+C_DEMO = os.path.join(ROOT, "tests", "c_consumer", "solve_demo")
+
+
+def build_c_consumer(verbose: bool = False) -> str:
+    """Compile the plain C consumer of the C ABI used by the GPU tests
+    (gcc, linked against the in-tree libresalloc.so and the HIP runtime)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    tmp = C_DEMO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(ROOT, "include"),
+           C_DEMO_SRC, "-o", tmp, "-L", HERE, "-lresalloc", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", "-Wl,-rpath,$ORIGIN/../../paper_2104_00282_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("gcc failed building the C consumer")
+    os.replace(tmp, C_DEMO)
+    return C_DEMO
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_c_consumer(verbose=True))
