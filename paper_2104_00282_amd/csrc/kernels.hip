@@ -39,7 +39,12 @@ template <> struct Vec2<float> { using type = float2; };
 template <> struct Vec2<double> { using type = double2; };
 template <typename F> using V2 = typename Vec2<F>::type;
 
-__device__ __forceinline__ float dlog(float x) { return logf(x); }
+// FP32: the hardware base-2 logarithm times ln 2 (about 1 ulp of log2 x);
+// FP64: the device library.
+__device__ __forceinline__ float dlog(float x)
+{
+    return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+}
 __device__ __forceinline__ double dlog(double x) { return log(x); }
 // x^y for x >= 0 and y != 0 (every use here: a base t + eps or w / alpha,
 // an exponent 1 - a or 1 / a), as 2^(y log2 x) with the hardware's base-2
@@ -90,6 +95,7 @@ struct Job {
     F v;               // net utility u(t) - p^T x
 };
 
+// 1/x: FP32 with the hardware reciprocal (about 1 ulp), FP64 exactly rounded.
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 
@@ -216,13 +222,13 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const Px& px, F 
             // (linear) the right end if w > alpha, else the left end
             F tu;
             if (!AF || c == F(-1)) {
-                tu = w * den / num - eps;
+                tu = w * den * frcp(num) - eps;
             } else {
                 const F a = afair_exponent(c);
                 if (a == F(0))
                     tu = (w * den > num) ? F(INFINITY) : F(-INFINITY);
                 else
-                    tu = dpow(w * den / num, F(1) / a) - eps;
+                    tu = dpow(w * den * frcp(num), frcp(a)) - eps;
             }
             t = fmin(fmax(tu, alo), ahi);
             walk = tu >= ahi;
@@ -250,7 +256,7 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const Px& px, F 
     }
     // eq. e-xixj on the final segment (lo = -1: the origin, x_hi = t / a_hi)
     const F den = ahi - alo;
-    const F rden = F(1) / den;
+    const F rden = frcp(den);
     const F xh = (t - alo) * rden;
     const F xl = (lo >= 0) ? (ahi - t) * rden : F(0);
     J.j1 = j1;
