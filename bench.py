@@ -392,6 +392,69 @@ def bench_dual_evals(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_scale(args):
+    """One problem sized for the device's memory: n = 8e8 jobs, m = 64 (205 GB
+    of FP32 T in HBM, the roofline-64 recipe drawn on the device in row
+    chunks with torch's seeded generator).  Solver steps timed as in the
+    default workload, and a cold solve to a 1e-4 relative gap."""
+    import torch
+    import paper_2104_00282_amd as ra
+
+    n, m = args.scale_n, 64
+    dev = torch.device("cuda:0")
+    log("generating n=%d m=%d on the device (%.0f GB of T)" % (n, m, n * m * 4 / 1e9))
+    g = torch.Generator(device=dev)
+    g.manual_seed(210400282 + 9)
+    s = (0.2 + 4.8 * torch.rand(m, generator=g, device=dev)).contiguous()
+    T = torch.empty((n, m), dtype=torch.float32, device=dev)
+    chunk = 1 << 24
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        T[a:b].normal_(generator=g).exp_().mul_(s)
+    kind = (torch.rand(n, generator=g, device=dev) < 0.5).to(torch.uint8)
+    w = 0.5 + 1.5 * torch.rand(n, generator=g, device=dev)
+    c = 0.5 + 1.5 * torch.rand(n, generator=g, device=dev)
+    R = np.full(m, 0.1 * n / m)
+    torch.cuda.synchronize()
+    ctx = ra.Context(0)
+    prob = ra.Problem(ctx, T, w, c, kind, R, 1e-3, validate=False)
+    del w, c, kind
+    p, _, _ = prob.solve(tol_rel=0.0, max_iter=args.warmup, max_evals=args.warmup)
+    ra.ra_set_kernel_timing(ctx.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info, _ = prob.solve(p0=p, tol_rel=0.0, max_iter=args.steps, max_evals=args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kms, launches = ra.ra_get_kernel_timing(ctx.handle)
+    ra.ra_set_kernel_timing(ctx.handle, False)
+    steps = info["dual_evals"]
+    ms = dt * 1e3 / steps
+    kms = kms / max(launches, 1)
+    t0 = time.perf_counter()
+    _, sinfo, _ = prob.solve(tol_rel=1e-4, max_iter=200)
+    solve_s = time.perf_counter() - t0
+    bytes_per_launch = n * m * 4 + n * 8
+    achieved = bytes_per_launch / (kms / 1e3) / 1e9
+    out = {"metric": "job·resource entries/s in ∇g at the largest single-GPU size",
+           "value": n * m / (ms / 1e3), "unit": "job·resource entries/s", "n_gpus": 1,
+           "steps": steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "scale: n=%d jobs, m=%d resources (%.0f GB of T), roofline-64 "
+                                  "recipe" % (n, m, n * m * 4 / 1e9),
+                      "dual_kernel_ms": kms,
+                      "device_memory_GB": torch.cuda.max_memory_allocated() / 1e9,
+                      "solve_to_1e-4": {"seconds": solve_s, "dual_evals": sinfo["dual_evals"],
+                                        "rel_gap": sinfo["rel_gap"]}},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "dual evaluation (k_dual_vec<64, false, false>)",
+                        "bytes_per_launch": bytes_per_launch, "launches": launches}}
+    prob.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch_rounds(args):
     """Throughput of one batched round (all instances active, fixed prices
     path of the solver, 10 rounds timed on the host after 3 untimed) for
@@ -610,13 +673,15 @@ def main():
                     help="only run the plain copy used to scale the HBM counters")
     ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
                                            "batch-rounds", "e1", "demand-vectors", "demands",
-                                           "alpha-fair", "dual-evals"],
+                                           "alpha-fair", "dual-evals", "scale"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
                          "warmstart: learned start vs cold start; solves: time to gap on the "
                          "single-instance configurations")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--scale-n", type=int, default=800_000_000,
+                    help="jobs of the scale workload (m = 64; 8e8 is 205 GB of T)")
     ap.add_argument("--floor-iters", type=int, default=300)
     ap.add_argument("--stall-evals", type=int, default=100)
     ap.add_argument("--train-count", type=int, default=20000)
@@ -631,14 +696,15 @@ def main():
         calibrate_copy()
         return
     if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1",
-                         "demand-vectors", "demands", "alpha-fair", "dual-evals"):
+                         "demand-vectors", "demands", "alpha-fair", "dual-evals", "scale"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
         {"batched": bench_batched, "warmstart": bench_warmstart,
          "solves": bench_solves, "batch-rounds": bench_batch_rounds,
          "e1": bench_e1, "demand-vectors": bench_extension, "demands": bench_extension,
-         "alpha-fair": bench_extension, "dual-evals": bench_dual_evals}[args.workload](args)
+         "alpha-fair": bench_extension, "dual-evals": bench_dual_evals,
+         "scale": bench_scale}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
