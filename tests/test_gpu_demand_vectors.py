@@ -128,6 +128,14 @@ def test_solve_with_demand_vectors_certified_by_oracle(ctx, torch, m):
     assert abs(info["U_lb"] - U) <= 1e-5 * scale
     # the usage of the returned point respects R up to the certified gap
     assert np.all(ref.r <= I.R * 1.05)
+    # the dense allocation: the oracle's, with each column scaled by
+    # min(1, R_j / r_j), and within the limits in demanded units
+    X = pr.allocation(p).cpu().numpy().astype(np.float64)
+    s = np.where(ref.r > I.R, I.R / ref.r, 1.0)
+    Xo = oracle.dense_allocation(I.n, m, ref.jobs) * s[None, :]
+    assert np.all(X >= 0) and np.all(X.sum(1) <= 1 + 1e-5)
+    assert np.all((D * X).sum(0) <= I.R * (1 + 1e-5))
+    assert (np.abs(X - Xo).max(1) <= 1e-4).mean() >= 0.999
     pr.close()
 
 
