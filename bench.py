@@ -245,7 +245,9 @@ def bench_solves(args):
     max(1e-6, 1.5 floor); the floor is the best gap of a long reference run.
     Also to a relative gap of 1e-4 (entries ending in _to_1e-4).
     GPU: cold start (p = 1) and the paper's data-dependent start (its extra
-    pass included), median of 3 runs. CPU: the FP64 oracle's own solve from
+    pass included), each with the host price loop and with the price update
+    on the device (arms ending in _device_loop; small-log is FP64 and runs the
+    host loop either way), median of 3 runs. CPU: the FP64 oracle's own solve from
     p = 1 to the same target, on the two smaller configurations."""
     import torch
     import oracle
@@ -269,10 +271,14 @@ def bench_solves(args):
         floor = ref["rel_gap"]
         target = max(tol_min, 1.5 * floor)
         prob.solve(max_iter=0)  # graph capture outside the timings
+        prob.solve(max_iter=0, device_loop=True)
         row = {"n": I.n, "m": I.m, "dtype": "f64" if I.T.dtype == np.float64 else "f32",
                "floor": floor, "target": target}
         for level, tol in (("", target), ("_to_1e-4", max(1e-4, target))):
-            for arm, kw in (("gpu_cold", {}), ("gpu_paper_init", {"paper_init": True})):
+            for arm, kw in (("gpu_cold", {}), ("gpu_paper_init", {"paper_init": True}),
+                            ("gpu_cold_device_loop", {"device_loop": True}),
+                            ("gpu_paper_init_device_loop", {"paper_init": True,
+                                                            "device_loop": True})):
                 runs = []
                 for _ in range(3):
                     torch.cuda.synchronize()
@@ -505,7 +511,8 @@ def bench_e1(args):
     """The paper's medium-size example (§6.2: n = 1e6, m = 4, log and
     target-priority utilities) solved from the paper's start to its tolerance
     g - U <= 1e-3 n: wall time (median of 5, the start's pass included),
-    iterations, and the allocation's outcome shares the paper prints."""
+    iterations, and the allocation's outcome shares the paper prints; the same
+    solve with the price update on the device beside it."""
     import torch
     import synth
     import paper_2104_00282_amd as ra
@@ -521,6 +528,15 @@ def bench_e1(args):
         ts = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (I.T, I.w, I.c, I.kind)]
         pr = ra.Problem(ctx, ts[0], ts[1], ts[2], ts[3], I.R, I.eps, validate=False)
         pr.solve(max_iter=0)
+        pr.solve(max_iter=0, device_loop=True)
+        dev_runs = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, dinfo, _ = pr.solve(tol_rel=0.0, tol_abs=1e-3 * n, max_iter=300, paper_init=True,
+                                   device_loop=True)
+            dev_runs.append((time.perf_counter() - t0, dinfo))
+        dev_runs.sort(key=lambda r: r[0])
         runs = []
         for _ in range(5):
             torch.cuda.synchronize()
@@ -535,7 +551,12 @@ def bench_e1(args):
                       "gap_per_job": (info["g"] - info["U_lb"]) / n,
                       "prices": [float(v) for v in p],
                       "statistics": allocation_statistics(I.T, I.w, I.c, I.kind, X),
-                      "paper_seconds_their_gpu": paper_gpu_s[kind]}
+                      "paper_seconds_their_gpu": paper_gpu_s[kind],
+                      "device_loop": {"seconds": dev_runs[2][0],
+                                      "iters": dev_runs[2][1]["iters"],
+                                      "dual_evals": dev_runs[2][1]["dual_evals"],
+                                      "gap_per_job": (dev_runs[2][1]["g"]
+                                                      - dev_runs[2][1]["U_lb"]) / n}}
         log("%s: %s" % (kind, json.dumps(rows[kind])))
         pr.close()
     out = {"metric": "time to the paper's tolerance (g - U <= 1e-3 n), medium-size example",

@@ -156,12 +156,30 @@ typedef struct {
                                 must be finite, 0 <= init_step <= 10               */
     double tol_abs;          /* > 0: also stop when g - U(X~) <= tol_abs (Algorithm 2's
                                 absolute test; the paper suggests 1e-3 n)          */
+    int32_t device_loop;     /* 1: run the price update itself on the device: after
+                                each pass, the kernel that sums its columns also
+                                takes the L-BFGS step (one wave, FP64) and writes
+                                the next prices, and the host replays graphs of 6
+                                passes until the loop publishes its outcome in
+                                pinned memory.  Applies to problems on the
+                                vectorised kernels (FP32 T, m in {4, 8, 16, 32,
+                                64}, T and any demand vectors 16-byte aligned)
+                                with lbfgs_mem <= 32, verbose = 0 and timing off;
+                                otherwise the host loop runs.  Same iteration as
+                                the host loop; its dot products are summed in
+                                another order, so iterates agree to rounding.
+                                Spare passes of the last replay (no-ops) may
+                                still be queued on the context's stream when the
+                                call returns.  ra_batch_solve ignores it.  0 or 1 */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
 typedef struct {
     int32_t iters;           /* price updates taken                                  */
-    int32_t dual_evals;      /* dual evaluations (line-search trials included)       */
+    int32_t dual_evals;      /* points evaluated and taken into the iteration (line-
+                                search trials included); a last pass whose only
+                                use was to certify the previous point is not
+                                counted                                           */
     int32_t fell_back;       /* projected-subgradient steps taken                     */
     int32_t converged;       /* 1 if rel_gap <= tol_rel                               */
     double g;                /* dual value at the returned prices (upper bound)      */
@@ -174,7 +192,8 @@ typedef struct {
 
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
- * stall_evals = 0 (off), init_step = 0 (default step), tol_abs = 0 (off). */
+ * stall_evals = 0 (off), init_step = 0 (default step), tol_abs = 0 (off),
+ * device_loop = 0. */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
 /* Per-job demands (§7, "Extensions and variations"): the usage limit becomes

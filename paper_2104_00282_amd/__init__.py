@@ -143,13 +143,14 @@ class Problem:
 
     def solve(self, p0=None, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, method=0, use_graph=True,
               verbose=False, max_evals=0, stall_evals=0, init_step=0.0, paper_init=False,
-              tol_abs=0.0):
+              tol_abs=0.0, device_loop=False):
         """Price discovery; returns (p, info dict, status).  paper_init starts
         from the paper's data-dependent prices (ra_init_prices) unless p0 is
         given."""
         o = ra_solve_opts_default()
         o.init_step = init_step
         o.tol_abs = tol_abs
+        o.device_loop = 1 if device_loop else 0
         o.max_evals = max_evals
         o.stall_evals = stall_evals
         o.tol_rel = tol_rel

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libresalloc.so")
-SOURCES = ["kernels.hip", "runtime.hip", "mlp.hip", "probe.hip"]
+SOURCES = ["kernels.hip", "runtime.hip", "mlp.hip", "probe.hip", "loop.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -26,6 +26,7 @@
 // accumulators after every tile, reduced across the block in a fixed order
 // and written as one row of block partials; no global atomics are used, so
 // results are reproducible bit for bit.
+#include "colsum.hpp"
 #include "ra_kernels.h"
 
 #include <math.h>
@@ -361,8 +362,14 @@ __global__ void __launch_bounds__(256) k_dual_vec(
     const PriceArgs<M> pa, const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
     float eps, double* __restrict__ partial,
     int* __restrict__ jpair, float2* __restrict__ xpair, float2* __restrict__ tpair,
-    int16_t* __restrict__ j1out, const float* __restrict__ dem, const float* __restrict__ dvec)
+    int16_t* __restrict__ j1out, const float* __restrict__ dem, const float* __restrict__ dvec,
+    const PriceArgs<M>* __restrict__ dpa, const int* __restrict__ skip)
 {
+    // dpa (optional): the prices in device memory, written by the device
+    // price loop, instead of the argument block; skip (optional): when *skip
+    // is set the pass is not needed (the loop has ended) and the kernel
+    // returns at once.
+    if (skip && *skip) return;
     // dem (DEM, optional): per-job demands d_i; prm then holds w_i / d_i, so
     // each job is solved at prices p unchanged, and its net value, usage and
     // certificate terms are scaled by d_i (the subproblem at prices d_i p).
@@ -378,12 +385,13 @@ __global__ void __launch_bounds__(256) k_dual_vec(
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const bool prev = pa.has_prev != 0;
+    const bool prev = (dpa ? dpa->has_prev : pa.has_prev) != 0;
     if (threadIdx.x < M) {
-        ptab[threadIdx.x] = pa.p[threadIdx.x];
-        qtab[threadIdx.x] = pa.q[threadIdx.x];
-        stab[threadIdx.x] = pa.s[threadIdx.x];
-        sctab[threadIdx.x] = pa.sc[threadIdx.x];
+        const int t = threadIdx.x;
+        ptab[t] = dpa ? dpa->p[t] : pa.p[t];
+        qtab[t] = dpa ? dpa->q[t] : pa.q[t];
+        stab[t] = dpa ? dpa->s[t] : pa.s[t];
+        sctab[t] = dpa ? dpa->sc[t] : pa.sc[t];
     }
     if (lane < M) hist[wv][lane] = 0.f;
     __syncthreads();
@@ -488,7 +496,8 @@ __global__ void __launch_bounds__(256) k_dual_vec(
             // made opaque once per tile: the prices are then read again for
             // every tile instead of being held in scalar registers across the
             // loop (4 M of them would not fit)
-            ArgPtr<M> pk = (ArgPtr<M>)__builtin_amdgcn_kernarg_segment_ptr();
+            ArgPtr<M> pk = dpa ? (ArgPtr<M>)dpa
+                               : (ArgPtr<M>)__builtin_amdgcn_kernarg_segment_ptr();
             asm volatile("" : "+s"(pk));
             Job<float> J;
             solve(ArgPrices<M, false>{pk, ptab}, J);
@@ -1068,20 +1077,15 @@ __global__ void __launch_bounds__(256) k_init_gen(const F* __restrict__ T,
 __global__ void __launch_bounds__(256) k_reduce_cols(const double* __restrict__ partial, int nb,
                                                      int ncols, double* __restrict__ out,
                                                      unsigned* __restrict__ ticket,
-                                                     unsigned* __restrict__ flag)
+                                                     unsigned* __restrict__ flag,
+                                                     const int* __restrict__ skip)
 {
+    if (skip && *skip) return;  // the device price loop has ended
     __shared__ double red[256];
     const int j = blockIdx.x;
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) s += partial[(int64_t)b * ncols + j];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
+    const double s = column_sum(partial, nb, ncols, j, red);
     if (threadIdx.x == 0) {
-        out[j] = red[0];
+        out[j] = s;
         if (flag) {
             __threadfence_system();
             if (atomicAdd(ticket, 1u) == (unsigned)gridDim.x - 1u) {
@@ -1292,22 +1296,45 @@ static PriceArgs<M> price_args(const PriceBlock<float>& h)
 
 template <int M>
 static void launch_vec(int grid, hipStream_t st, const float* T, const float2* prm, int64_t n,
-                       const PriceBlock<float>& h, float eps, double* partial, int* jp,
-                       float2* xp, float2* tp, int16_t* j1, const float* dem, const float* dv)
+                       const PriceBlock<float>* h, float eps, double* partial, int* jp,
+                       float2* xp, float2* tp, int16_t* j1, const float* dem, const float* dv,
+                       const void* dprices = nullptr, const int* skip = nullptr)
 {
-    const PriceArgs<M> a = price_args<M>(h);
+    // with device prices the argument block is not read
+    const PriceArgs<M> a = h ? price_args<M>(*h) : PriceArgs<M>{};
+    const auto* dpa = static_cast<const PriceArgs<M>*>(dprices);
     if (dv)
         k_dual_vec<M, false, true><<<grid, 256, 0, st>>>(a, T, prm, n, eps, partial, jp, xp, tp,
-                                                         j1, nullptr, dv);
+                                                         j1, nullptr, dv, dpa, skip);
     else if (dem)
         k_dual_vec<M, true, false><<<grid, 256, 0, st>>>(a, T, prm, n, eps, partial, jp, xp, tp,
-                                                         j1, dem, nullptr);
+                                                         j1, dem, nullptr, dpa, skip);
     else
         k_dual_vec<M, false, false><<<grid, 256, 0, st>>>(a, T, prm, n, eps, partial, jp, xp,
-                                                          tp, j1, nullptr, nullptr);
+                                                          tp, j1, nullptr, nullptr, dpa, skip);
 }
 
 bool dual_is_vec(int dtype, int m, bool vec_ok) { return dtype == 0 && vec_ok && vec_class(m); }
+
+hipError_t launch_dual_dev(int m, int grid, hipStream_t st, const void* T, const void* prm,
+                           int64_t n, double eps, double* partial, const void* dem,
+                           const void* dvec, const void* dprices, const int* skip)
+{
+    const float* Tf = static_cast<const float*>(T);
+    const float2* pr = static_cast<const float2*>(prm);
+    const float e = (float)eps;
+    const float* df = static_cast<const float*>(dem);
+    const float* dv = static_cast<const float*>(dvec);
+    switch (m) {
+    case 4: launch_vec<4>(grid, st, Tf, pr, n, nullptr, e, partial, nullptr, nullptr, nullptr, nullptr, df, dv, dprices, skip); break;
+    case 8: launch_vec<8>(grid, st, Tf, pr, n, nullptr, e, partial, nullptr, nullptr, nullptr, nullptr, df, dv, dprices, skip); break;
+    case 16: launch_vec<16>(grid, st, Tf, pr, n, nullptr, e, partial, nullptr, nullptr, nullptr, nullptr, df, dv, dprices, skip); break;
+    case 32: launch_vec<32>(grid, st, Tf, pr, n, nullptr, e, partial, nullptr, nullptr, nullptr, nullptr, df, dv, dprices, skip); break;
+    case 64: launch_vec<64>(grid, st, Tf, pr, n, nullptr, e, partial, nullptr, nullptr, nullptr, nullptr, df, dv, dprices, skip); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,
                        const void* prm, int64_t n, const void* prices, const void* host_prices,
@@ -1325,7 +1352,7 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
         const float* df = static_cast<const float*>(dem);
         const float* dv = static_cast<const float*>(dvec);
         if (dual_is_vec(dtype, m, vec_ok)) {
-            const auto& h = *static_cast<const PriceBlock<float>*>(host_prices);
+            const auto* h = static_cast<const PriceBlock<float>*>(host_prices);
             switch (m) {
             case 4: launch_vec<4>(grid, st, Tf, pr, n, h, e, partial, jp, xp, tp, j1, df, dv); break;
             case 8: launch_vec<8>(grid, st, Tf, pr, n, h, e, partial, jp, xp, tp, j1, df, dv); break;
@@ -1415,9 +1442,9 @@ hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem
 }
 
 hipError_t launch_reduce_cols(hipStream_t st, const double* partial, int nb, int ncols,
-                              double* out, unsigned* ticket, unsigned* flag)
+                              double* out, unsigned* ticket, unsigned* flag, const int* skip)
 {
-    k_reduce_cols<<<ncols, 256, 0, st>>>(partial, nb, ncols, out, ticket, flag);
+    k_reduce_cols<<<ncols, 256, 0, st>>>(partial, nb, ncols, out, ticket, flag, skip);
     return hipGetLastError();
 }
 

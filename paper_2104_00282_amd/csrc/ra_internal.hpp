@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "dev_loop.hpp"
 #include "resalloc.h"
 
 struct ra_ctx {
@@ -59,6 +60,14 @@ struct ra_problem {
     void* xpair_ws = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
+    // device price loop: its state, the prices it writes for the next pass,
+    // pinned status words, and the captured graph of a chunk of passes
+    ra::DevLoop* dloop = nullptr;
+    void* dprices = nullptr;
+    ra::DevStatus* h_dl = nullptr;
+    void* h_dlstage = nullptr;  // pinned: the header and first prices of a solve
+    hipGraphExec_t dl_gexec = nullptr;
+    hipGraph_t dl_graph = nullptr;
 };
 
 namespace ra {

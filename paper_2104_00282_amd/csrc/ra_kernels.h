@@ -100,7 +100,25 @@ hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
 // launches), the launch ends by setting *flag = 1 after every out[j] is
 // visible to the host.
 hipError_t launch_reduce_cols(hipStream_t st, const double* partial, int nb, int ncols,
-                              double* out, unsigned* ticket = nullptr, unsigned* flag = nullptr);
+                              double* out, unsigned* ticket = nullptr, unsigned* flag = nullptr,
+                              const int* skip = nullptr);
+
+// A vectorised dual pass (m in {4, 8, 16, 32, 64}) reading its prices from
+// device memory (dprices: a PriceArgs<m> written by the device price loop);
+// the pass returns at once when *skip is set.  No per-job outputs.
+hipError_t launch_dual_dev(int m, int grid, hipStream_t st, const void* T, const void* prm,
+                           int64_t n, double eps, double* partial, const void* dem,
+                           const void* dvec, const void* dprices, const int* skip);
+
+struct DevLoop;
+struct DevStatus;
+// The column sums of a dual pass (partial: nb rows of m + 3) into out, then
+// one step of the device price loop (loop.hip), which writes the next pass's
+// prices to pa (a PriceArgs<m>) and, when the loop ends, its outcome to hs
+// (host memory).  Returns at once when the loop has ended.  m in {4, 8, 16,
+// 32, 64}.
+hipError_t launch_reduce_step(int m, hipStream_t st, const double* partial, int nb, DevLoop* L,
+                              double* out, void* pa, DevStatus* hs);
 
 // Lower bound of the column-scaled allocation (§5): partial2 [grid][2] gets
 // sum_i u_i(t~_i) and sum_i u_i(t_i) - u_i(t~_i); r and R are device m-vectors.

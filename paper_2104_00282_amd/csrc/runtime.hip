@@ -22,6 +22,9 @@
 #include <chrono>
 #include <cstdlib>
 #include <map>
+#include <memory>
+#include <new>
+#include <cstddef>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -349,6 +352,12 @@ ra_status ra_problem_destroy(ra_problem* P)
     }
     if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->dl_gexec) (void)hipGraphExecDestroy(P->dl_gexec);
+    if (P->dl_graph) (void)hipGraphDestroy(P->dl_graph);
+    (void)hipFree(P->dloop);
+    (void)hipFree(P->dprices);
+    if (P->h_dl) (void)hipHostFree(P->h_dl);
+    if (P->h_dlstage) (void)hipHostFree(P->h_dlstage);
     (void)hipFree(P->prm);
     (void)hipFree(P->Rdev);
     (void)hipFree(P->partial);
@@ -509,6 +518,7 @@ void ra_solve_opts_default(ra_solve_opts* o)
     o->stall_evals = 0;
     o->init_step = 0.0;
     o->tol_abs = 0.0;
+    o->device_loop = 0;
 }
 
 static bool valid_opts(const ra_solve_opts& o)
@@ -516,8 +526,197 @@ static bool valid_opts(const ra_solve_opts& o)
     return o.tol_rel >= 0.0 && o.max_iter >= 0 && o.max_evals >= 0 && o.stall_evals >= 0 &&
            o.lbfgs_mem >= 1 && o.lbfgs_mem <= 64 && (o.method == 0 || o.method == 1) &&
            (o.init >= 0 && o.init <= 2) && o.init_step >= 0.0 && o.init_step <= 10.0 &&
-           o.tol_abs >= 0.0 && std::isfinite(o.tol_abs);
+           o.tol_abs >= 0.0 && std::isfinite(o.tol_abs) &&
+           (o.device_loop == 0 || o.device_loop == 1);
 }
+
+namespace {
+
+// Captured evaluation graphs hold the kernels' arguments; drop them when the
+// problem's inputs to those kernels change.
+void drop_graphs(ra_problem* P)
+{
+    // spare passes of a device-loop solve may still be queued
+    if (P->dl_gexec) (void)hipStreamSynchronize(P->ctx->stream);
+    if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->dl_gexec) (void)hipGraphExecDestroy(P->dl_gexec);
+    if (P->dl_graph) (void)hipGraphDestroy(P->dl_graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+    P->dl_gexec = nullptr;
+    P->dl_graph = nullptr;
+}
+
+// Passes per replay of the device loop's graph: one host synchronisation
+// per this many passes (later passes of a chunk return at once once the loop
+// has ended).
+constexpr int DL_CHUNK = 6;
+
+bool device_loop_applies(const ra_problem* P, const ra_solve_opts& o)
+{
+    const ra_ctx* ctx = P->ctx;
+    return o.device_loop && ra::dual_is_vec(P->dt, P->m, dual_vec(P)) &&
+           P->m <= ra::DL_MAX_M && o.lbfgs_mem <= ra::DL_MAX_MEM && !ctx->timing &&
+           !o.verbose && ctx->stream != nullptr;
+}
+
+// The price block of a vectorised pass at prices p (no previous point), in
+// the layout of PriceArgs<m>: p, 1/p, q, 1/q, s, 1 - s (m floats each), then
+// has_prev.
+std::vector<float> first_price_args(int m, const std::vector<double>& p, std::vector<double>& pe,
+                                    const std::vector<double>& R, double& pR)
+{
+    std::vector<float> a(6 * (size_t)m + 1, 0.f);
+    pR = 0.0;
+    pe.resize(m);
+    for (int j = 0; j < m; ++j) {
+        const float pf = (float)std::max(p[j], 0.0);
+        a[j] = pf;
+        a[m + j] = pf > 0.f ? 1.0f / pf : INFINITY;
+        a[2 * m + j] = 0.f;
+        a[3 * m + j] = INFINITY;
+        a[4 * m + j] = 1.f;
+        a[5 * m + j] = 0.f;
+        pe[j] = (double)pf;
+        pR += (double)pf * R[j];
+    }
+    return a;  // the last word (has_prev) stays 0
+}
+
+ra_status capture_dev_loop(ra_problem* P)
+{
+    ra_ctx* ctx = P->ctx;
+    if (P->dl_gexec) return RA_OK;
+    hipStream_t st = ctx->stream;
+    const int* skip = &P->dloop->done;
+    RA_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < DL_CHUNK && e == hipSuccess; ++k) {
+        e = ra::launch_dual_dev(P->m, P->grid, st, P->T, P->prm, P->n, P->eps, P->partial, P->dem,
+                                P->dvec, P->dprices, skip);
+        if (e == hipSuccess)
+            e = ra::launch_reduce_step(P->m, st, P->partial, P->grid, P->dloop, P->dout,
+                                       P->dprices, P->h_dl);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(st, &g);
+    if (e == hipSuccess) e = ee;
+    if (e == hipSuccess) e = hipGraphInstantiate(&P->dl_gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        P->dl_gexec = nullptr;
+        return fail(ctx, RA_EDEVICE, "device loop graph: %s", hipGetErrorString(e));
+    }
+    P->dl_graph = g;
+    return RA_OK;
+}
+
+// Algorithm 2 with the price update on the device: the host writes the
+// loop's configuration and first prices, then replays a graph of DL_CHUNK
+// passes [dual kernel -> column sums and step], keeping one replay queued
+// ahead of the device, until the step that ends the loop publishes the
+// outcome in pinned memory.  Spare passes of the last replays return at once;
+// they may still be queued on the stream when this returns.
+ra_status solve_device(ra_problem* P, const ra_solve_opts& o, const std::vector<double>& p0,
+                       double* p_inout, ra_solve_info* info,
+                       std::chrono::steady_clock::time_point t0)
+{
+    ra_ctx* ctx = P->ctx;
+    hipStream_t st = ctx->stream;
+    const int m = P->m;
+    if (!P->dloop) {
+        RA_HIP(ctx, hipMalloc((void**)&P->dloop, sizeof(ra::DevLoop)));
+        // the reduction's ticket starts at zero
+        RA_HIP(ctx, hipMemsetAsync(P->dloop, 0, sizeof(ra::DevLoop), st));
+    }
+    if (!P->dprices) RA_HIP(ctx, hipMalloc(&P->dprices, sizeof(float) * (6 * ra::DL_MAX_M + 1)));
+    if (!P->h_dl)
+        RA_HIP(ctx, hipHostMalloc((void**)&P->h_dl, sizeof(ra::DevStatus), hipHostMallocCoherent));
+    // the header, then the first pass's price block
+    constexpr size_t hbytes = offsetof(ra::DevLoop, res_p);
+    if (!P->h_dlstage)
+        RA_HIP(ctx, hipHostMalloc(&P->h_dlstage, sizeof(ra::DevLoop) + 4096, hipHostMallocDefault));
+    // the previous solve's copies from this buffer ended before its passes
+    ra::DevLoop* h = new (P->h_dlstage) ra::DevLoop();
+    h->m = m;
+    h->mem = o.lbfgs_mem;
+    h->method = o.method;
+    h->max_iter = o.max_iter;
+    h->max_evals = o.max_evals;
+    h->stall_evals = o.stall_evals;
+    h->n = (double)P->n;
+    h->tol_rel = o.tol_rel;
+    h->tol_abs = o.tol_abs;
+    h->init_step = o.init_step;
+    for (int j = 0; j < m; ++j) h->R[j] = P->R[j];
+    std::vector<double> pe;
+    double pR = 0.0;
+    const std::vector<float> a = first_price_args(m, p0, pe, P->R, pR);
+    for (int j = 0; j < m; ++j) h->pe[j] = pe[j];
+    h->pR = pR;
+    h->lam = 1.0;
+    // earlier replays may still be queued: the new header is written in
+    // stream order after them, and none of them writes the status record
+    ra::DevStatus* hs = P->h_dl;
+    __atomic_store_n(&hs->passes, 0, __ATOMIC_RELAXED);
+    __atomic_store_n(&hs->done, 0, __ATOMIC_RELEASE);
+    char* pb = static_cast<char*>(P->h_dlstage) + sizeof(ra::DevLoop);
+    std::memcpy(pb, a.data(), sizeof(float) * a.size());
+    RA_HIP(ctx, hipMemcpyAsync(P->dloop, h, hbytes, hipMemcpyHostToDevice, st));
+    RA_HIP(ctx, hipMemcpyAsync(P->dprices, pb, sizeof(float) * a.size(), hipMemcpyHostToDevice,
+                               st));
+    ra_status cs = capture_dev_loop(P);
+    if (cs != RA_OK) return cs;
+    // the number of passes cannot exceed the budget, or 21 per iteration
+    // (20 halvings and a subgradient step) plus the final certification
+    const int64_t bound = o.max_evals > 0 ? (int64_t)o.max_evals : (int64_t)(o.max_iter + 2) * 21;
+    const int64_t max_chunks = bound / DL_CHUNK + 2;
+    int64_t launched = 0;
+    for (uint64_t k = 0;; ++k) {
+        const int done = __atomic_load_n(&hs->done, __ATOMIC_ACQUIRE);
+        if (done) break;
+        const int64_t passes = __atomic_load_n(&hs->passes, __ATOMIC_RELAXED);
+        // keep one replay queued behind the one the device is running
+        if (launched < max_chunks && passes >= (launched - 1) * DL_CHUNK) {
+            RA_HIP(ctx, hipGraphLaunch(P->dl_gexec, st));
+            ++launched;
+            continue;
+        }
+        if ((k & 4095) == 0) {
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(&hs->done, __ATOMIC_ACQUIRE)) break;
+                if (launched >= max_chunks)
+                    return fail(ctx, RA_EDEVICE,
+                                "the device price loop did not end within its budget");
+                continue;
+            }
+            if (e != hipErrorNotReady)
+                return fail(ctx, RA_EDEVICE, "device price loop failed: %s", hipGetErrorString(e));
+        }
+        __builtin_ia32_pause();
+    }
+    if (hs->done == 2) return fail(ctx, RA_ENUMERIC, "non-finite dual value, usage or gap");
+    const bool conv = hs->converged != 0;
+    for (int j = 0; j < m; ++j) p_inout[j] = hs->p[j];
+    if (info) {
+        info->iters = hs->iters;
+        info->dual_evals = hs->evals;
+        info->fell_back = hs->fallbacks;
+        info->converged = conv ? 1 : 0;
+        info->g = hs->g;
+        info->U_lb = hs->certified ? hs->U : NAN;
+        info->rel_gap = hs->certified ? hs->rel : INFINITY;
+        info->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->restarted = 0;
+        info->warm_evals = 0;
+    }
+    return conv ? RA_OK : RA_ENOTCONV;
+}
+
+}  // namespace
 
 ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opts,
                    double* p_inout, ra_solve_info* info)
@@ -547,6 +746,8 @@ ra_status ra_solve(ra_ctx* ctx, const ra_problem* prob, const ra_solve_opts* opt
         ra_status st = init_prices(P, p.data());
         if (st != RA_OK) return st;
     }
+
+    if (device_loop_applies(P, o)) return solve_device(P, o, p, p_inout, info, t0);
 
     ra::PriceLoop L(m, P->n, P->R.data(), o, p.data());
     std::vector<double> pe, rr;
@@ -595,14 +796,7 @@ ra_status ra_problem_set_demands(ra_ctx* ctx, ra_problem* P, const void* d)
     hipStream_t st = ctx->stream;
     const size_t bytes = (size_t)P->n * elt(P->dt);
     // captured graphs hold the previous demand pointer
-    if (P->gexec) {
-        (void)hipGraphExecDestroy(P->gexec);
-        P->gexec = nullptr;
-    }
-    if (P->graph) {
-        (void)hipGraphDestroy(P->graph);
-        P->graph = nullptr;
-    }
+    drop_graphs(P);
     if (d && P->dvec)
         return fail(ctx, RA_EINVAL, "the problem has demand vectors; remove them first");
     if (!d) {
@@ -662,14 +856,7 @@ ra_status ra_problem_set_demand_vectors(ra_ctx* ctx, ra_problem* P, const void* 
         if (bad) return fail(ctx, RA_EINVAL, "demand vectors must be positive and finite");
     }
     // captured graphs hold the previous kernel and its arguments
-    if (P->gexec) {
-        (void)hipGraphExecDestroy(P->gexec);
-        P->gexec = nullptr;
-    }
-    if (P->graph) {
-        (void)hipGraphDestroy(P->graph);
-        P->graph = nullptr;
-    }
+    drop_graphs(P);
     P->dvec = D;
     const int g = ra::dual_grid(ctx->cus, P->m, P->dt, P->n, dual_vec(P), D != nullptr);
     if (g > P->grid_cap) {
