@@ -170,7 +170,8 @@ typedef struct {
                                 another order, so iterates agree to rounding.
                                 Spare passes of the last replay (no-ops) may
                                 still be queued on the context's stream when the
-                                call returns.  ra_batch_solve ignores it.  0 or 1 */
+                                call returns.  ra_batch_solve and
+                                ra_solve_learned ignore it.  0 or 1              */
 } ra_solve_opts;
 
 /* Outcome of a solve. */

@@ -171,7 +171,7 @@ struct Step {
             L->npairs = 0;
             dj = (pj <= 0.0 && gj > 0.0) ? 0.0 : -gj;
         }
-        if (on) L->d[j] = on ? dj : 0.0;
+        if (on) L->d[j] = dj;
         const double dn = wmax(on ? fabs(dj) : 0.0);
         if (dn == 0.0) {
             go_final();

@@ -679,7 +679,13 @@ ra_status solve_device(ra_problem* P, const ra_solve_opts& o, const std::vector<
         const int64_t passes = __atomic_load_n(&hs->passes, __ATOMIC_RELAXED);
         // keep one replay queued behind the one the device is running
         if (launched < max_chunks && passes >= (launched - 1) * DL_CHUNK) {
-            RA_HIP(ctx, hipGraphLaunch(P->dl_gexec, st));
+            const hipError_t e = hipGraphLaunch(P->dl_gexec, st);
+            if (e != hipSuccess) {
+                // no earlier replay may outlive this call: a later solve
+                // resets the status record they write
+                (void)hipStreamSynchronize(st);
+                return fail(ctx, RA_EDEVICE, "device loop launch: %s", hipGetErrorString(e));
+            }
             ++launched;
             continue;
         }
