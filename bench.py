@@ -223,8 +223,10 @@ def bench_warmstart(args):
                         "decayed 10x), evaluated on %d fresh instances (n = %d, m = 16)"
                         % (args.train_count, args.train_n, args.epochs, args.batch, args.lr,
                            args.eval_count, args.eval_n),
-            "targets": "relative gaps 1e-3, 1e-4 and max(1e-6, 1.5 x floor), floor from a "
-                       "reference run",
+            "targets": "relative gaps 1e-3, 1e-4, max(1e-6, 1.5 x floor) with the floor from a "
+                       "long reference run from p = 1, and the same with the smallest floor of "
+                       "three reference runs (from p = 1, the paper's start and the network's "
+                       "prediction; level floor_any)",
             "fallback": "cold restart when the certified gap has not fallen below the first "
                         "certificate within 5 certificates",
         },

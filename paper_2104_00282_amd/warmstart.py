@@ -99,7 +99,7 @@ def constant_network(ctx, net_like, Y_train):
     return const
 
 
-LEVELS = (1e-3, 1e-4, "floor")
+LEVELS = (1e-3, 1e-4, "floor", "floor_any")
 
 
 def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters=300,
@@ -107,9 +107,12 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
     """Cold start (p = 1), the paper's data-dependent start and the learned
     warm start (and optionally a constant predictor) on fresh instances, to each
     relative-gap level of `levels` separately ("floor" = max(1e-6, 1.5 x the
-    smallest gap a long reference run certifies), the tightest target the
-    column-scaling recovery allows). Returns a list of per-instance dicts
-    {"floor_gap": g, level: {arm: info, "target": tol}}."""
+    smallest gap a long reference run from p = 1 certifies, the tightest
+    target the column-scaling recovery allows on that path; "floor_any" the
+    same with the smallest gap of three long reference runs, from p = 1, from
+    the paper's start and from the network's prediction, so that no start's
+    own path defines the target). Returns a list of per-instance dicts
+    {"floor_gap": g, "floor_any_gap": g, level: {arm: info, "target": tol}}."""
     import synth
 
     rows = []
@@ -121,11 +124,26 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
             probs.append(Problem(ctx, T, w, c, kind, R, 1e-3, validate=False))
         _, ref, _ = batch_solve(probs, tol_rel=0.0, max_iter=floor_iters,
                                 stall_evals=stall_evals)
-        for pr, rf in zip(probs, ref):
+        refs = [ref]
+        if "floor_any" in levels:
+            _, rp, _ = batch_solve(probs, tol_rel=0.0, max_iter=floor_iters,
+                                   stall_evals=stall_evals, paper_init=True)
+            # the learned solve's empty-memory step is 2 % of max p
+            preds = [pr.predict_prices(net) for pr in probs]
+            _, rw, _ = batch_solve(probs, p0=preds, tol_rel=0.0, max_iter=floor_iters,
+                                   stall_evals=stall_evals, init_step=0.02)
+            refs += [rp, rw]
+        for k, (pr, rf) in enumerate(zip(probs, ref)):
             pr.solve(max_iter=0)  # capture the evaluation graph outside the timings
-            row = {"floor_gap": rf["rel_gap"]}
+            any_gap = min(r[k]["rel_gap"] for r in refs)
+            row = {"floor_gap": rf["rel_gap"], "floor_any_gap": any_gap}
             for lv in levels:
-                tol = max(1e-6, 1.5 * rf["rel_gap"]) if lv == "floor" else float(lv)
+                if lv == "floor":
+                    tol = max(1e-6, 1.5 * rf["rel_gap"])
+                elif lv == "floor_any":
+                    tol = max(1e-6, 1.5 * any_gap)
+                else:
+                    tol = float(lv)
                 arms = {}
                 arms["cold"] = pr.solve(tol_rel=tol, max_iter=max_iter, stall_evals=stall_evals)[1]
                 arms["warm"] = pr.solve_learned(net, tol_rel=tol, max_iter=max_iter,
@@ -150,6 +168,8 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
 def summarize(rows, levels=LEVELS):
     out = {"instances": len(rows),
            "floor_median": float(np.median([r["floor_gap"] for r in rows]))}
+    if "floor_any_gap" in rows[0]:
+        out["floor_any_median"] = float(np.median([r["floor_any_gap"] for r in rows]))
     for lv in levels:
         key = str(lv)
 
@@ -176,7 +196,7 @@ def summarize(rows, levels=LEVELS):
         if "const" in lvl:
             lvl["const_speedup_total"] = (lvl["cold"]["seconds_total"] /
                                           lvl["const"]["seconds_total"])
-        if lv == "floor":
+        if lv in ("floor", "floor_any"):
             lvl["targets_at_1e-6"] = int(sum(r[key]["target"] <= 1e-6 for r in rows))
         out[key] = lvl
     return out

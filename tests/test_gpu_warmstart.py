@@ -25,10 +25,15 @@ def test_trained_network_gains_over_cold_start():
     X, Y, gaps = ws.solved_set(ctx, 400, 20000, m, seed0=synth.BASE_SEED + 300000, group=200)
     net, info = ws.train(ctx, X, Y, hidden=64, epochs=60, batch=64, lr=2e-3)
     assert info["val_loss"] < 0.5 * info["const_val_loss"]
+    levels = (1e-3, 1e-4, "floor_any")
     rows = ws.evaluate(ctx, net, 16, 50000, m, seed0=synth.BASE_SEED + 400000, group=16,
-                       levels=(1e-3, 1e-4))
-    s = ws.summarize(rows, levels=(1e-3, 1e-4))
+                       levels=levels)
+    s = ws.summarize(rows, levels=levels)
     print(s)
+    # the start-independent floor is the smallest of three reference runs, the
+    # p = 1 run among them
+    assert all(r["floor_any_gap"] <= r["floor_gap"] for r in rows)
+    assert all(r["floor_any"]["target"] == max(1e-6, 1.5 * r["floor_any_gap"]) for r in rows)
     lv = s["0.001"]
     assert lv["warm"]["evals_median"] < lv["cold"]["evals_median"]
     assert lv["warm"]["reached"] >= lv["cold"]["reached"] - 1
