@@ -47,6 +47,9 @@ __device__ __forceinline__ float dlog(float x)
     return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
 }
 __device__ __forceinline__ double dlog(double x) { return log(x); }
+// 1/x: FP32 with the hardware reciprocal (about 1 ulp), FP64 exactly rounded.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 // x^y for x >= 0 and y != 0 (every use here: a base t + eps or w / alpha,
 // an exponent 1 - a or 1 / a), as 2^(y log2 x) with the hardware's base-2
 // logarithm and exponential: relative error about (|y log2 x| + 1) 2^-23,
@@ -56,7 +59,16 @@ __device__ __forceinline__ float dpow(float x, float y)
     return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
 }
 __device__ __forceinline__ double dpow(double x, double y) { return pow(x, y); }
-__device__ __forceinline__ float dexpm1(float x) { return expm1f(x); }
+// e^x - 1, FP32: a degree-5 Taylor polynomial for |x| < 1/32 (truncation
+// below 2e-10 relative), else the hardware base-2 exponential minus one
+// (relative error below 1e-5 where |e^x - 1| >= 0.03).  FP64: the library.
+__device__ __forceinline__ float dexpm1(float x)
+{
+    const float poly =
+        x * (1.f + x * (0.5f + x * (1.f / 6.f + x * (1.f / 24.f + x * (1.f / 120.f)))));
+    const float big = __builtin_amdgcn_exp2f(x * 1.44269504088896341f) - 1.f;
+    return fabsf(x) < 0.03125f ? poly : big;
+}
 __device__ __forceinline__ double dexpm1(double x) { return expm1(x); }
 
 // Packed utility code c of a job (second field of prm), told apart by its
@@ -78,7 +90,7 @@ __device__ __forceinline__ F utility(bool caplin, F w, F c, F eps, F t)
     if (caplin) return w * (t < c ? t : c);
     if (!AF || c == F(-1)) return w * dlog(t + eps);
     const F e = F(1) - afair_exponent(c);
-    return w * dpow(t + eps, e) / e;
+    return w * dpow(t + eps, e) * frcp(e);
 }
 
 __device__ __forceinline__ void wave_sync()
@@ -95,10 +107,6 @@ struct Job {
     F tlo, thi;        // a_jlo x_lo and a_jhi x_hi
     F v;               // net utility u(t) - p^T x
 };
-
-// 1/x: FP32 with the hardware reciprocal (about 1 ulp), FP64 exactly rounded.
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 
 // The prices one job pays per unit of each resource.  SharedPrices: the price
 // vector p, alike for every job; P and IP (= 1/p) are read with wave-uniform
@@ -275,7 +283,19 @@ __device__ __forceinline__ void solve_job(const Row& a, int mm, const Px& px, F 
     J.tlo = (left | right) ? F(0) : alo * xl;
 }
 
-__device__ __forceinline__ float dlog1p(float x) { return log1pf(x); }
+// log(1 + x) for x >= 0, FP32: a degree-5 Taylor polynomial below 1/32
+// (truncation below 1e-8 relative), else the hardware logarithm of u = 1 + x
+// with the rounding of u undone by the factor x / (u - 1) (u - 1 is exact);
+// relative error a few 1e-7.  The device library's log1pf costs about ten
+// times as many instructions.  FP64: the library.
+__device__ __forceinline__ float dlog1p(float x)
+{
+    const float poly =
+        x * (1.f + x * (-0.5f + x * (1.f / 3.f + x * (-0.25f + x * 0.2f))));
+    const float u = 1.f + x;
+    const float big = dlog(u) * (x * frcp(u - 1.f));
+    return x < 0.03125f ? poly : big;
+}
 __device__ __forceinline__ double dlog1p(double x) { return log1p(x); }
 
 // Lower-bound contribution of one job (§5): its allocation on (lo, hi) with
@@ -293,11 +313,11 @@ __device__ __forceinline__ void scaled_utility(bool caplin, F w, F c, F eps, int
     const F dt = (jlo >= 0 ? SC[jlo] * tlo : F(0)) + (jhi >= 0 ? SC[jhi] * thi : F(0));
     U = utility<F, AF>(caplin, w, c, eps, tt);
     if (!caplin && (!AF || c == F(-1))) {
-        du = w * dlog1p(dt / (tt + eps));
+        du = w * dlog1p(dt * frcp(tt + eps));
     } else if (!caplin) {
         // u(t) - u(t~) = U ((1 + dt / (t~ + eps))^(1 - a) - 1)
         const F e = F(1) - afair_exponent(c);
-        du = U * dexpm1(e * dlog1p(dt / (tt + eps)));
+        du = U * dexpm1(e * dlog1p(dt * frcp(tt + eps)));
     } else {
         const F t = tlo + thi;
         du = (tt >= c) ? F(0) : (t <= c ? w * dt : w * (c - tt));

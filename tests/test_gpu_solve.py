@@ -170,3 +170,29 @@ def test_alpha_fair_solve_certificate(ctx, torch):
     assert abs(info["U_lb"] - U) <= 1e-5 * scale
     assert U <= g
     prob.close()
+
+
+@pytest.mark.parametrize("m,log_frac,r_scale,alpha", [(4, 1.0, 0.05, False), (16, 0.5, 0.1, False),
+                                                      (64, 0.7, 0.2, False), (16, 0.5, 0.1, True),
+                                                      (8, 0.0, 0.05, True)])
+def test_gap_of_first_point_matches_oracle(ctx, torch, m, log_frac, r_scale, alpha):
+    """The certificate of the start p = 1 (a budget of two passes: the second
+    certifies the first) against the oracle's g - U(X~) there, relative to
+    the gap itself: the utility lost by scaling is summed per job with the
+    kernel's own log1p and expm1, so an error in them shows here first."""
+    print("first-point gap m=%d alpha=%s" % (m, alpha), flush=True)
+    I = synth.random_small(30000, m, seed=700 + m, dtype=np.float32, log_frac=log_frac,
+                           r_scale=r_scale)
+    if alpha:
+        rng = np.random.default_rng(800 + m)
+        sel = rng.random(I.n) < 0.5
+        I.kind = np.where(sel, 2, I.kind).astype(np.uint8)
+        I.c = np.where(sel, rng.choice([0.0, 0.3, 0.5, 2.0, 3.0], I.n), I.c).astype(np.float32)
+    prob = _problem(ctx, torch, I)
+    p, info, _ = prob.solve(p0=np.ones(m), tol_rel=0.0, max_iter=50, max_evals=2)
+    assert np.array_equal(p, np.ones(m))
+    g, U = _certificate(I, p)
+    gap, gap_gpu = g - U, info["g"] - info["U_lb"]
+    assert gap > 1e-3 * abs(g)  # columns overused at p = 1: scaling loses utility
+    assert info["g"] == pytest.approx(g, rel=1e-5)
+    assert abs(gap_gpu - gap) <= 1e-4 * gap + 1e-7 * abs(g)
