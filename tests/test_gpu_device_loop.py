@@ -179,3 +179,18 @@ def test_other_problems_run_the_host_loop(ctx, torch):
         pb, ib, _ = prob.solve(tol_rel=1e-6, max_iter=60, lbfgs_mem=mem, device_loop=True)
         assert np.array_equal(pa, pb)
         assert ia["g"] == ib["g"] and ia["dual_evals"] == ib["dual_evals"]
+
+
+@pytest.mark.parametrize("mem", [1, 3, 32])
+def test_memory_sizes_match_host(ctx, torch, mem):
+    """The L-BFGS ring buffer at its smallest, an odd and its largest size
+    on the device: the same passes and iterates as the host loop."""
+    I = synth.random_small(20000, 32, seed=515 + mem, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    kw = dict(tol_rel=1e-9, max_iter=300, max_evals=40, lbfgs_mem=mem)
+    ph, ih, _ = prob.solve(**kw)
+    pd, idv, _ = prob.solve(device_loop=True, **kw)
+    assert idv["dual_evals"] == ih["dual_evals"]
+    assert idv["iters"] == ih["iters"] and idv["fell_back"] == ih["fell_back"]
+    assert np.allclose(pd, ph, rtol=1e-5, atol=0)
+    assert idv["rel_gap"] == pytest.approx(ih["rel_gap"], rel=1e-3)
