@@ -55,7 +55,7 @@ typedef enum {
     RA_EDEVICE = 3,      /* a HIP runtime call or kernel launch failed          */
     RA_ENUMERIC = 4,     /* non-finite dual value or gradient                   */
     RA_ENOTCONV = 5,     /* solver stopped at max_iter above the tolerance      */
-    RA_EUNSUPPORTED = 6  /* valid request this build does not implement        */
+    RA_EUNSUPPORTED = 6  /* valid request the library does not implement       */
 } ra_status;
 
 typedef enum { RA_F32 = 0, RA_F64 = 1 } ra_dtype;
