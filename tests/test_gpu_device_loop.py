@@ -194,3 +194,21 @@ def test_memory_sizes_match_host(ctx, torch, mem):
     assert idv["iters"] == ih["iters"] and idv["fell_back"] == ih["fell_back"]
     assert np.allclose(pd, ph, rtol=1e-5, atol=0)
     assert idv["rel_gap"] == pytest.approx(ih["rel_gap"], rel=1e-3)
+
+
+def test_kernel_timing_keeps_the_host_loop(ctx, torch):
+    """With per-kernel timing on, every pass is timed on the host side, so
+    device_loop = 1 runs the host loop: the same result, and every pass of
+    the solve shows up in the timing counters."""
+    import paper_2104_00282_amd as ra
+    I = synth.random_small(20000, 16, seed=520, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    pa, ia, _ = prob.solve(tol_rel=1e-5, max_iter=50)
+    ra.ra_set_kernel_timing(ctx.handle, True)
+    try:
+        pb, ib, _ = prob.solve(tol_rel=1e-5, max_iter=50, device_loop=True)
+        _, launches = ra.ra_get_kernel_timing(ctx.handle)
+    finally:
+        ra.ra_set_kernel_timing(ctx.handle, False)
+    assert np.array_equal(pa, pb) and ia["dual_evals"] == ib["dual_evals"]
+    assert launches >= ib["dual_evals"]
