@@ -44,7 +44,8 @@ class PriceLoop {
 public:
     PriceLoop(int m, int64_t n, const double* R, const ra_solve_opts& o, const double* p0)
         : m_(m), n_(n), R_(R, R + m), o_(o), next_(p0, p0 + m), S_(o.lbfgs_mem, std::vector<double>(m)),
-          Y_(o.lbfgs_mem, std::vector<double>(m)), rho_(o.lbfgs_mem), alpha_(o.lbfgs_mem), d_(m)
+          Y_(o.lbfgs_mem, std::vector<double>(m)), rho_(o.lbfgs_mem), alpha_(o.lbfgs_mem), d_(m),
+          step_(m), y_(m), q_(m)
     {
         for (double& v : next_) v = std::max(v, 0.0);
     }
@@ -75,13 +76,19 @@ public:
                 return;
             }
         }
-        Point e;
-        e.p = p_eval;
+        // the evaluated point, built in a member so that its vectors keep
+        // their storage from one pass to the next (no allocation per pass)
+        Point& e = eval_;
+        e.p.assign(p_eval.begin(), p_eval.end());
         e.g = g;
         e.f = g / (double)n_;
         e.r.assign(r, r + m_);
         e.grad.resize(m_);
         for (int j = 0; j < m_; ++j) e.grad[j] = (R_[j] - r[j]) / (double)n_;
+        e.U = 0.0;
+        e.gap = 0.0;
+        e.rel = INFINITY;
+        e.certified = false;
         ++evals_;
         const State was = state_;
         pend_ = e;
@@ -92,10 +99,10 @@ public:
             start_iteration();
             break;
         case LINE_SEARCH: {
-            std::vector<double> step(m_);
+            std::vector<double>& step = step_;
             for (int j = 0; j < m_; ++j) step[j] = e.p[j] - cur_.p[j];
             if (e.f <= cur_.f + 1e-4 * dot(cur_.grad, step)) {
-                std::vector<double> y(m_);
+                std::vector<double>& y = y_;
                 for (int j = 0; j < m_; ++j) y[j] = e.grad[j] - cur_.grad[j];
                 const double sy = dot(step, y);
                 if (sy > 1e-12 * std::sqrt(dot(step, step) * dot(y, y))) {
@@ -201,7 +208,8 @@ private:
             return;
         }
         const int M = (int)S_.size();
-        std::vector<double> q = cur_.grad;
+        std::vector<double>& q = q_;
+        q = cur_.grad;
         for (int h = 0; h < npairs_; ++h) {
             const int s = (head_ - 1 - h + M) % M;
             alpha_[h] = rho_[s] * dot(S_[s], q);
@@ -274,6 +282,10 @@ private:
     bool have_pend_ = false;
     std::vector<std::vector<double>> S_, Y_;
     std::vector<double> rho_, alpha_, d_;
+    // scratch reused by every pass: the evaluated point, the step and
+    // gradient change of a line-search trial, the two-loop vector
+    Point eval_;
+    std::vector<double> step_, y_, q_;
     int npairs_ = 0, head_ = 0, ls_ = 0;
     double lam_ = 1.0;
     int evals_ = 0, iters_ = 0, fallbacks_ = 0, sg_steps_ = 0;

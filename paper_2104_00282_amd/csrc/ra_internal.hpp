@@ -7,10 +7,12 @@
 #include <cstdarg>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "dev_loop.hpp"
+#include "host_pool.hpp"
 #include "resalloc.h"
 
 struct ra_ctx {
@@ -27,6 +29,7 @@ struct ra_ctx {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     std::map<std::string, int> batch_tuned;  // batch shape -> blocks per CU
+    std::unique_ptr<ra::HostPool> pool;      // host threads of the batched solver
 };
 
 struct ra_problem {

@@ -1129,16 +1129,28 @@ ra_status batch_alloc(ra_ctx* ctx, BatchWs& ws, int B, int Wmax)
 // Fill the tables of one round for the active problems `act` (ascending) with
 // W waves: items, prices (next point and, if any, the point to certify),
 // byte-balanced per-wave tile chunks, partial slots.  Returns the tile count.
+// Spread per-problem work over the context's host threads when there is
+// enough of it; fn(lo, hi) handles problems [lo, hi).
+void for_problems(ra::HostPool* pool, int A, const std::function<void(int, int)>& fn)
+{
+    if (pool && A >= 64)
+        pool->run(A, fn);
+    else
+        fn(0, A);
+}
+
 int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
                    const std::vector<ra::PriceLoop>& loops, const std::vector<int>& act, int W,
-                   std::vector<std::vector<double>>& p_eval)
+                   std::vector<std::vector<double>>& p_eval, ra::HostPool* pool)
 {
     const int A = (int)act.size();
     ra::BatchItem* it = ws.items();
     float* pr = ws.prices();
     std::vector<int64_t> tiles(A), cost(A);
     int64_t tt = 0, C = 0;
-    for (int a = 0; a < A; ++a) {
+    // each problem's record and price rows (independent per problem)
+    for_problems(pool, A, [&](int lo, int hi) {
+    for (int a = lo; a < hi; ++a) {
         const ra_problem* P = probs[act[a]];
         const ra::PriceLoop& L = loops[act[a]];
         const int tr = ra::batch_rows(P->m);
@@ -1148,7 +1160,6 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
         it[a].prm = static_cast<const float2*>(P->prm);
         it[a].n = P->n;
         it[a].m = P->m;
-        it[a].tile0 = (int)tt;
         it[a].eps = (float)P->eps;
         const ra::Point* prev = L.pending();
         it[a].has_prev = prev ? 1 : 0;
@@ -1171,6 +1182,11 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
                     over ? (float)((prev->r[j] - P->R[j]) / prev->r[j]) : 0.0f;
             }
         }
+    }
+    });
+    // tile offsets in problem order
+    for (int a = 0; a < A; ++a) {
+        it[a].tile0 = (int)tt;
         tt += tiles[a];
         C += tiles[a] * cost[a];
     }
@@ -1378,6 +1394,22 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     }
     const bool graph = o.use_graph && ctx->stream != nullptr;
 
+    // host threads for the per-problem work between rounds (created once per
+    // context, for batches large enough to use them)
+    if (B >= 64 && !ctx->pool) {
+        const int hw = (int)std::thread::hardware_concurrency();
+        const int workers = std::min(hw, 16) - 1;
+        if (workers >= 1) {
+            try {
+                ctx->pool.reset(new ra::HostPool(workers));
+            } catch (...) {  // no threads: the work stays on this thread
+                ctx->pool.reset();
+            }
+        }
+    }
+    ra::HostPool* pool = ctx->pool.get();
+    std::vector<char> bad;
+
     // grid: tuned per batch shape (timing one round per candidate)
     if (ctx->batch_tuned.empty()) tune_cache_load(ctx);
     const std::string sig = batch_signature(P);
@@ -1387,7 +1419,6 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
 
     std::vector<int> act;
     std::vector<std::vector<double>> p_eval(B);
-    std::vector<double> r(ra::BATCH_MAX_M);
     if (bpc == 0) {
         act.resize(B);
         for (int b = 0; b < B; ++b) act[b] = b;
@@ -1397,7 +1428,7 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
         float best_ms = INFINITY;
         for (int c = 1; c <= occ; ++c) {
             const int grid = ctx->cus * c;
-            batch_fill(ws, P, loops, act, grid * 4, p_eval);
+            batch_fill(ws, P, loops, act, grid * 4, p_eval, pool);
             for (int rep = 0; rep < 2; ++rep) {  // first run warms up
                 RA_HIP(ctx, hipEventRecord(e0, ctx->stream));
                 ra_status s = batch_enqueue(ctx, ws, grid);
@@ -1424,20 +1455,33 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
         for (int b = 0; b < B; ++b)
             if (!loops[b].done()) act.push_back(b);
         if (act.empty()) break;
-        batch_fill(ws, P, loops, act, grid * 4, p_eval);
+        batch_fill(ws, P, loops, act, grid * 4, p_eval, pool);
         ra_status s = batch_run(ctx, ws, grid, graph);
         if (s != RA_OK) return s;
-        for (size_t a = 0; a < act.size(); ++a) {
-            const int b = act[a];
-            const ra_problem* Pb = P[b];
-            const double* row = ws.hout + a * ra::BATCH_COLS;
-            double pR = 0.0;
-            for (int j = 0; j < Pb->m; ++j) pR += p_eval[a][j] * Pb->R[j];
-            const double gv = pR + row[ra::BATCH_MAX_M];
-            if (!std::isfinite(gv)) return fail(ctx, RA_ENUMERIC, "problem %d: non-finite dual value", b);
-            for (int j = 0; j < Pb->m; ++j) r[j] = row[j];
-            loops[b].feed(p_eval[a], gv, r.data(), row[ra::BATCH_MAX_M + 2]);
-        }
+        // every active problem's price loop takes its step (independent per
+        // problem); a non-finite dual value is reported for the first such
+        // problem after all have been visited
+        const int A = (int)act.size();
+        bad.assign(A, 0);
+        for_problems(pool, A, [&](int lo, int hi) {
+            double rr[ra::BATCH_MAX_M];
+            for (int a = lo; a < hi; ++a) {
+                const int b = act[a];
+                const ra_problem* Pb = P[b];
+                const double* row = ws.hout + (size_t)a * ra::BATCH_COLS;
+                double pR = 0.0;
+                for (int j = 0; j < Pb->m; ++j) pR += p_eval[a][j] * Pb->R[j];
+                const double gv = pR + row[ra::BATCH_MAX_M];
+                if (!std::isfinite(gv)) {
+                    bad[a] = 1;
+                    continue;
+                }
+                for (int j = 0; j < Pb->m; ++j) rr[j] = row[j];
+                loops[b].feed(p_eval[a], gv, rr, row[ra::BATCH_MAX_M + 2]);
+            }
+        });
+        for (int a = 0; a < A; ++a)
+            if (bad[a]) return fail(ctx, RA_ENUMERIC, "problem %d: non-finite dual value", act[a]);
     }
     // the last reduction may still be retiring after its flag
     RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
