@@ -901,9 +901,10 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
 // active problems a < header[0] (blocks stride over them).  Seven groups of
 // BATCH_COLS lanes take every seventh slot, and their sums are added in
 // group order (a fixed order, so results are reproducible).  With `flag`,
-// out is host memory the host polls: one lane per block writes the block's
-// rows and makes them visible system-wide, then takes a ticket; the block
-// with the last ticket resets the counter and raises *flag = 1.
+// out is host memory the host polls: lane c of a block writes column c of
+// the block's rows, and one lane makes them visible system-wide and takes a
+// ticket; the block with the last ticket resets the counter and raises
+// *flag = 1.
 constexpr int BATCH_RED_GROUPS = 7;  // 7 x 35 lanes of a 256-lane block
 
 __global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__ partial,
@@ -914,7 +915,6 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__
                                                       unsigned* __restrict__ flag)
 {
     __shared__ double grp[BATCH_RED_GROUPS][BATCH_COLS];
-    __shared__ double row[BATCH_COLS];
     const int tid = threadIdx.x;
     const int g = tid / BATCH_COLS, c = tid % BATCH_COLS;
     const int A = header[0];
@@ -931,11 +931,8 @@ __global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__
         if (tid < BATCH_COLS) {
             double s = grp[0][tid];
             for (int h = 1; h < BATCH_RED_GROUPS; ++h) s += grp[h][tid];
-            row[tid] = s;
+            out[(int64_t)a * BATCH_COLS + tid] = s;
         }
-        __syncthreads();
-        if (tid == 0)
-            for (int k = 0; k < BATCH_COLS; ++k) out[(int64_t)a * BATCH_COLS + k] = row[k];
         __syncthreads();
     }
     if (flag && tid == 0) {
