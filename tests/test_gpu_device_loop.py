@@ -212,3 +212,19 @@ def test_kernel_timing_keeps_the_host_loop(ctx, torch):
         ra.ra_set_kernel_timing(ctx.handle, False)
     assert np.array_equal(pa, pb) and ia["dual_evals"] == ib["dual_evals"]
     assert launches >= ib["dual_evals"]
+
+
+@pytest.mark.parametrize("n,m", [(1, 4), (65, 8), (1000, 64)])
+def test_tiny_and_ragged_problems(ctx, torch, n, m):
+    """A single job, one tile and a ragged second, a few tiles at m = 64:
+    the device loop ends as the host loop does."""
+    I = synth.random_small(n, m, seed=530 + n, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    kw = dict(tol_rel=1e-6, max_iter=100, stall_evals=40)
+    ph, ih, sh = prob.solve(**kw)
+    pd, idv, sd = prob.solve(device_loop=True, **kw)
+    assert sd == sh
+    assert idv["dual_evals"] == ih["dual_evals"] and idv["iters"] == ih["iters"]
+    assert np.allclose(pd, ph, rtol=1e-5, atol=1e-12)
+    if np.isfinite(ih["rel_gap"]):
+        assert idv["rel_gap"] == pytest.approx(ih["rel_gap"], rel=1e-3, abs=1e-9)
