@@ -37,15 +37,19 @@ def test_trained_network_gains_over_cold_start():
     lv = s["0.001"]
     assert lv["warm"]["evals_median"] < lv["cold"]["evals_median"]
     assert lv["warm"]["reached"] >= lv["cold"]["reached"] - 1
-    # certificate of one warm solve, re-evaluated by the oracle on a host copy
-    T, w, c, kind, R = synth.warmstart_device(50000, m, seed=synth.BASE_SEED + 400000)
-    pr = ra.Problem(ctx, T, w, c, kind, R, 1e-3)
-    p, inf, _ = pr.solve_learned(net, tol_rel=1e-4, stall_evals=100)
-    Th, wh, ch, kh = T.cpu().numpy(), w.cpu().numpy(), c.cpu().numpy(), kind.cpu().numpy()
-    d = oracle.dual_eval(Th, wh, ch, kh, 1e-3, R, p, per_job=True)
-    U, _ = oracle.lower_bound(Th, wh, ch, kh, 1e-3, R, d.r, d.jobs)
-    assert abs(inf["g"] - d.g) <= 1e-5 * (abs(d.g) + abs(U))
-    assert abs(inf["U_lb"] - U) <= 1e-5 * (abs(d.g) + abs(U))
-    pr.close()
+    # certificates of warm solves, re-evaluated by the oracle on a host copy:
+    # at the evaluation size of the test and at the full evaluation size of
+    # the learned-start configuration (n = 1e6, m = 16)
+    for n_eval, seed in ((50000, synth.BASE_SEED + 400000), (1_000_000, synth.BASE_SEED + 200000)):
+        T, w, c, kind, R = synth.warmstart_device(n_eval, m, seed=seed)
+        pr = ra.Problem(ctx, T, w, c, kind, R, 1e-3)
+        p, inf, _ = pr.solve_learned(net, tol_rel=1e-4, stall_evals=100)
+        Th, wh, ch, kh = T.cpu().numpy(), w.cpu().numpy(), c.cpu().numpy(), kind.cpu().numpy()
+        d = oracle.dual_eval(Th, wh, ch, kh, 1e-3, R, p, per_job=True)
+        U, _ = oracle.lower_bound(Th, wh, ch, kh, 1e-3, R, d.r, d.jobs)
+        assert abs(inf["g"] - d.g) <= 1e-5 * (abs(d.g) + abs(U))
+        assert abs(inf["U_lb"] - U) <= 1e-5 * (abs(d.g) + abs(U))
+        assert np.isfinite(inf["rel_gap"]) and inf["rel_gap"] < 1e-2
+        pr.close()
     net.close()
     ctx.close()
