@@ -782,3 +782,93 @@ def test_first_vertex_decided_in_single_precision():
     p = np.array([1.0, 1.0])
     assert oracle.first_vertex(T64, p)[0] == 1
     assert oracle.first_vertex(T64.astype(np.float32), p)[0] == 0
+
+
+# ------------------------------- efficiency-per-price margin (j1) -----
+
+def _keys64(T, p):
+    """Efficiency per price a_ij / p_j in FP64: p_j = 0 gives +inf for
+    a_ij > 0, and a_ij = 0 gives key 0 (never chosen), whatever p_j."""
+    T = np.asarray(T, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        k = np.where(p[None, :] > 0, T / np.where(p > 0, p, 1.0)[None, :], np.inf)
+    return np.where(T > 0, k, 0.0)
+
+
+def _margin_numpy(T, p):
+    """(j1, margin) from the sorted keys of each row: j1 = first index of the
+    largest key (-1 when every key is 0), margin = (k1 - k2) / k1 with k2 the
+    largest key among the other entries; 0 for equal keys, 1 when only the
+    best key is infinite."""
+    K = _keys64(T, p)
+    j1 = np.argmax(K, axis=1)
+    k1 = K[np.arange(len(K)), j1]
+    K2 = K.copy()
+    K2[np.arange(len(K)), j1] = -1.0
+    k2 = K2.max(axis=1) if K.shape[1] > 1 else np.zeros(len(K))
+    k2 = np.maximum(k2, 0.0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mg = np.where(np.isinf(k1), np.where(np.isinf(k2), 0.0, 1.0), (k1 - k2) / k1)
+    mg = np.where(k1 > 0, mg, 0.0)
+    return np.where(k1 > 0, j1, -1), mg
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 16, 64])
+def test_margin1_matches_keys_computed_independently(m):
+    """The oracle's first vertex and its margin equal a numpy computation of
+    the sorted keys, on rows with zero entries, zero prices and exact ties."""
+    I = synth.random_small(3000, m, seed=2000 + m, dtype=np.float64, zero_frac=0.2)
+    rng = np.random.default_rng(2100 + m)
+    I.T[::29] = 0.0                                  # rows with nothing to buy
+    if m > 1:
+        I.T[5::31, m - 1] = I.T[5::31, 0]            # equal keys under equal prices
+    p = 0.2 + rng.random(m) * 2
+    if m > 1:
+        p[m - 1] = p[0]
+    for pp in (p, np.where(np.arange(m) % 4 == 1, 0.0, p)):
+        ref = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, pp, per_job=True)
+        j1, mg = _margin_numpy(I.T, pp)
+        assert np.array_equal(ref.jobs["j1"], j1)
+        np.testing.assert_allclose(ref.jobs["margin1"], mg, rtol=1e-12, atol=0)
+
+
+def test_margin1_special_cases():
+    p = np.array([1.0, 2.0, 0.5])
+    cases = [
+        ([1.0, 2.0, 0.5], 0.0),        # keys 1, 1, 1: exact three-way tie
+        ([2.0, 1.0, 0.25], 0.75),      # keys 2, 0.5, 0.5
+        ([0.0, 0.0, 0.0], 0.0),        # nothing to buy: j1 = -1
+        ([0.0, 0.0, 0.3], 1.0),        # a single positive key
+    ]
+    for row, want in cases:
+        J = oracle.subproblem(np.array(row), p, LOG, 1.0, 0.0, 1e-3)
+        assert J["margin1"] == pytest.approx(want, abs=1e-15), (row, J)
+    pz = np.array([0.0, 0.0, 1.0])
+    assert oracle.subproblem(np.array([1.0, 2.0, 5.0]), pz, LOG, 1.0, 0.0, 1e-3)["margin1"] == 0.0
+    J = oracle.subproblem(np.array([1.0, 0.0, 5.0]), pz, LOG, 1.0, 0.0, 1e-3)
+    assert J["j1"] == 0 and J["margin1"] == 1.0    # one free resource beats every finite key
+    J = oracle.subproblem(np.array([0.0, 0.0, 5.0]), pz, LOG, 1.0, 0.0, 1e-3)
+    assert J["j1"] == 2 and J["margin1"] == pytest.approx(1.0)  # a = 0 never wins at p = 0
+
+
+def test_margin1_is_the_relative_price_change_that_moves_the_argmax():
+    """margin1 = mu means: raising the winner's price by a factor below
+    1 / (1 - mu) keeps it the best efficiency per price, and raising it by
+    more hands the first vertex to another resource (a numpy argmax decides,
+    not the oracle)."""
+    rng = np.random.default_rng(2200)
+    T = 0.1 + rng.random((400, 6))
+    p = 0.2 + rng.random(6)
+    ref = oracle.dual_eval(T, np.ones(400), np.zeros(400), np.zeros(400, np.uint8), 1e-3,
+                           np.ones(6), p, per_job=True)
+    checked = 0
+    for i in range(400):
+        j1, mu = int(ref.jobs["j1"][i]), float(ref.jobs["margin1"][i])
+        if not 1e-4 < mu < 0.99:
+            continue
+        for f, stays in ((1.0 - 1e-3, True), (1.0 + 1e-3, False)):
+            q = p.copy()
+            q[j1] *= f / (1.0 - mu)
+            assert (int(np.argmax(T[i] / q)) == j1) == stays, (i, mu, f)
+        checked += 1
+    assert checked > 300
