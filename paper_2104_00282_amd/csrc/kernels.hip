@@ -148,139 +148,184 @@ struct DemandPrices {
     __device__ __forceinline__ F at(int j) const { return b.at(j) * d.at(j); }
 };
 
-// First envelope vertex: largest key a_j * (1/p_j); lowest j on exact ties;
-// a_j = 0 never wins (key 0, or NaN when p_j = 0).
-template <typename F, int M, class Row, class Px>
+// First envelope vertex (§4.1): the largest key a_j * (1/p_j); a_j = 0 never
+// wins (key 0, or NaN when p_j = 0); equal finite keys go to the lowest j.
+// FREE (some price is zero): every free resource with a_j > 0 has key +inf,
+// and of those the one with the largest a_j (then the lowest j) is the
+// vertex: the cost is zero up to the farthest free point, so the nearer free
+// points lie inside an envelope segment.  Taking the first of them instead
+// would make the walk step through every free resource in turn.
+template <typename F, int M, bool FREE, class Row, class Px>
 __device__ __forceinline__ int scan_first(const Row& a, int mm, const Px& px)
 {
-    F best = F(0);
+    F best = F(0), abest = F(0);
     int j1 = -1;
+    auto step = [&](int j) {
+        const F aj = a.get(j);
+        const F key = aj * px.inv(j);
+        bool b = key > best;
+        if constexpr (FREE) b = b | ((key == best) & (key == F(INFINITY)) & (aj > abest));
+        best = b ? key : best;
+        if constexpr (FREE) abest = b ? aj : abest;
+        j1 = b ? j : j1;
+    };
     if constexpr (M > 0) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const F key = a.get(j) * px.inv(j);
-            const bool b = key > best;
-            best = b ? key : best;
-            j1 = b ? j : j1;
-        }
+        for (int j = 0; j < M; ++j) step(j);
     } else {
-        for (int j = 0; j < mm; ++j) {
-            const F key = a.get(j) * px.inv(j);
-            const bool b = key > best;
-            best = b ? key : best;
-            j1 = b ? j : j1;
-        }
+        for (int j = 0; j < mm; ++j) step(j);
     }
     return j1;
 }
 
 // Next envelope vertex after (ac, pc): smallest slope (p_j - pc)/(a_j - ac)
 // over a_j > ac, compared by cross-multiplication; lowest j on ties; -1 if
-// no resource is more efficient than the current vertex.
+// no resource is more efficient than the current vertex.  The cost curve is
+// nondecreasing, so every point right of an envelope vertex costs at least
+// as much (p_j >= pc where a_j > ac); the price difference is clamped at 0,
+// which also makes the comparison false for every a_j <= ac (its left side
+// is >= 0, its right side <= 0) without a second test.
 template <typename F, int M, class Row, class Px>
 __device__ __forceinline__ int scan_next(const Row& a, int mm, const Px& px, F ac, F pc)
 {
     F bn = F(1), bd = F(0);
     int jn = -1;
+    auto step = [&](int j) {
+        const F d = a.get(j) - ac;
+        const F nm = fmax(px.get(j) - pc, F(0));
+        const bool b = nm * bd < bn * d;
+        bn = b ? nm : bn;
+        bd = b ? d : bd;
+        jn = b ? j : jn;
+    };
     if constexpr (M > 0) {
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const F d = a.get(j) - ac;
-            const F nm = px.get(j) - pc;
-            const bool b = (d > F(0)) & (nm * bd < bn * d);
-            bn = b ? nm : bn;
-            bd = b ? d : bd;
-            jn = b ? j : jn;
-        }
+        for (int j = 0; j < M; ++j) step(j);
     } else {
-        for (int j = 0; j < mm; ++j) {
-            const F d = a.get(j) - ac;
-            const F nm = px.get(j) - pc;
-            const bool b = (d > F(0)) & (nm * bd < bn * d);
-            bn = b ? nm : bn;
-            bd = b ? d : bd;
-            jn = b ? j : jn;
-        }
+        for (int j = 0; j < mm; ++j) step(j);
     }
     return jn;
 }
 
-// One job's subproblem (Algorithm 1 of §4.2 as an envelope walk).
-// a.get(j): entry j in an unrolled scan; a.at(j): entry j for a per-lane j;
-// px: the job's prices (SharedPrices or DemandPrices).
-template <typename F, int M, bool AF = true, class Row, class Px>
-__device__ __forceinline__ void solve_job(const Row& a, int mm, const Px& px, F w, F c,
-                                          bool caplin, F eps, Job<F>& J)
+// Maximiser of u(t) minus the cost on the envelope segment from (alo, plo) to
+// (ahi, phi) (§4.2), of slope alpha = (phi - plo) / (ahi - alo):
+//   log, eq. e-opt-t-log: clip((u')^{-1}(alpha), alo, ahi) with
+//     (u')^{-1}(alpha) = w / alpha - eps (+inf for alpha = 0); the alpha-fair
+//     family: (w / alpha)^(1/a) - eps, and for a = 0 (linear) the right end
+//     if w > alpha, else the left end;
+//   capped linear, eq. e-opt-t-target: the left end if w <= alpha, else the
+//     cap clipped to the segment.
+// `on` tells whether the unclipped maximiser reaches the right end, i.e.
+// whether the optimum may lie on a later segment.
+template <typename F, bool AF>
+__device__ __forceinline__ F segment_argmax(bool caplin, F w, F c, F eps, F alo, F plo, F ahi,
+                                            F phi, bool& on)
 {
-    const int j1 = scan_first<F, M>(a, mm, px);
+    const F num = phi - plo, den = ahi - alo;
+    if (!caplin) {
+        F tu;
+        if (!AF || c == F(-1)) {
+            tu = w * den * frcp(num) - eps;
+        } else {
+            const F a = afair_exponent(c);
+            if (a == F(0))
+                tu = (w * den > num) ? F(INFINITY) : F(-INFINITY);
+            else
+                tu = dpow(w * den * frcp(num), frcp(a)) - eps;
+        }
+        on = tu >= ahi;
+        return fmin(fmax(tu, alo), ahi);
+    }
+    if (w * den <= num) {
+        on = false;
+        return alo;
+    }
+    on = c >= ahi;
+    return fmin(fmax(c, alo), ahi);
+}
+
+// The segment of the envelope that holds a job's optimum: ends lo, hi
+// (lo = -1: the origin; hi = -1: nothing to buy) and the optimal throughput t.
+template <typename F>
+struct Seg {
+    int lo, hi, j1;
+    F alo, plo, ahi, phi, t;
+};
+
+// Algorithm 1 of §4.2 as an envelope walk from the origin: the first vertex
+// by the largest efficiency per price, then further vertices only while the
+// segment's maximiser reaches its right end (u - c is concave, so the first
+// segment whose maximiser lies before its right end holds the optimum).
+// a.get(j): entry j in an unrolled scan; a.at(j): entry j for a per-lane j;
+// px: the job's prices (SharedPrices, ArgPrices or DemandPrices); fr: some
+// price is zero (wave-uniform).
+template <typename F, int M, bool AF, class Row, class Px>
+__device__ __forceinline__ Seg<F> walk_job(const Row& a, int mm, const Px& px, F w, F c,
+                                           bool caplin, F eps, bool fr)
+{
+    Seg<F> S;
+    S.j1 = fr ? scan_first<F, M, true>(a, mm, px) : scan_first<F, M, false>(a, mm, px);
     // An all-zero row (j1 < 0) buys nothing: t = 0.  It runs through the same
     // code with an empty segment so that every result has one definition.
-    const bool any = j1 >= 0;
-    int lo = -1, hi = any ? j1 : -1;
-    F alo = F(0), plo = F(0);
-    F ahi = any ? a.at(j1) : F(1), phi = any ? px.at(j1) : F(0);
-    F t = F(0);
+    const bool any = S.j1 >= 0;
+    S.lo = -1;
+    S.hi = any ? S.j1 : -1;
+    S.alo = F(0);
+    S.plo = F(0);
+    S.ahi = any ? a.at(S.j1) : F(1);
+    S.phi = any ? px.at(S.j1) : F(0);
+    S.t = F(0);
     bool walk = any;
     while (walk) {
-        // segment [alo, ahi] of slope alpha = num / den (den > 0, num >= 0)
-        const F num = phi - plo, den = ahi - alo;
-        if (!caplin) {
-            // eq. e-opt-t-log: t = clip((u')^{-1}(alpha), alo, ahi),
-            // (u')^{-1}(alpha) = w / alpha - eps (+inf for alpha = 0); the
-            // alpha-fair family: (w / alpha)^(1/a) - eps, and for a = 0
-            // (linear) the right end if w > alpha, else the left end
-            F tu;
-            if (!AF || c == F(-1)) {
-                tu = w * den * frcp(num) - eps;
-            } else {
-                const F a = afair_exponent(c);
-                if (a == F(0))
-                    tu = (w * den > num) ? F(INFINITY) : F(-INFINITY);
-                else
-                    tu = dpow(w * den * frcp(num), frcp(a)) - eps;
-            }
-            t = fmin(fmax(tu, alo), ahi);
-            walk = tu >= ahi;
-        } else if (w * den <= num) {  // eq. e-opt-t-target, w <= alpha
-            t = alo;
-            walk = false;
-        } else {  // w > alpha: the cap clipped to the segment
-            t = fmin(fmax(c, alo), ahi);
-            walk = c >= ahi;
-        }
+        S.t = segment_argmax<F, AF>(caplin, w, c, eps, S.alo, S.plo, S.ahi, S.phi, walk);
         if (walk) {
-            const int jn = scan_next<F, M>(a, mm, px, ahi, phi);
-            if (jn < 0) {  // right end of the curve, t = max_j a_j
-                t = ahi;
+            const int jn = scan_next<F, M>(a, mm, px, S.ahi, S.phi);
+            if (jn < 0) {  // right end of the curve: t = max_j a_j
                 walk = false;
             } else {
-                lo = hi;
-                alo = ahi;
-                plo = phi;
-                hi = jn;
-                ahi = a.at(jn);
-                phi = px.at(jn);
+                S.lo = S.hi;
+                S.alo = S.ahi;
+                S.plo = S.phi;
+                S.hi = jn;
+                S.ahi = a.at(jn);
+                S.phi = px.at(jn);
             }
         }
     }
-    // eq. e-xixj on the final segment (lo = -1: the origin, x_hi = t / a_hi)
-    const F den = ahi - alo;
+    return S;
+}
+
+// Allocation and net value on the final segment (eq. e-xixj; lo = -1: the
+// origin, x_hi = t / a_hi), v = u(t) - (p_lo x_lo + p_hi x_hi).
+template <typename F, bool AF>
+__device__ __forceinline__ void finish_job(const Seg<F>& S, F w, F c, bool caplin, F eps,
+                                           Job<F>& J)
+{
+    const F den = S.ahi - S.alo;
     const F rden = frcp(den);
-    const F xh = (t - alo) * rden;
-    const F xl = (lo >= 0) ? (ahi - t) * rden : F(0);
-    J.j1 = j1;
-    J.v = utility<F, AF>(caplin, w, c, eps, t) - (plo * xl + phi * xh);
+    const F xh = (S.t - S.alo) * rden;
+    const F xl = (S.lo >= 0) ? (S.ahi - S.t) * rden : F(0);
+    J.j1 = S.j1;
+    J.v = utility<F, AF>(caplin, w, c, eps, S.t) - (S.plo * xl + S.phi * xh);
     // a zero share is not part of the support; a single resource is
     // reported as (j_lo, j_hi) = (-1, j).  Written with selects only, so the
     // result stays in registers.
     const bool left = xh == F(0);   // t at the left end: only `lo` (or nothing)
     const bool right = xl == F(0);  // only `hi`
-    J.jhi = left ? lo : hi;
-    J.jlo = (left | right) ? -1 : lo;
+    J.jhi = left ? S.lo : S.hi;
+    J.jlo = (left | right) ? -1 : S.lo;
     J.xhi = left ? xl : xh;
     J.xlo = (left | right) ? F(0) : xl;
-    J.thi = left ? alo * xl : ahi * xh;
-    J.tlo = (left | right) ? F(0) : alo * xl;
+    J.thi = left ? S.alo * xl : S.ahi * xh;
+    J.tlo = (left | right) ? F(0) : S.alo * xl;
+}
+
+// One job's subproblem (§3, eq. e-subprob) by the envelope walk.
+template <typename F, int M, bool AF = true, class Row, class Px>
+__device__ __forceinline__ void solve_job(const Row& a, int mm, const Px& px, F w, F c,
+                                          bool caplin, F eps, bool fr, Job<F>& J)
+{
+    finish_job<F, AF>(walk_job<F, M, AF>(a, mm, px, w, c, caplin, eps, fr), w, c, caplin, eps, J);
 }
 
 // log(1 + x) for x >= 0, FP32: a degree-5 Taylor polynomial below 1/32
@@ -415,6 +460,10 @@ __global__ void __launch_bounds__(256) k_dual_vec(
     }
     if (lane < M) hist[wv][lane] = 0.f;
     __syncthreads();
+    // some price zero (wave-uniform): the first-vertex scans then order free
+    // resources by throughput
+    const bool freep = __ballot(ptab[lane % M] == 0.f) != 0ull;
+    const bool freeq = prev && (__ballot(qtab[lane % M] == 0.f) != 0ull);
 
     double racc = 0.0, vacc = 0.0, uacc = 0.0, duacc = 0.0;
     const int64_t ntiles = (n + TR - 1) / TR;
@@ -504,13 +553,12 @@ __global__ void __launch_bounds__(256) k_dual_vec(
             }
             const LdsRow drow{dtl + lane * S};
             const bool caplin = is_capped(wc.y);
-            auto solve = [&](auto base, Job<float>& out) {
+            // the job's prices: the base prices, scaled by its demand vector
+            auto job_prices = [&](auto base) {
                 if constexpr (DV)
-                    solve_job<float, M>(row, M,
-                                        DemandPrices<float, decltype(base), LdsRow>{base, drow},
-                                        wc.x, wc.y, caplin, eps, out);
+                    return DemandPrices<float, decltype(base), LdsRow>{base, drow};
                 else
-                    solve_job<float, M>(row, M, base, wc.x, wc.y, caplin, eps, out);
+                    return base;
             };
             // the price block at the start of the argument segment, its address
             // made opaque once per tile: the prices are then read again for
@@ -520,13 +568,18 @@ __global__ void __launch_bounds__(256) k_dual_vec(
                                : (ArgPtr<M>)__builtin_amdgcn_kernarg_segment_ptr();
             asm volatile("" : "+s"(pk));
             Job<float> J;
-            solve(ArgPrices<M, false>{pk, ptab}, J);
+            const Seg<float> SP = walk_job<float, M, true>(
+                row, M, job_prices(ArgPrices<M, false>{pk, ptab}), wc.x, wc.y, caplin, eps, freep);
+            finish_job<float, true>(SP, wc.x, wc.y, caplin, eps, J);
             if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? drow.at(J.jlo) : dj) * J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? drow.at(J.jhi) : dj) * J.xhi);
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<float> K;
-                solve(ArgPrices<M, true>{pk, qtab}, K);
+                const Seg<float> SQ = walk_job<float, M, true>(
+                    row, M, job_prices(ArgPrices<M, true>{pk, qtab}), wc.x, wc.y, caplin, eps,
+                    freeq);
+                finish_job<float, true>(SQ, wc.x, wc.y, caplin, eps, K);
                 float u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab,
                                u, loss);
@@ -594,6 +647,14 @@ __global__ void __launch_bounds__(256) k_dual_gen(
     const bool prev = pb->has_prev != 0;
     for (int j = lane; j < m; j += 64) hist[wv][j] = F(0);
     __syncthreads();
+    // some price zero (wave-uniform): see scan_first
+    bool zp = false, zq = false;
+    for (int j = lane; j < m; j += 64) {
+        zp |= P[j] == F(0);
+        zq |= prev && pb->q[j] == F(0);
+    }
+    const bool freep = __ballot(zp) != 0ull;
+    const bool freeq = __ballot(zq) != 0ull;
 
     double racc[4] = {0.0, 0.0, 0.0, 0.0};
     double vacc = 0.0, uacc = 0.0, duacc = 0.0;
@@ -608,23 +669,23 @@ __global__ void __launch_bounds__(256) k_dual_gen(
             const bool caplin = is_capped(wc.y);
             const F dj = dem ? dem[i] : F(1);
             const GlobalRow<F> drow{DV ? dvec + i * m : nullptr};
-            auto solve = [&](const F* Pp, const F* IPp, Job<F>& out) {
+            auto solve = [&](const F* Pp, const F* IPp, bool fr, Job<F>& out) {
                 if constexpr (DV)
                     solve_job<F, 0>(row, m,
                                     DemandPrices<F, SharedPrices<F>, GlobalRow<F>>{
                                         SharedPrices<F>{Pp, IPp, Pp}, drow},
-                                    wc.x, wc.y, caplin, eps, out);
+                                    wc.x, wc.y, caplin, eps, fr, out);
                 else
                     solve_job<F, 0>(row, m, SharedPrices<F>{Pp, IPp, Pp}, wc.x, wc.y, caplin, eps,
-                                    out);
+                                    fr, out);
             };
-            solve(P, IP, J);
+            solve(P, IP, freep, J);
             if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? drow.at(J.jlo) : dj) * J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? drow.at(J.jhi) : dj) * J.xhi);
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<F> K;
-                solve(pb->q, pb->invq, K);
+                solve(pb->q, pb->invq, freeq, K);
                 F u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, pb->s, pb->sc,
                                u, loss);
@@ -692,9 +753,9 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
                                               const float* __restrict__ Qp,
                                               const float* __restrict__ IQ, const float* ptab,
                                               const float* qtab, const float* stab,
-                                              const float* sctab, bool prev, int lane,
-                                              double& racc, double& vacc, double& uacc,
-                                              double& duacc)
+                                              const float* sctab, bool prev, bool freep,
+                                              bool freeq, int lane, double& racc, double& vacc,
+                                              double& uacc, double& duacc)
 {
     constexpr int Q = M / 4;
     constexpr int S = M + ((Q & 1) ? 0 : 4);
@@ -719,14 +780,14 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
             const bool caplin = is_capped(wc[k].y);
             Job<float> J;
             solve_job<float, M, AF>(row, M, SharedPrices<float>{P, IP, ptab}, wc[k].x, wc[k].y,
-                                    caplin, eps, J);
+                                    caplin, eps, freep, J);
             if (J.jlo >= 0) atomicAdd(&hist[J.jlo], dm[k] * J.xlo);
             if (J.jhi >= 0) atomicAdd(&hist[J.jhi], dm[k] * J.xhi);
             vacc += (double)J.v * (double)dm[k];
             if (prev) {
                 Job<float> K;
                 solve_job<float, M, AF>(row, M, SharedPrices<float>{Qp, IQ, qtab}, wc[k].x,
-                                        wc[k].y, caplin, eps, K);
+                                        wc[k].y, caplin, eps, freeq, K);
                 float u, loss;
                 scaled_utility<float, AF>(caplin, wc[k].x, wc[k].y, eps, K.jlo, K.jhi, K.tlo,
                                           K.thi, stab, sctab, u, loss);
@@ -809,6 +870,7 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
 
     int slot = segbase[w];
     int cur = -1;
+    bool freep = false, freeq = false;  // some price zero (see scan_first)
     BatchItem it;
     const float *P = nullptr, *IP = nullptr, *Qp = nullptr, *IQ = nullptr;
     double racc = 0.0, vacc = 0.0, uacc = 0.0, duacc = 0.0;
@@ -842,6 +904,8 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
             IP = pr + BATCH_MAX_M;
             Qp = pr + 2 * BATCH_MAX_M;
             IQ = pr + 3 * BATCH_MAX_M;
+            freep = __ballot(lane < it.m && pr[lane] == 0.f) != 0ull;
+            freeq = __ballot(lane < it.m && pr[2 * BATCH_MAX_M + lane] == 0.f) != 0ull;
             if (lane < it.m) {
                 tabs[wv][0][lane] = pr[lane];
                 tabs[wv][1][lane] = pr[2 * BATCH_MAX_M + lane];
@@ -877,19 +941,19 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
         const float* sct = tabs[wv][3];
         switch (m) {
         case 4:
-            batch_compute<4, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+            batch_compute<4, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane, racc,
                              vacc, uacc, duacc);
             break;
         case 8:
-            batch_compute<8, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane, racc,
+            batch_compute<8, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane, racc,
                              vacc, uacc, duacc);
             break;
         case 16:
-            batch_compute<16, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+            batch_compute<16, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane,
                               racc, vacc, uacc, duacc);
             break;
         default:
-            batch_compute<32, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, lane,
+            batch_compute<32, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane,
                               racc, vacc, uacc, duacc);
             break;
         }

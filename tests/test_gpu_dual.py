@@ -46,8 +46,18 @@ def _run(ctx, torch, I, p, tol):
     return info
 
 
-# several tiles per wave, several blocks, and a ragged last tile
+# several blocks and a ragged last tile; every wave gets at most one tile at
+# this size (the grid asks for one wave per tile up to its occupancy cap), so
+# the carry of prefetched tiles and deferred stores from one tile to the next
+# is covered by test_vectorised_several_tiles_per_wave
 N_SMALL = 64 * 4 * 5 + 37
+
+# The vectorised kernels launch at most 8 blocks of 4 waves per CU (2048
+# threads per CU): with n above 2 x 64 x 32 x CUs every wave takes at least
+# two 64-job tiles, whatever the kernel's occupancy.
+def _n_two_tiles_per_wave(torch):
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return 2 * 64 * 32 * cus
 
 
 @pytest.mark.parametrize("m", [4, 8, 16, 32, 64])
@@ -57,6 +67,18 @@ def test_vectorised_classes(ctx, torch, m):
     rng = np.random.default_rng(m)
     for p in (np.ones(m), 0.2 + rng.random(m) * 3):
         _run(ctx, torch, I, p, TOL32)
+
+
+@pytest.mark.parametrize("m", [4, 8, 16, 32])
+def test_vectorised_several_tiles_per_wave(ctx, torch, m):
+    """Every job compared with the oracle at a size where each wave of the
+    vectorised kernel solves two or more tiles (prefetch of the next tile,
+    per-job outputs stored one tile late) and the last tile is ragged."""
+    n = _n_two_tiles_per_wave(torch) + 37
+    print("vectorised m=%d n=%d" % (m, n), flush=True)
+    I = synth.random_small(n, m, seed=150 + m, dtype=np.float32)
+    p = 0.2 + np.random.default_rng(150 + m).random(m) * 3
+    _run(ctx, torch, I, p, TOL32)
 
 
 @pytest.mark.parametrize("m", [1, 3, 5, 17, 100, 256])
@@ -94,7 +116,7 @@ def test_zero_entries_and_zero_prices(ctx, torch):
         prob = _problem(ctx, torch, I)
         p = round_prices(p, np.float32)
         out = prob.dual_eval(p, lower_bound=True, support=True, j1=True)
-        compare_dual(I, p, out, TOL32, max_mismatch_frac=1.0)
+        compare_dual(I, p, out, TOL32, max_mismatch_frac=1.0, min_clear=0.0)
         prob.close()
 
 
@@ -132,7 +154,7 @@ def test_exact_ties(ctx, torch):
     p = np.array([1, 2, 1, 2, 0.5, 0.5, 3, 3], dtype=np.float64)
     _run_ties = _problem(ctx, torch, I)
     out = _run_ties.dual_eval(p, lower_bound=True, support=True, j1=True)
-    compare_dual(I, p, out, TOL32, max_mismatch_frac=1.0)
+    compare_dual(I, p, out, TOL32, max_mismatch_frac=1.0, min_clear=0.0)
     _run_ties.close()
 
 
@@ -145,43 +167,20 @@ def test_mixed16_full_size(ctx, torch):
         _run(ctx, torch, I, p, TOL32)
 
 
-def test_roofline64_full_size_sampled(ctx, torch):
+def test_roofline64_full_size(ctx, torch):
     """The roofline workload (n = 1e7, m = 64) in the launch configuration
-    the benchmark times: all outputs at full size, 20,000 sampled jobs
-    compared one by one with the oracle, r checked against the sum of the
-    reported allocations over all 1e7 jobs."""
+    the benchmark times, every job compared with the oracle: j1, the support
+    and shares of all 1e7 jobs, r, g and U(X~) (relative 1e-5)."""
     print("roofline-64 full size: generating", flush=True)
     I = synth.roofline_64()
     prob = _problem(ctx, torch, I, validate=False)
     p = round_prices(np.full(64, 0.12), np.float32)
     print("roofline-64: evaluating", flush=True)
     out = prob.dual_eval(p, lower_bound=True, support=True, j1=True)
-    jp = out["j_pair"].long()
-    xp = out["x_pair"].double()
-    r = torch.zeros(64, dtype=torch.float64, device=jp.device)
-    for k in range(2):
-        sel = jp[:, k] >= 0
-        r.index_add_(0, jp[sel, k], xp[sel, k])
-    r = r.cpu().numpy()
-    assert np.all(np.abs(out["r"] - r) <= 1e-6 * np.maximum(I.R, r))
-    assert out["g"] >= out["lower_bound"]
-    rng = np.random.default_rng(9)
-    idx = np.sort(rng.choice(I.n, 20000, replace=False))
-    sub = synth.Instance("sample", I.T[idx], I.w[idx], I.c[idx], I.kind[idx], I.R, I.eps, 0)
-    sout = {"j1": out["j1"][idx], "j_pair": out["j_pair"][idx], "x_pair": out["x_pair"][idx]}
-    import oracle
-    ref = oracle.dual_eval(sub.T, sub.w, sub.c, sub.kind, sub.eps, sub.R, p, per_job=True)
-    # per-job comparison only: r, g of the sample are compared through the
-    # sample's own oracle sums
-    Xg_r = np.zeros(64)
-    jpn = sout["j_pair"].cpu().numpy()
-    xpn = sout["x_pair"].cpu().numpy().astype(np.float64)
-    for k in range(2):
-        ok = jpn[:, k] >= 0
-        np.add.at(Xg_r, jpn[ok, k], xpn[ok, k])
-    sout["r"] = Xg_r
-    sout["g"] = ref.g  # g of the sample is not produced by the kernel
-    compare_dual(sub, p, sout, TOL32)
+    prob.close()
+    print("roofline-64: oracle over all rows", flush=True)
+    info = compare_dual(I, p, out, TOL32)
+    print("roofline-64:", info, flush=True)
 
 
 def test_deterministic(ctx, torch):

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import to_device
+from gpu_util import _utility64, check_relative, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -106,15 +106,25 @@ def test_allocation_matches_certificate(ctx, torch):
 
 
 @pytest.mark.parametrize("m", [64, 16])
-def test_fused_certificate_matches_separate_bound(ctx, torch, m):
+@pytest.mark.parametrize("free", [False, True])
+def test_fused_certificate_matches_separate_bound(ctx, torch, m, free):
     """A solve's certificate comes from the fused pass (the next pass solves
-    every job again at the previous prices inside the same sweep over T); it
-    must agree with the separate lower-bound path of ra_dual_eval at the same
-    prices, on a ragged n, after runs of several lengths."""
+    every job again at the previous prices inside the same sweep over T); it must
+    agree with the separate lower-bound path of ra_dual_eval at the same
+    prices, on a ragged n, after runs of several lengths.  free: limits far
+    above demand on a quarter of the resources, whose prices then reach zero
+    (trial points with free resources, where the first-vertex scan orders
+    free resources by throughput)."""
     I = synth.random_small(100003, m, seed=46 + m, dtype=np.float32)
+    if free:
+        I.R[::4] = 10.0 * I.n
     prob = _problem(ctx, torch, I)
+    p0 = None
+    if free:
+        p0, _, _ = prob.solve(tol_rel=0.0, max_iter=30, max_evals=40)
+        assert np.count_nonzero(p0 == 0) >= 1
     for iters in (1, 2, 5, 17):
-        p, info, _ = prob.solve(tol_rel=0.0, max_iter=iters, max_evals=iters + 1)
+        p, info, _ = prob.solve(p0=p0, tol_rel=0.0, max_iter=iters, max_evals=iters + 1)
         d = prob.dual_eval(p, lower_bound=True)
         assert info["g"] == d["g"]
         assert info["U_lb"] == pytest.approx(d["lower_bound"], rel=1e-10)
@@ -196,3 +206,56 @@ def test_gap_of_first_point_matches_oracle(ctx, torch, m, log_frac, r_scale, alp
     assert gap > 1e-3 * abs(g)  # columns overused at p = 1: scaling loses utility
     assert info["g"] == pytest.approx(g, rel=1e-5)
     assert abs(gap_gpu - gap) <= 1e-4 * gap + 1e-7 * abs(g)
+
+
+def _oracle_certificate(I, p):
+    """g and U(X~) at p by the oracle, with the magnitudes of their summed
+    terms (for check_relative)."""
+    d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+    U, du = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, d.r, d.jobs)
+    scale_g = abs(float(p @ I.R)) + np.abs(d.jobs["v"]).sum()
+    w64, c64 = I.w.astype(np.float64), I.c.astype(np.float64)
+    uabs = 2.0 * np.abs(_utility64(I.kind, w64, c64, I.eps, d.jobs["t"])).sum()
+    return d.g, U, scale_g, uabs
+
+
+def test_roofline64_solver_passes_certified(ctx, torch):
+    """The pass the benchmark times, at its full size (n = 1e7, m = 64, about
+    76 tiles per wave): eight passes of a cold solve, each also certifying
+    the previous point, among them a trial point with a zero price.
+    The oracle re-evaluates g and U(X~) at the best certified prices over all
+    1e7 rows (relative 1e-5)."""
+    print("roofline-64 solve: generating", flush=True)
+    I = synth.roofline_64()
+    prob = _problem(ctx, torch, I)
+    p, info, _ = prob.solve(tol_rel=0.0, max_iter=8, max_evals=8)
+    prob.close()
+    assert info["dual_evals"] == 8 and np.isfinite(info["U_lb"])
+    print("roofline-64 solve: oracle certificate", info, flush=True)
+    g, U, sg, su = _oracle_certificate(I, p)
+    check_relative(info["g"], g, sg, 1e-5, "g")
+    check_relative(info["U_lb"], U, su, 1e-5, "U(X~)")
+    assert info["rel_gap"] == pytest.approx((g - U) / max(abs(g), abs(U)), rel=1e-2, abs=1e-6)
+
+
+def test_mixed16_solve_to_target(ctx, torch):
+    """The mixed-16 configuration (n = 1e6, m = 16, log and capped-linear
+    jobs) solved to its time-to-gap target: 1e-6, or 1.5 times the gap floor
+    the FP64 oracle's own cold solve reaches when that floor lies above 1e-6
+    (capped-linear jobs at ties bound what the paper's column-scaling
+    recovery can certify).  The oracle re-evaluates g and U(X~) at the
+    returned prices over all rows."""
+    I = synth.mixed_16()
+    print("mixed-16: oracle floor", flush=True)
+    _, io = oracle.solve(I.T, I.w, I.c, I.kind, I.eps, I.R, tol_rel=0.0, max_iter=40)
+    target = max(1e-6, 1.5 * io["rel_gap"])
+    prob = _problem(ctx, torch, I)
+    p, info, st = prob.solve(tol_rel=target, max_iter=300, stall_evals=100)
+    prob.close()
+    print("mixed-16: target %.3g, oracle floor %.3g, GPU" % (target, io["rel_gap"]), info,
+          flush=True)
+    assert info["converged"] == 1 and info["rel_gap"] <= target
+    g, U, sg, su = _oracle_certificate(I, p)
+    check_relative(info["g"], g, sg, 1e-5, "g")
+    check_relative(info["U_lb"], U, su, 1e-5, "U(X~)")
+    assert (g - U) / max(abs(g), abs(U)) <= target + 1e-6
