@@ -124,8 +124,9 @@ ra_status ra_problem_destroy(ra_problem *prob);
  *   j1           device, n int16 or NULL: argmax_j a_ij / p_j, the first
  *                vertex of the job's cost curve, decided in the element type
  *                with the key a_ij * (1/p_j) (1/p_j rounded to dt, +inf for
- *                p_j = 0); lowest j on equal keys; -1 when no key is
- *                positive (an all-zero row).  With demand vectors the prices
+ *                p_j = 0); lowest j on equal finite keys; among free
+ *                resources (p_j = 0, infinite keys) the largest a_ij, then
+ *                the lowest j; -1 when no key is positive (an all-zero row).  With demand vectors the prices
  *                are d_ij p_j and the FP32 kernels form the reciprocal with
  *                the hardware approximation (about 1 ulp)
  * Errors: RA_EINVAL, RA_EDEVICE, RA_ENUMERIC (non-finite g or grad). */
