@@ -134,6 +134,26 @@ ra_status ra_dual_eval(ra_ctx *ctx, const ra_problem *prob, const double *p, dou
                        double *grad, double *lower_bound, int16_t *j_pair, void *x_pair,
                        int16_t *j1);
 
+/* ra_dual_eval for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments and results as ra_dual_eval without the per-job outputs:
+ *   p            host, m prices (>= 0, finite)
+ *   g, grad      host, 1 and m: g(p) and R - r
+ *   lower_bound  host, 1 or NULL: U(X~), here from a second pass over T that
+ *                solves every job again at p and scales it by the column
+ *                scales of r(p), instead of a per-job workspace
+ * No device memory is allocated: the dual kernel's block partials and their
+ * column sums live in a static device array of 2 MiB + 2 KiB that each GPU
+ * the library runs on holds until the process ends; a launch uses at most
+ * 2^18 / (m + 3) blocks so that its partials fit (the kernels stride over
+ * the jobs), so every problem the library accepts fits.  Calls on one GPU
+ * share that array: calls that overlap on one GPU (other threads, other
+ * contexts) race and must be serialised by the caller.  Synchronous on the
+ * context stream.
+ * Errors: RA_EINVAL, RA_EDEVICE, RA_ENUMERIC, as ra_dual_eval. */
+ra_status ra_dual_eval_noalloc(ra_ctx *ctx, const ra_problem *prob, const double *p, double *g,
+                               double *grad, double *lower_bound);
+
 /* Options of the price-discovery loop (§5, Algorithm 2). */
 typedef struct {
     double tol_rel;          /* stop when (g - U(X~)) / max(|g|, |U(X~)|) <= tol_rel */

@@ -57,6 +57,7 @@ PROTOTYPES = {
                                 _vp, _d, _int]),
     "ra_problem_destroy": (_st, [_vp]),
     "ra_dual_eval": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "ra_dual_eval_noalloc": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "ra_solve_opts_default": (None, [ctypes.POINTER(ra_solve_opts)]),
     "ra_solve": (_st, [_vp, _vp, ctypes.POINTER(ra_solve_opts), _vp,
                        ctypes.POINTER(ra_solve_info)]),

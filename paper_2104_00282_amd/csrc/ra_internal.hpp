@@ -23,6 +23,7 @@ struct ra_ctx {
     std::string err;
     int live_problems = 0;  // problems created on this context and not destroyed
     bool closed = false;    // ra_destroy called; freed when the last problem goes
+    double* scratch = nullptr; // device address of this device's static scratch
     bool timing = false;    // bracket dual-kernel launches with events
     bool timed_pending = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -29,12 +29,41 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
+
+// Device scratch of the allocation-free evaluation (ra_dual_eval_noalloc):
+// the dual kernel's block partials, then the column sums they reduce to.
+// Each GPU the library runs on holds its own copy until the process ends.
+constexpr int NOALLOC_PARTIAL = 1 << 18;                  // doubles (2 MiB)
+constexpr int NOALLOC_OUT = RA_MAX_RESOURCES + 3;         // one row of column sums
+static __device__ __align__(256) double scratch[NOALLOC_PARTIAL + NOALLOC_OUT];
 
 namespace {
 
 using ra::fail;
+
+// The device address of `scratch` on each device, found once per device
+// with that device current (the host-side name of the array is not a device
+// address).
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+double* scratch_ptr[MAX_DEVICES] = {};
+
+hipError_t scratch_address(int dev, double** out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* a = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = static_cast<double*>(a);
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
 
 size_t elt(int dt) { return dt == 0 ? 4 : 8; }
 size_t price_block_bytes(int dt)
@@ -74,7 +103,7 @@ double fill_prices(ra_problem* P, const double* p, std::vector<double>* prounded
 // Ask the next pass for the lower bound of a previously evaluated point:
 // its (already rounded) prices q and the column scales of its usage r (§5).
 template <typename F>
-void fill_prev_t(ra_problem* P, const std::vector<double>& q, const std::vector<double>& r)
+void fill_prev_t(ra_problem* P, const double* q, const double* r)
 {
     auto* b = static_cast<ra::PriceBlock<F>*>(P->h_pblock);
     for (int j = 0; j < P->m; ++j) {
@@ -88,12 +117,18 @@ void fill_prev_t(ra_problem* P, const std::vector<double>& q, const std::vector<
     b->has_prev = 1;
 }
 
-void fill_prev(ra_problem* P, const std::vector<double>& q, const std::vector<double>& r)
+// The same from plain arrays (m entries each).
+void fill_prev_arrays(ra_problem* P, const double* q, const double* r)
 {
     if (P->dt == 0)
         fill_prev_t<float>(P, q, r);
     else
         fill_prev_t<double>(P, q, r);
+}
+
+void fill_prev(ra_problem* P, const std::vector<double>& q, const std::vector<double>& r)
+{
+    fill_prev_arrays(P, q.data(), r.data());
 }
 
 // The vectorised dual kernels need T, and demand vectors when set, 16-byte
@@ -311,6 +346,10 @@ ra_status ra_create(ra_ctx** out, int device_ordinal, void* hip_stream)
         return RA_EDEVICE;
     }
     c->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    if (scratch_address(c->dev, &c->scratch) != hipSuccess) {
+        delete c;
+        return RA_EDEVICE;
+    }
     if (hip_stream) {
         c->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -501,6 +540,77 @@ ra_status ra_dual_eval(ra_ctx* ctx, const ra_problem* prob, const double* p, dou
     }
     *g = gv;
     for (int j = 0; j < P->m; ++j) grad[j] = P->R[j] - o[j];
+    return RA_OK;
+}
+
+ra_status ra_dual_eval_noalloc(ra_ctx* ctx, const ra_problem* prob, const double* p,
+                               double* g, double* grad, double* lower_bound)
+{
+    if (!ctx) return RA_EINVAL;
+    if (!prob || prob->ctx != ctx) return fail(ctx, RA_EINVAL, "problem is NULL or from another context");
+    if (!p || !g || !grad) return fail(ctx, RA_EINVAL, "p, g and grad are required");
+    if (!ctx->scratch) return fail(ctx, RA_EDEVICE, "device scratch address unknown");
+    ra_problem* P = const_cast<ra_problem*>(prob);
+    const int m = P->m;
+    for (int j = 0; j < m; ++j)
+        if (!(p[j] >= 0.0) || !std::isfinite(p[j]))
+            return fail(ctx, RA_EINVAL, "p[%d] = %g must be >= 0 and finite", j, p[j]);
+    // the block partials of at most NOALLOC_PARTIAL / (m + 3) blocks fit the
+    // scratch; the dual kernels stride over the tiles, so a launch with fewer
+    // blocks than the problem's usual grid covers every job
+    const int ncols = ra::partial_cols(m);
+    const int grid = std::min(P->grid, NOALLOC_PARTIAL / ncols);
+    if (grid < 1 || ncols > NOALLOC_OUT)
+        return fail(ctx, RA_EINVAL, "m = %d needs more scratch than the %d doubles held", m,
+                    NOALLOC_PARTIAL + NOALLOC_OUT);
+    RA_HIP(ctx, hipSetDevice(ctx->dev));
+    hipStream_t st = ctx->stream;
+    double* part = ctx->scratch;
+    double* dsum = ctx->scratch + NOALLOC_PARTIAL;
+    const bool vec = ra::dual_is_vec(P->dt, m, dual_vec(P));
+    double pe[RA_MAX_RESOURCES], o[NOALLOC_OUT], r[RA_MAX_RESOURCES];
+    // one pass at p, or (pass 2) at p again with the certificate of p: every
+    // job solved at q = p and its allocation scaled by the column scales of
+    // r(p) (§5), in place of the per-job support workspace of ra_dual_eval
+    auto pass = [&](bool with_prev) -> ra_status {
+        (void)fill_prices(P, p, nullptr);
+        if (with_prev) fill_prev_arrays(P, pe, r);
+        if (!vec)
+            RA_HIP(ctx, hipMemcpyAsync(P->pblock, P->h_pblock, price_block_bytes(P->dt),
+                                       hipMemcpyHostToDevice, st));
+        RA_HIP(ctx, ra::launch_dual(P->dt, m, dual_vec(P), grid, st, P->T, P->prm, P->n,
+                                    P->pblock, P->h_pblock, P->eps, part, nullptr, nullptr,
+                                    nullptr, nullptr, P->dem, P->dvec));
+        RA_HIP(ctx, ra::launch_reduce_cols(st, part, grid, ncols, dsum));
+        RA_HIP(ctx, hipMemcpyAsync(o, dsum, sizeof(double) * ncols, hipMemcpyDeviceToHost, st));
+        RA_HIP(ctx, hipStreamSynchronize(st));
+        return RA_OK;
+    };
+    double pR = 0.0;
+    for (int j = 0; j < m; ++j) {
+        pe[j] = P->dt == 0 ? (double)(float)p[j] : p[j];
+        pR += pe[j] * P->R[j];
+    }
+    ra_status s1 = pass(false);
+    if (s1 != RA_OK) return s1;
+    const double gv = pR + o[m];
+    if (!std::isfinite(gv)) return fail(ctx, RA_ENUMERIC, "non-finite dual value");
+    for (int j = 0; j < m; ++j) {
+        if (!std::isfinite(o[j])) return fail(ctx, RA_ENUMERIC, "non-finite usage");
+        r[j] = o[j];
+    }
+    if (lower_bound) {
+        ra_status s2 = pass(true);
+        if (s2 != RA_OK) return s2;
+        // U(X~) = g - [p^T (R - r) + sum_i (u(t_i) - u(t~_i))]
+        double pq = 0.0;
+        for (int j = 0; j < m; ++j) pq += pe[j] * (P->R[j] - r[j]);
+        const double U = gv - (pq + o[m + 2]);
+        if (!std::isfinite(U)) return fail(ctx, RA_ENUMERIC, "non-finite lower bound");
+        *lower_bound = U;
+    }
+    *g = gv;
+    for (int j = 0; j < m; ++j) grad[j] = P->R[j] - r[j];
     return RA_OK;
 }
 
