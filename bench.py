@@ -695,6 +695,43 @@ def bench_extension(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_pass_curve(args):
+    """A cold solve of the roofline instance, pass by pass (for a kernel
+    trace of passes 1..steps): the plain read of T first (as the default
+    workload does before its timed steps), then `steps` solver passes from
+    p = 1 with no stopping test.  Prints the solve's outcome; the per-pass
+    kernel times come from the profiler's trace."""
+    import torch
+    import synth
+    import paper_2104_00282_amd as ra
+
+    n, m = args.n, 64
+    log("generating roofline instance n=%d m=%d" % (n, m))
+    I = synth.roofline_64(n=n, m=m)
+    dev = torch.device("cuda:0")
+    T = torch.from_numpy(I.T).to(dev)
+    w = torch.from_numpy(I.w).to(dev)
+    c = torch.from_numpy(I.c).to(dev)
+    kind = torch.from_numpy(I.kind).to(dev)
+    ctx = ra.Context(0)
+    prob = ra.Problem(ctx, T, w, c, kind, I.R, I.eps, validate=False)
+    read_ms = ra.ra_stream_read_ms(ctx.handle, T.data_ptr(), n * m * 4, 20)
+    log("cold solve: %d passes" % args.steps)
+    ra.ra_set_kernel_timing(ctx.handle, True)
+    t0 = time.perf_counter()
+    p, info, _ = prob.solve(tol_rel=0.0, max_iter=args.steps, max_evals=args.steps)
+    dt = time.perf_counter() - t0
+    kms, launches = ra.ra_get_kernel_timing(ctx.handle)
+    ra.ra_set_kernel_timing(ctx.handle, False)
+    out = {"metric": "cold solve of the roofline instance, pass by pass", "passes": launches,
+           "dual_kernel_ms_mean": kms / max(launches, 1), "wall_ms": dt * 1e3,
+           "read_ceiling_GB/s": (n * m * 4) / (read_ms / 1e3) / 1e9,
+           "rel_gap": info["rel_gap"], "zero_prices_at_end": int(np.count_nonzero(p == 0))}
+    prob.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def synth_seed(offset):
     import synth
     return synth.BASE_SEED + offset
@@ -742,7 +779,7 @@ def main():
                     help="only run the plain copy used to scale the HBM counters")
     ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
                                            "batch-rounds", "e1", "demand-vectors", "demands",
-                                           "alpha-fair", "dual-evals", "scale"],
+                                           "alpha-fair", "dual-evals", "scale", "pass-curve"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
@@ -765,7 +802,8 @@ def main():
         calibrate_copy()
         return
     if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1",
-                         "demand-vectors", "demands", "alpha-fair", "dual-evals", "scale"):
+                         "demand-vectors", "demands", "alpha-fair", "dual-evals", "scale",
+                         "pass-curve"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
@@ -773,7 +811,7 @@ def main():
          "solves": bench_solves, "batch-rounds": bench_batch_rounds,
          "e1": bench_e1, "demand-vectors": bench_extension, "demands": bench_extension,
          "alpha-fair": bench_extension, "dual-evals": bench_dual_evals,
-         "scale": bench_scale}[args.workload](args)
+         "scale": bench_scale, "pass-curve": bench_pass_curve}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "

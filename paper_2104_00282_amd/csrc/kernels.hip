@@ -295,6 +295,256 @@ __device__ __forceinline__ Seg<F> walk_job(const Row& a, int mm, const Px& px, F
     return S;
 }
 
+
+// ------------------------------------------------------------------------
+// Envelope walk shared by the lanes of a wavefront (vectorised kernels).
+// ------------------------------------------------------------------------
+// A lane-per-job walk makes the whole wave scan a full row whenever any of
+// its 64 jobs needs a further vertex, and usually few do.  Here every lane
+// first finds its job's first vertex and first segment; then, while some
+// jobs still need a further vertex, the W walkers of the wave are ranked and
+// each is given G = 64 / W lanes (rounded down to a power of two, at most
+// M / 4): lane k G + s scans entries [s M/G, (s + 1) M/G) of walker k's row,
+// read from the staged tile, and a butterfly over the G lanes keeps the
+// smallest slope (on equal slopes the lower part, so the lowest j).  The
+// walker then moves to that vertex and takes the closed form on the new
+// segment (segment_argmax), as in walk_from.
+
+// One lane's part of a shared next-vertex scan: entries [s E, (s + 1) E),
+// E = M / G, of the row at rowp (LDS).  G = 1: every lane scans the whole row,
+// so the prices are read at wave-uniform indices (px.get, argument block);
+// otherwise from the price table in LDS, four at a time.
+template <int M, int G, class Px>
+__device__ __forceinline__ void coop_scan_part(const float* rowp, int s, float ac, float pc,
+                                               const Px& px, float& bn, float& bd, int& jn)
+{
+    constexpr int E = M / G;
+    const int j0 = G == 1 ? 0 : s * E;
+    bn = 1.f;
+    bd = 0.f;
+    jn = -1;
+    // the LDS reads of up to 8 chunks (32 entries) at a time, then their
+    // compare chain: the latency is paid once per batch
+    constexpr int NC = E / 4, BC = NC < 8 ? NC : 8;
+#pragma unroll
+    for (int c0 = 0; c0 < NC; c0 += BC) {
+        float4 a4[BC], p4[G == 1 ? 1 : BC];
+#pragma unroll
+        for (int e = 0; e < BC; ++e) {
+            a4[e] = *reinterpret_cast<const float4*>(rowp + j0 + 4 * (c0 + e));
+            if constexpr (G > 1)
+                p4[e] = *reinterpret_cast<const float4*>(px.tab + j0 + 4 * (c0 + e));
+        }
+#pragma unroll
+        for (int e = 0; e < BC; ++e) {
+            const float av[4] = {a4[e].x, a4[e].y, a4[e].z, a4[e].w};
+            float pv[4];
+            if constexpr (G == 1) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) pv[k] = px.get(4 * (c0 + e) + k);
+            } else {
+                pv[0] = p4[e].x;
+                pv[1] = p4[e].y;
+                pv[2] = p4[e].z;
+                pv[3] = p4[e].w;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int j = j0 + 4 * (c0 + e) + k;
+                const float d = av[k] - ac;
+                const float nm = fmaxf(pv[k] - pc, 0.f);  // as scan_next
+                const bool b = nm * bd < bn * d;
+                bn = b ? nm : bn;
+                bd = b ? d : bd;
+                jn = b ? j : jn;
+            }
+        }
+    }
+    // butterfly over the G lanes of this walker: lanes with bit `off` set
+    // hold the upper part of the pair
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const float obn = __shfl_xor(bn, off), obd = __shfl_xor(bd, off);
+        const int ojn = __shfl_xor(jn, off);
+        const bool upper = (threadIdx.x & off) != 0;
+        const float abn = upper ? obn : bn, abd = upper ? obd : bd;
+        const int ajn = upper ? ojn : jn;
+        const float ubn = upper ? bn : obn, ubd = upper ? bd : obd;
+        const int ujn = upper ? jn : ojn;
+        const bool take = (ujn >= 0) & ((ajn < 0) | (ubn * abd < abn * ubd));
+        bn = take ? ubn : abn;
+        bd = take ? ubd : abd;
+        jn = take ? ujn : ajn;
+    }
+}
+
+// Continue the walks of the lanes with `walking` set (S: their current
+// segment, amax: their row's largest throughput) until every job of the
+// wave holds its final segment.  All 64 lanes must call it together.
+// tile: the staged tile (row r at tile + r * RS); slots: 64 ints of LDS.
+template <int M, int RS, bool AF, class Row, class Px>
+__device__ __forceinline__ void coop_walk(Seg<float>& S, bool walking, float amax, const Row& a,
+                                          const Px& px, const float* tile, int* slots, int lane,
+                                          float w, float c, bool caplin, float eps)
+{
+    constexpr int GMAX = M / 4 < 16 ? M / 4 : 16;
+    for (;;) {
+        const uint64_t mask = __ballot(walking);
+        if (mask == 0ull) break;
+        const int W = __popcll(mask);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        const int G0 = W > 32 ? 1 : W > 16 ? 2 : W > 8 ? 4 : W > 4 ? 8 : 16;
+        const int G = G0 < GMAX ? G0 : GMAX;
+        float bn, bd;
+        int jn;
+        if (G == 1) {
+            // more than 32 walkers: every lane scans its own row (no ranking)
+            coop_scan_part<M, 1>(tile + lane * RS, 0, S.ahi, S.phi, px, bn, bd, jn);
+            if (walking) {
+                if (jn < 0) {
+                    walking = false;
+                } else {
+                    S.lo = S.hi;
+                    S.alo = S.ahi;
+                    S.plo = S.phi;
+                    S.hi = jn;
+                    S.ahi = a.at(jn);
+                    S.phi = px.at(jn);
+                    bool on;
+                    S.t = segment_argmax<float, AF>(caplin, w, c, eps, S.alo, S.plo, S.ahi,
+                                                    S.phi, on);
+                    walking = on & (S.ahi < amax);
+                }
+            }
+            continue;
+        }
+        if (walking) slots[rank] = lane;
+        wave_sync();
+        // lane = k G + s works for walker k
+        const int k = lane / G, s = lane & (G - 1);
+        const int wl = k < W ? slots[k] : lane;
+        const float ac = __shfl(S.ahi, wl), pc = __shfl(S.phi, wl);
+        const float* rowp = tile + wl * RS;
+        if constexpr (GMAX >= 2) {
+            if (G == 2)
+                coop_scan_part<M, 2>(rowp, s, ac, pc, px, bn, bd, jn);
+            else if constexpr (GMAX >= 4) {
+                if (G == 4)
+                    coop_scan_part<M, 4>(rowp, s, ac, pc, px, bn, bd, jn);
+                else if constexpr (GMAX >= 8) {
+                    if (G == 8)
+                        coop_scan_part<M, 8>(rowp, s, ac, pc, px, bn, bd, jn);
+                    else if constexpr (GMAX >= 16)
+                        coop_scan_part<M, 16>(rowp, s, ac, pc, px, bn, bd, jn);
+                }
+            }
+        }
+        // walker `rank` reads its result from lane rank G
+        const int jw = __shfl(jn, (rank * G) & 63);
+        wave_sync();  // the slots are written again in the next round
+        if (walking) {
+            if (jw < 0) {  // no point beyond: t = a_hi already
+                walking = false;
+            } else {
+                S.lo = S.hi;
+                S.alo = S.ahi;
+                S.plo = S.phi;
+                S.hi = jw;
+                S.ahi = a.at(jw);
+                S.phi = px.at(jw);
+                bool on;
+                S.t = segment_argmax<float, AF>(caplin, w, c, eps, S.alo, S.plo, S.ahi, S.phi, on);
+                walking = on & (S.ahi < amax);
+            }
+        }
+    }
+}
+
+// The first segment of a job from its first vertex j1: its closed form, and
+// whether the walk goes on (the maximiser reaches the segment's right end
+// and some resource lies beyond it).
+template <bool AF, class Row, class Px>
+__device__ __forceinline__ Seg<float> first_segment(const Row& a, const Px& px, int j1, float amax,
+                                                    float w, float c, bool caplin, float eps,
+                                                    bool& walking)
+{
+    Seg<float> S;
+    const bool any = j1 >= 0;
+    S.j1 = j1;
+    S.lo = -1;
+    S.hi = any ? j1 : -1;
+    S.alo = 0.f;
+    S.plo = 0.f;
+    S.ahi = any ? a.at(j1) : 1.f;
+    S.phi = any ? px.at(j1) : 0.f;
+    S.t = 0.f;
+    walking = false;
+    if (any) {
+        bool on;
+        S.t = segment_argmax<float, AF>(caplin, w, c, eps, S.alo, S.plo, S.ahi, S.phi, on);
+        walking = on & (S.ahi < amax);
+    }
+    return S;
+}
+
+
+// The start of a job's walk when some price is zero, with the row in
+// registers.  A free resource costs nothing, so the first vertex is the free
+// resource with the largest throughput a_F (scan_first's rule), found by a
+// pass over the free entries alone (the index test is wave-uniform) that
+// also takes the row's largest throughput; when the maximiser passes a_F,
+// the next vertex from (a_F, 0) comes from one scan_next, which a later
+// walk round would otherwise do.  Rows with no free throughput (a_j = 0 on
+// every free resource) take the first vertex by efficiency per price.
+// Every lane of the wave must call it together.
+template <int M, bool AF, class Row, class Px>
+__device__ __forceinline__ Seg<float> free_start(const Row& a, const Px& px, float w, float c,
+                                                 bool caplin, float eps, float& amax,
+                                                 bool& walking)
+{
+    float aF = 0.f, am = 0.f;
+    int jF = -1;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const float aj = a.get(j);
+        am = fmaxf(am, aj);
+        if (px.get(j) == 0.f) {
+            const bool b = aj > aF;
+            aF = b ? aj : aF;
+            jF = b ? j : jF;
+        }
+    }
+    amax = am;
+    int j1 = jF;
+    if (__ballot(jF < 0) != 0ull) {
+        const int jk = scan_first<float, M, true>(a, M, px);
+        j1 = jF >= 0 ? jF : jk;
+    }
+    Seg<float> S = first_segment<AF>(a, px, j1, amax, w, c, caplin, eps, walking);
+    const bool from_free = walking & (jF >= 0);
+    if (__ballot(from_free) != 0ull) {
+        const int jn = scan_next<float, M>(a, M, px, S.ahi, S.phi);
+        if (from_free) {
+            if (jn < 0) {
+                walking = false;
+            } else {
+                S.lo = S.hi;
+                S.alo = S.ahi;
+                S.plo = S.phi;
+                S.hi = jn;
+                S.ahi = a.at(jn);
+                S.phi = px.at(jn);
+                bool on;
+                S.t = segment_argmax<float, AF>(caplin, w, c, eps, S.alo, S.plo, S.ahi, S.phi,
+                                                on);
+                walking = on & (S.ahi < amax);
+            }
+        }
+    }
+    return S;
+}
+
 // Allocation and net value on the final segment (eq. e-xixj; lo = -1: the
 // origin, x_hi = t / a_hi), v = u(t) - (p_lo x_lo + p_hi x_hi).
 template <typename F, bool AF>
@@ -423,7 +673,7 @@ struct GlobalRow {
 // The price block is the first kernel argument, so it starts the argument
 // segment (the AMDGPU kernel ABI lays arguments out in order from offset 0).
 template <int M, bool DEM, bool DV>
-__global__ void __launch_bounds__(256) k_dual_vec(
+__global__ void __launch_bounds__(256, 2) k_dual_vec(
     const PriceArgs<M> pa, const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
     float eps, double* __restrict__ partial,
     int* __restrict__ jpair, float2* __restrict__ xpair, float2* __restrict__ tpair,
@@ -446,7 +696,9 @@ __global__ void __launch_bounds__(256) k_dual_vec(
     __shared__ __attribute__((aligned(16))) float tile[4][TR * S];
     __shared__ __attribute__((aligned(16))) float dtile[DV ? 4 : 1][DV ? TR * S : 4];
     __shared__ float hist[4][M];
-    __shared__ float ptab[M], qtab[M], stab[M], sctab[M];
+    __shared__ __attribute__((aligned(16))) float ptab[M], qtab[M];
+    __shared__ float stab[M], sctab[M];
+    __shared__ int wslot[4][64];  // walkers of a shared walk round (coop_walk)
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -540,46 +792,99 @@ __global__ void __launch_bounds__(256) k_dual_vec(
 
         const int64_t i = ti * TR + lane;
         pend_i = -1;
-        if (i < n) {
-            RegRow<M> row;
-            row.lds = tl + lane * S;
+        RegRow<M> row;
+        row.lds = tl + lane * S;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
-                row.v[4 * q + 0] = v.x;
-                row.v[4 * q + 1] = v.y;
-                row.v[4 * q + 2] = v.z;
-                row.v[4 * q + 3] = v.w;
+        for (int q = 0; q < Q; ++q) {
+            const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
+            row.v[4 * q + 0] = v.x;
+            row.v[4 * q + 1] = v.y;
+            row.v[4 * q + 2] = v.z;
+            row.v[4 * q + 3] = v.w;
+        }
+        const bool caplin = is_capped(wc.y);
+        // the price block at the start of the argument segment, its address
+        // made opaque once per tile: the prices are then read again for
+        // every tile instead of being held in scalar registers across the
+        // loop (4 M of them would not fit)
+        ArgPtr<M> pk = dpa ? (ArgPtr<M>)dpa : (ArgPtr<M>)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(pk));
+        Job<float> J, K;
+        if constexpr (DV) {
+            // demand vectors: each job walks its own envelope at d_i * p
+            if (i < n) {
+                const LdsRow drow{dtl + lane * S};
+                using PA = ArgPrices<M, false>;
+                using PB = ArgPrices<M, true>;
+                const DemandPrices<float, PA, LdsRow> pp{PA{pk, ptab}, drow};
+                finish_job<float, true>(
+                    walk_job<float, M, true>(row, M, pp, wc.x, wc.y, caplin, eps, freep), wc.x,
+                    wc.y, caplin, eps, J);
+                if (prev) {
+                    const DemandPrices<float, PB, LdsRow> pq{PB{pk, qtab}, drow};
+                    finish_job<float, true>(
+                        walk_job<float, M, true>(row, M, pq, wc.x, wc.y, caplin, eps, freeq),
+                        wc.x, wc.y, caplin, eps, K);
+                }
             }
-            const LdsRow drow{dtl + lane * S};
-            const bool caplin = is_capped(wc.y);
-            // the job's prices: the base prices, scaled by its demand vector
-            auto job_prices = [&](auto base) {
-                if constexpr (DV)
-                    return DemandPrices<float, decltype(base), LdsRow>{base, drow};
-                else
-                    return base;
+        } else {
+            // every lane takes part (rows past n are zero: nothing to buy),
+            // the walks beyond the first segment shared by the wave
+            // both walk starts read the row from registers; the walks read rows
+            // from the staged tile, so the registers are free then.  The row's
+            // largest throughput (where every walk ends) is found only in waves
+            // where some walk goes on.
+            const ArgPrices<M, false> pp{pk, ptab};
+            const ArgPrices<M, true> pq{pk, qtab};
+            float amax = INFINITY;
+            bool have_max = false;
+            auto row_max = [&](bool on) {
+                if (!have_max && __ballot(on) != 0ull) {
+                    amax = 0.f;
+#pragma unroll
+                    for (int j = 0; j < M; ++j) amax = fmaxf(amax, row.get(j));
+                    have_max = true;
+                }
             };
-            // the price block at the start of the argument segment, its address
-            // made opaque once per tile: the prices are then read again for
-            // every tile instead of being held in scalar registers across the
-            // loop (4 M of them would not fit)
-            ArgPtr<M> pk = dpa ? (ArgPtr<M>)dpa
-                               : (ArgPtr<M>)__builtin_amdgcn_kernarg_segment_ptr();
-            asm volatile("" : "+s"(pk));
-            Job<float> J;
-            const Seg<float> SP = walk_job<float, M, true>(
-                row, M, job_prices(ArgPrices<M, false>{pk, ptab}), wc.x, wc.y, caplin, eps, freep);
+            bool walking, walking_q = false;
+            Seg<float> SP, SQ;
+            if (freep) {
+                SP = free_start<M, true>(row, pp, wc.x, wc.y, caplin, eps, amax, walking);
+                have_max = true;
+            } else {
+                SP = first_segment<true>(row, pp, scan_first<float, M, false>(row, M, pp), amax,
+                                         wc.x, wc.y, caplin, eps, walking);
+                row_max(walking);
+                walking = walking & (SP.ahi < amax);
+            }
+            if (prev) {
+                if (freeq) {
+                    float amq;
+                    SQ = free_start<M, true>(row, pq, wc.x, wc.y, caplin, eps, amq, walking_q);
+                    amax = amq;
+                    have_max = true;
+                } else {
+                    SQ = first_segment<true>(row, pq, scan_first<float, M, false>(row, M, pq),
+                                             amax, wc.x, wc.y, caplin, eps, walking_q);
+                    row_max(walking_q);
+                    walking_q = walking_q & (SQ.ahi < amax);
+                }
+            }
+            coop_walk<M, S, true>(SP, walking, amax, row, pp, tl, wslot[wv], lane, wc.x, wc.y,
+                                  caplin, eps);
             finish_job<float, true>(SP, wc.x, wc.y, caplin, eps, J);
-            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? drow.at(J.jlo) : dj) * J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? drow.at(J.jhi) : dj) * J.xhi);
+            if (prev) {
+                walking = walking_q;
+                coop_walk<M, S, true>(SQ, walking, amax, row, pq, tl, wslot[wv], lane, wc.x,
+                                      wc.y, caplin, eps);
+                finish_job<float, true>(SQ, wc.x, wc.y, caplin, eps, K);
+            }
+        }
+        if (i < n) {
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? dtl[lane * S + J.jlo] : dj) * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? dtl[lane * S + J.jhi] : dj) * J.xhi);
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
-                Job<float> K;
-                const Seg<float> SQ = walk_job<float, M, true>(
-                    row, M, job_prices(ArgPrices<M, true>{pk, qtab}), wc.x, wc.y, caplin, eps,
-                    freeq);
-                finish_job<float, true>(SQ, wc.x, wc.y, caplin, eps, K);
                 float u, loss;
                 scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab, sctab,
                                u, loss);
