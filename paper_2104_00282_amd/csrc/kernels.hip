@@ -673,7 +673,7 @@ struct GlobalRow {
 // The price block is the first kernel argument, so it starts the argument
 // segment (the AMDGPU kernel ABI lays arguments out in order from offset 0).
 template <int M, bool DEM, bool DV>
-__global__ void __launch_bounds__(256, 2) k_dual_vec(
+__global__ void __launch_bounds__(256, DV ? 1 : 2) k_dual_vec(
     const PriceArgs<M> pa, const float* __restrict__ T, const float2* __restrict__ prm, int64_t n,
     float eps, double* __restrict__ partial,
     int* __restrict__ jpair, float2* __restrict__ xpair, float2* __restrict__ tpair,
@@ -811,21 +811,47 @@ __global__ void __launch_bounds__(256, 2) k_dual_vec(
         asm volatile("" : "+s"(pk));
         Job<float> J, K;
         if constexpr (DV) {
-            // demand vectors: each job walks its own envelope at d_i * p
+            // demand vectors: each job walks its own envelope at d_i * p; the
+            // usage and value at p are taken before the walk at q, which keeps
+            // fewer values live (the demand row then stays in registers)
             if (i < n) {
-                const LdsRow drow{dtl + lane * S};
+                // the job's demand row in registers for the unrolled scans
+                // (per-lane indices read the staged tile)
+                RegRow<M> drow;
+                drow.lds = dtl + lane * S;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const float4 v = *reinterpret_cast<const float4*>(drow.lds + 4 * q);
+                    drow.v[4 * q + 0] = v.x;
+                    drow.v[4 * q + 1] = v.y;
+                    drow.v[4 * q + 2] = v.z;
+                    drow.v[4 * q + 3] = v.w;
+                }
                 using PA = ArgPrices<M, false>;
                 using PB = ArgPrices<M, true>;
-                const DemandPrices<float, PA, LdsRow> pp{PA{pk, ptab}, drow};
+                const DemandPrices<float, PA, RegRow<M>> pp{PA{pk, ptab}, drow};
                 finish_job<float, true>(
                     walk_job<float, M, true>(row, M, pp, wc.x, wc.y, caplin, eps, freep), wc.x,
                     wc.y, caplin, eps, J);
+                if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], drow.at(J.jlo) * J.xlo);
+                if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], drow.at(J.jhi) * J.xhi);
+                vacc += (double)J.v;
                 if (prev) {
-                    const DemandPrices<float, PB, LdsRow> pq{PB{pk, qtab}, drow};
+                    const DemandPrices<float, PB, RegRow<M>> pq{PB{pk, qtab}, drow};
                     finish_job<float, true>(
                         walk_job<float, M, true>(row, M, pq, wc.x, wc.y, caplin, eps, freeq),
                         wc.x, wc.y, caplin, eps, K);
+                    float u, loss;
+                    scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, stab,
+                                   sctab, u, loss);
+                    uacc += (double)u;
+                    duacc += (double)loss;
                 }
+                pend_i = i;
+                pend_jp = (J.jlo & 0xffff) | (J.jhi << 16);
+                pend_x = make_float2(J.xlo, J.xhi);
+                pend_t = make_float2(J.tlo, J.thi);
+                pend_j1 = (int16_t)J.j1;
             }
         } else {
             // every lane takes part (rows past n are zero: nothing to buy),
@@ -880,9 +906,9 @@ __global__ void __launch_bounds__(256, 2) k_dual_vec(
                 finish_job<float, true>(SQ, wc.x, wc.y, caplin, eps, K);
             }
         }
-        if (i < n) {
-            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], (DV ? dtl[lane * S + J.jlo] : dj) * J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], (DV ? dtl[lane * S + J.jhi] : dj) * J.xhi);
+        if (!DV && i < n) {
+            if (J.jlo >= 0) atomicAdd(&hist[wv][J.jlo], dj * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[wv][J.jhi], dj * J.xhi);
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 float u, loss;
