@@ -133,6 +133,7 @@ def batched_vs_loop(args):
     ent = sum(I.n * I.m for I in insts)
     log("reference run for the gap floors (%d iterations)" % args.floor_iters)
     _, ref, _ = ra.batch_solve(probs, tol_rel=0.0, max_iter=args.floor_iters)
+    tune = ctx.batch_tuning()  # the launch shape was tuned on the reference run's first prices
     floors = np.array([r["rel_gap"] for r in ref])
     targets = np.maximum(1e-6, 1.5 * floors)
     max_iter = 2 * args.floor_iters
@@ -181,6 +182,7 @@ def batched_vs_loop(args):
         "floor_median": float(np.median(floors)),
         "floor_max": float(floors.max()),
         "targets_at_1e-6": int((targets <= 1e-6).sum()),
+        "launch_shape": tune.get("chosen"),
     }
     for pr in probs:
         pr.close()
@@ -497,7 +499,8 @@ def bench_batch_rounds(args):
             keep.append(ts)
             probs.append(ra.Problem(ctx, ts[0], ts[1], ts[2], ts[3], I.R, I.eps, validate=False))
         torch.cuda.synchronize()
-        ra.batch_solve(probs, tol_rel=0.0, max_iter=3, max_evals=3)
+        ra.batch_solve(probs, tol_rel=0.0, max_iter=3, max_evals=3)  # tunes the launch shape
+        tune = ctx.batch_tuning()
         best = None
         for _ in range(3):
             torch.cuda.synchronize()
@@ -508,8 +511,12 @@ def bench_batch_rounds(args):
             best = t if best is None else min(best, t)
         nbytes = sum(I.n * I.m * 4 + I.n * 8 for I in insts)
         rows["m=" + "/".join(str(m) for m in ms)] = {"ms_per_round": best * 1e3, "bytes": nbytes,
-                                                      "TB/s": nbytes / best / 1e12}
-        log("%s: %s" % (ms, rows["m=" + "/".join(str(m) for m in ms)]))
+                                                      "TB/s": nbytes / best / 1e12,
+                                                      "shape": tune.get("chosen"),
+                                                      "tuning": tune.get("candidates")}
+        r = rows["m=" + "/".join(str(m) for m in ms)]
+        log("%s: %.3f ms per round, %.3f TB/s, shape %s" % (ms, r["ms_per_round"], r["TB/s"],
+                                                              r["shape"]))
         for pr in probs:
             pr.close()
         del keep

@@ -42,6 +42,7 @@
 #ifndef RESALLOC_H
 #define RESALLOC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -283,11 +284,18 @@ ra_status ra_get_allocation(ra_ctx *ctx, const ra_problem *prob, const double *p
 /* Batched price discovery: B problems of one context solved together.
  * Each problem runs its own price loop (as ra_solve, same options); every
  * round evaluates all problems still running in one persistent kernel launch
- * (problems laid end to end, each wavefront streaming a byte-balanced
- * contiguous share), replayed from one captured HIP graph per round.  The
- * launch's grid size is chosen by timing candidates on the first round of a
- * new batch shape (cached in the context, and in the text file named by the
- * environment variable RESALLOC_TUNE_CACHE when it is set).
+ * (problems laid end to end in tiles of consecutive jobs, each wavefront
+ * streaming a contiguous share of the tiles, the shares balanced by the
+ * measured cost per job of each m class), replayed from one captured HIP
+ * graph per round.  The launch shape (the tile height of each m class, the
+ * tile budget the kernel is compiled for, blocks per compute unit) is chosen
+ * by an autotuner that times candidate rounds at the first prices of a new
+ * batch signature (number of problems, MiB of T, m classes, kernel variant);
+ * its choice is cached in the context, and in the text file named by the
+ * environment variable RESALLOC_TUNE_CACHE when it is set, and
+ * ra_batch_tuning returns the times of its candidates.  ra_batch_set_shape
+ * fixes a shape instead.  Results do not depend on the shape beyond the
+ * order of floating-point sums.
  *   B         number of problems (>= 1)
  *   probs     host, B problem handles created on ctx; each FP32 with m in
  *             {4, 8, 16, 32} and T 16-byte aligned, else RA_EUNSUPPORTED
@@ -302,6 +310,29 @@ ra_status ra_get_allocation(ra_ctx *ctx, const ra_problem *prob, const double *p
 ra_status ra_batch_solve(ra_ctx *ctx, int32_t B, ra_problem *const *probs,
                          const ra_solve_opts *opts, const double *tol_each, double *p_inout,
                          ra_solve_info *infos);
+
+/* Fix the launch shape of later ra_batch_solve calls on ctx (callers that
+ * want the same shape, and so the same summation order, in every process):
+ *   tile_floats    1024, 2048 or 4096: floats of T a wavefront holds per
+ *                  tile (the register budget of the kernel variant); 0
+ *                  returns to the autotuner (rows and blocks_per_cu ignored)
+ *   rows           host, 4 tile heights for m = 4, 8, 16, 32: each 0 (no
+ *                  problems of that class allowed) or a multiple of 64, at
+ *                  most 512, with rows[c] * m <= tile_floats
+ *   blocks_per_cu  0 (as many as fit) .. 8
+ * A batch with a class whose height is 0 fails with RA_EINVAL.  Errors:
+ * RA_EINVAL. */
+ra_status ra_batch_set_shape(ra_ctx *ctx, int32_t tile_floats, const int32_t *rows,
+                             int32_t blocks_per_cu);
+
+/* The autotuner's record of its last tuning on ctx, as JSON text:
+ * {"signature": ..., "candidates": [{"tile_floats", "m" (0 = the whole
+ * batch), "rows", "bpc", "ms"}, ...], "chosen": {"tile_floats", "rows",
+ * "bpc", "ms", "cost_ns_per_job"}}; "" before any tuning.  *len (if len is
+ * not NULL) gets its length without the terminating zero; with buf not NULL
+ * the text and a zero are copied to buf, which needs cap >= *len + 1 bytes
+ * (else RA_EINVAL, nothing copied). */
+ra_status ra_batch_tuning(const ra_ctx *ctx, char *buf, size_t cap, size_t *len);
 
 /* ---- Learned warm start (not in the paper; the paper's own starting point
  * is p = 1 or a data-dependent heuristic, §5 "Initialization"). ----------

@@ -20,14 +20,15 @@ from ._capi import (RA_EDEVICE, RA_EINVAL, RA_ENOMEM, RA_ENOTCONV, RA_ENUMERIC, 
                     ra_destroy, ra_dual_eval, ra_get_allocation, ra_last_error, ra_problem_create,
                     ra_problem_destroy, ra_solve, ra_solve_info, ra_solve_opts,
                     ra_solve_opts_default, ra_status_string, ra_set_kernel_timing,
-                    ra_get_kernel_timing, ra_batch_solve, ra_stream_read_ms)
+                    ra_get_kernel_timing, ra_batch_solve, ra_stream_read_ms,
+                    ra_batch_set_shape, ra_batch_tuning)
 
 __all__ = [
     "Context", "Problem", "RAError", "ra_create", "ra_destroy", "ra_status_string",
     "ra_last_error", "ra_problem_create", "ra_problem_destroy", "ra_dual_eval",
     "ra_solve_opts_default", "ra_solve", "ra_get_allocation", "ra_solve_opts", "ra_solve_info",
     "ra_set_kernel_timing", "ra_get_kernel_timing", "ra_batch_solve", "batch_solve", "MLP",
-    "ra_stream_read_ms",
+    "ra_stream_read_ms", "ra_batch_set_shape", "ra_batch_tuning",
 ]
 
 
@@ -64,6 +65,16 @@ class Context:
         self.device = device
         self.handle = ra_create(device, None)
         _LIVE.add(self)
+
+    def set_batch_shape(self, tile_floats, rows=(0, 0, 0, 0), blocks_per_cu=0):
+        """Fix the batched launch shape (tile_floats 0: back to the autotuner)."""
+        ra_batch_set_shape(self.handle, tile_floats, rows, blocks_per_cu)
+
+    def batch_tuning(self):
+        """The autotuner's record of its last tuning (dict; {} if none)."""
+        import json
+        txt = ra_batch_tuning(self.handle)
+        return json.loads(txt) if txt else {}
 
     def close(self):
         if self.handle:

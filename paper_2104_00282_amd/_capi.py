@@ -64,6 +64,9 @@ PROTOTYPES = {
     "ra_get_allocation": (_st, [_vp, _vp, _vp, _vp]),
     "ra_batch_solve": (_st, [_vp, _i32, _vp, ctypes.POINTER(ra_solve_opts), _vp, _vp,
                              _vp]),
+    "ra_batch_set_shape": (_st, [_vp, _i32, ctypes.POINTER(_i32), _i32]),
+    "ra_batch_tuning": (_st, [_vp, ctypes.c_char_p, ctypes.c_size_t,
+                              ctypes.POINTER(ctypes.c_size_t)]),
     "ra_features": (_st, [_vp, _vp, _vp]),
     "ra_predict_prices": (_st, [_vp, _vp, _vp, _vp]),
     "ra_init_prices": (_st, [_vp, _vp, _vp]),
@@ -208,6 +211,28 @@ def ra_batch_solve(ctx, B, probs, opts, tol_each, p_inout, infos):
     if st not in (RA_OK, RA_ENOTCONV):
         raise RAError(st, ra_last_error(ctx))
     return st
+
+
+def ra_batch_set_shape(ctx, tile_floats, rows=(0, 0, 0, 0), blocks_per_cu=0):
+    """Fix the batched launch shape (tile_floats 0: back to the autotuner)."""
+    arr = (_i32 * 4)(*[int(r) for r in rows])
+    st = lib().ra_batch_set_shape(ctx, int(tile_floats), arr, int(blocks_per_cu))
+    if st != RA_OK:
+        raise RAError(st, ra_last_error(ctx))
+    return st
+
+
+def ra_batch_tuning(ctx):
+    """The autotuner's JSON record of its last tuning on ctx ("" if none)."""
+    n = ctypes.c_size_t()
+    st = lib().ra_batch_tuning(ctx, None, 0, ctypes.byref(n))
+    if st != RA_OK:
+        raise RAError(st, ra_last_error(ctx))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    st = lib().ra_batch_tuning(ctx, buf, n.value + 1, ctypes.byref(n))
+    if st != RA_OK:
+        raise RAError(st, ra_last_error(ctx))
+    return buf.value.decode()
 
 
 def check(ctx, st, allow=(RA_OK,)):

@@ -1062,68 +1062,126 @@ __global__ void __launch_bounds__(256) k_dual_gen(
 
 // ------------------------------------------------------------------------
 // Batched dual kernel: many FP32 problems with m in {4, 8, 16, 32} evaluated
-// in one persistent launch per price iteration.  A batched tile is 8 KiB of
-// T whatever m (batch_rows(m) = 2048/m rows: 512 at m = 4, 64 at m = 32,
-// i.e. 32/m jobs per lane), so every wave streams the same bytes per step.
-// The host lays the active problems' tiles end to end and gives each
-// wavefront a contiguous chunk of that tile space, balanced by bytes.  The
-// next tile (possibly of the next problem) is loaded into registers while
-// the current one is solved from LDS.  A wave keeps FP64 accumulators for
-// the problem it is in and writes them to its next partial slot whenever it
-// crosses into another problem, so the slots of one problem are contiguous
-// and are summed in a fixed order by k_batch_reduce.
+// in one persistent launch per price iteration.  A batched tile is `rows`
+// consecutive jobs of one problem (BatchShape: a multiple of 64 per m class,
+// at most TF floats of T; TF is the register budget the kernel is compiled
+// for), so a lane solves rows / 64 jobs of a tile, one per 64-row step.  The
+// host lays the active problems' tiles end to end and gives each wavefront a
+// contiguous chunk of that tile space, balanced by the measured cost of each
+// m class.  The next tile (possibly of the next problem) is loaded into
+// registers while the current one is solved from LDS.  Each 64-row step
+// solves its jobs as the vectorised kernel does: first vertices from the
+// row in registers, then envelope walks shared by the wavefront.  A wave
+// keeps FP64 accumulators for the problem it is in and writes them to its
+// next partial slot whenever it crosses into another problem, so the slots
+// of one problem are contiguous and are summed in a fixed order by
+// k_batch_reduce.
 // ------------------------------------------------------------------------
-constexpr int BATCH_LDS_WAVE = 3072;  // max over m of batch_rows(m) x padded stride (m = 8)
 
-template <int M, bool AF>
+// The prices of one problem of a batch: wave-uniform reads of the price rows
+// in global memory (scalar loads), per-lane reads from the wave's LDS copy.
+struct BatchPrices {
+    const float* __restrict__ P;
+    const float* __restrict__ IP;
+    const float* tab;
+    __device__ __forceinline__ float get(int j) const { return P[j]; }
+    __device__ __forceinline__ float inv(int j) const { return IP[j]; }
+    __device__ __forceinline__ float at(int j) const { return tab[j]; }
+};
+
+// Minimum resident blocks per compute unit the batched kernel is compiled
+// for (its register budget): the larger the tile, the more registers the
+// prefetched tile holds.
+constexpr int batch_min_blocks(int tf, bool dem) { return tf <= 1024 ? (dem ? 3 : 4) : tf <= 2048 ? (dem ? 2 : 3) : 2; }
+
+// One staged tile of problem `it` (rows valid rows of height tr, at tl with
+// row stride batch_stride(M)): every job solved at the problem's prices P
+// and, with prev, at its previous prices Q (certificate); usage into the
+// wave's LDS histogram, then into the lane's FP64 accumulators.
+template <int M, int JPL, bool DEM, bool AF>
 __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, const float* tl,
-                                              const float2 (&wc)[8], const float (&dm)[8],
-                                              float* hist,
-                                              const float* __restrict__ P,
-                                              const float* __restrict__ IP,
-                                              const float* __restrict__ Qp,
-                                              const float* __restrict__ IQ, const float* ptab,
-                                              const float* qtab, const float* stab,
+                                              const float2* wcl, const float* dml, float* hist, int* slots, const BatchPrices& pp,
+                                              const BatchPrices& pq, const float* stab,
                                               const float* sctab, bool prev, bool freep,
                                               bool freeq, int lane, double& racc, double& vacc,
                                               double& uacc, double& duacc)
 {
     constexpr int Q = M / 4;
     constexpr int S = M + ((Q & 1) ? 0 : 4);
-    constexpr int JPL = BATCH_TILE_FLOATS / M / 64;  // jobs per lane
-    static_assert(JPL >= 1 && JPL <= 8, "batched tile shape");
-    static_assert((BATCH_TILE_FLOATS / M) * S <= BATCH_LDS_WAVE, "batched LDS tile");
     const float eps = it.eps;
 #pragma unroll
     for (int k = 0; k < JPL; ++k) {
+        if (64 * k >= rows) break;  // wave-uniform
         const int r = 64 * k + lane;
-        if (r < rows) {
-            RegRow<M> row;
-            row.lds = tl + r * S;
+        const float* sub = tl + 64 * k * S;  // this step's 64 rows
+        RegRow<M> row;
+        row.lds = sub + lane * S;
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
-                row.v[4 * q + 0] = v.x;
-                row.v[4 * q + 1] = v.y;
-                row.v[4 * q + 2] = v.z;
-                row.v[4 * q + 3] = v.w;
+        for (int q = 0; q < Q; ++q) {
+            const float4 v = *reinterpret_cast<const float4*>(row.lds + 4 * q);
+            row.v[4 * q + 0] = v.x;
+            row.v[4 * q + 1] = v.y;
+            row.v[4 * q + 2] = v.z;
+            row.v[4 * q + 3] = v.w;
+        }
+        // rows past the problem's end are zero (nothing to buy) and never summed
+        const float2 wck = wcl[r];
+        const float dmk = DEM ? dml[r] : 1.f;
+        const float w = wck.x, c = wck.y;
+        const bool caplin = is_capped(c);
+        float amax = INFINITY;
+        bool have_max = false;
+        auto row_max = [&](bool on) {
+            if (!have_max && __ballot(on) != 0ull) {
+                amax = 0.f;
+#pragma unroll
+                for (int j = 0; j < M; ++j) amax = fmaxf(amax, row.get(j));
+                have_max = true;
             }
-            const bool caplin = is_capped(wc[k].y);
-            Job<float> J;
-            solve_job<float, M, AF>(row, M, SharedPrices<float>{P, IP, ptab}, wc[k].x, wc[k].y,
-                                    caplin, eps, freep, J);
-            if (J.jlo >= 0) atomicAdd(&hist[J.jlo], dm[k] * J.xlo);
-            if (J.jhi >= 0) atomicAdd(&hist[J.jhi], dm[k] * J.xhi);
-            vacc += (double)J.v * (double)dm[k];
-            if (prev) {
-                Job<float> K;
-                solve_job<float, M, AF>(row, M, SharedPrices<float>{Qp, IQ, qtab}, wc[k].x,
-                                        wc[k].y, caplin, eps, freeq, K);
+        };
+        bool walking, walking_q = false;
+        Seg<float> SP, SQ;
+        if (freep) {
+            SP = free_start<M, AF>(row, pp, w, c, caplin, eps, amax, walking);
+            have_max = true;
+        } else {
+            SP = first_segment<AF>(row, pp, scan_first<float, M, false>(row, M, pp), amax, w, c,
+                                   caplin, eps, walking);
+            row_max(walking);
+            walking = walking & (SP.ahi < amax);
+        }
+        if (prev) {
+            if (freeq) {
+                float amq;
+                SQ = free_start<M, AF>(row, pq, w, c, caplin, eps, amq, walking_q);
+                amax = amq;
+                have_max = true;
+            } else {
+                SQ = first_segment<AF>(row, pq, scan_first<float, M, false>(row, M, pq), amax, w,
+                                       c, caplin, eps, walking_q);
+                row_max(walking_q);
+                walking_q = walking_q & (SQ.ahi < amax);
+            }
+        }
+        coop_walk<M, S, AF>(SP, walking, amax, row, pp, sub, slots, lane, w, c, caplin, eps);
+        Job<float> J;
+        finish_job<float, AF>(SP, w, c, caplin, eps, J);
+        if (r < rows) {
+            if (J.jlo >= 0) atomicAdd(&hist[J.jlo], dmk * J.xlo);
+            if (J.jhi >= 0) atomicAdd(&hist[J.jhi], dmk * J.xhi);
+            vacc += (double)J.v * (double)dmk;
+        }
+        if (prev) {
+            walking = walking_q;
+            coop_walk<M, S, AF>(SQ, walking, amax, row, pq, sub, slots, lane, w, c, caplin, eps);
+            Job<float> K;
+            finish_job<float, AF>(SQ, w, c, caplin, eps, K);
+            if (r < rows) {
                 float u, loss;
-                scaled_utility<float, AF>(caplin, wc[k].x, wc[k].y, eps, K.jlo, K.jhi, K.tlo,
-                                          K.thi, stab, sctab, u, loss);
-                uacc += (double)u * (double)dm[k];
-                duacc += (double)loss * (double)dm[k];
+                scaled_utility<float, AF>(caplin, w, c, eps, K.jlo, K.jhi, K.tlo, K.thi, stab,
+                                          sctab, u, loss);
+                uacc += (double)u * (double)dmk;
+                duacc += (double)loss * (double)dmk;
             }
         }
     }
@@ -1135,16 +1193,21 @@ __device__ __forceinline__ void batch_compute(const BatchItem& it, int rows, con
     wave_sync();
 }
 
-template <bool DEM, bool AF>
-__global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem* __restrict__ items,
-                                                    const float* __restrict__ prices,
-                                                    const int* __restrict__ chunk,
-                                                    const int* __restrict__ segbase,
-                                                    double* __restrict__ partial)
+// lds_floats: LDS floats per wave (dynamic shared memory, four waves per
+// block) for a staged tile: rows x batch_stride(m) floats of T, then the
+// (w, c) pairs of its rows, then (DEM) their demands.
+template <bool DEM, bool AF, int TF>
+__global__ void __launch_bounds__(256, batch_min_blocks(TF, DEM))
+    k_dual_batch(const BatchItem* __restrict__ items, const float* __restrict__ prices,
+                 const int* __restrict__ chunk, const int* __restrict__ segbase,
+                 double* __restrict__ partial, int lds_floats)
 {
-    __shared__ __attribute__((aligned(16))) float tile[4][BATCH_LDS_WAVE];
+    constexpr int V = TF / 256;                                      // float4 per lane of a tile
+    constexpr int JPL = TF / 256 < BATCH_MAX_JPL ? TF / 256 : BATCH_MAX_JPL;  // jobs per lane
+    extern __shared__ __attribute__((aligned(16))) float batch_tiles[];
     __shared__ float hist[4][BATCH_MAX_M];
-    __shared__ float tabs[4][4][BATCH_MAX_M];
+    __shared__ __attribute__((aligned(16))) float tabs[4][4][BATCH_MAX_M];
+    __shared__ int wslot[4][64];
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: saying so keeps the tile bookkeeping, the
     // problem records and the price reads in scalar registers and scalar
@@ -1152,49 +1215,49 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int w = blockIdx.x * 4 + wv;
     const int t0 = chunk[w], t1 = chunk[w + 1];
-    float* tl = tile[wv];
+    float* tl = batch_tiles + wv * lds_floats;
     float* hs = hist[wv];
     if (lane < BATCH_MAX_M) hs[lane] = 0.f;
     wave_sync();
     if (t0 >= t1) return;
 
-    // the tile in flight: 8 KiB of T (512 float4, 8 per lane) and the (w, c)
-    // of up to 8 jobs per lane; `an` is the problem of the last tile loaded
-    // (items[A].tile0 is the total tile count, so the scans stop)
-    float4 pre[8];
-    float2 wcn[8];
-    float dmn[8];
+    // the tile in flight: up to TF floats of T (V float4 per lane) and the
+    // (w, c) of up to JPL jobs per lane; `an` is the problem of the last tile
+    // loaded (items[A].tile0 is the total tile count, so the scans stop)
+    float4 pre[V];
+    float2 wcn[JPL];
+    float dmn[JPL];
     int an = 0, nrows = 0;
     auto load = [&](int t) {
         while (items[an + 1].tile0 <= t) ++an;
         const BatchItem& nx = items[an];
         const int m = nx.m;
-        const int tr = BATCH_TILE_FLOATS / m;
+        const int tr = nx.rows;
         const int64_t row0 = (int64_t)(t - nx.tile0) * tr;
         const int64_t left = nx.n - row0;
         const int rows = left < tr ? (int)left : tr;
         const float4* src = reinterpret_cast<const float4*>(nx.T + row0 * m);
         const int valid = rows * (m / 4);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < V; ++k) {
             const int ch = lane + 64 * k;
             pre[k] = (ch < valid) ? stream_load_global(src + ch) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < JPL; ++k) {
             const int r = 64 * k + lane;
             wcn[k] = (r < rows) ? load_global(nx.prm + row0 + r) : make_float2(1.f, -1.f);
         }
         if (DEM && nx.dem) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < JPL; ++k) {
                 const int r = 64 * k + lane;
                 dmn[k] = (r < rows) ? *(__attribute__((address_space(1))) const float*)(nx.dem + row0 + r)
                                     : 1.f;
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) dmn[k] = 1.f;
+            for (int k = 0; k < JPL; ++k) dmn[k] = 1.f;
         }
         nrows = rows;
     };
@@ -1203,7 +1266,7 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
     int cur = -1;
     bool freep = false, freeq = false;  // some price zero (see scan_first)
     BatchItem it;
-    const float *P = nullptr, *IP = nullptr, *Qp = nullptr, *IQ = nullptr;
+    BatchPrices pp{nullptr, nullptr, tabs[wv][0]}, pq{nullptr, nullptr, tabs[wv][1]};
     double racc = 0.0, vacc = 0.0, uacc = 0.0, duacc = 0.0;
     auto flush = [&]() {
         for (int off = 32; off > 0; off >>= 1) {
@@ -1231,10 +1294,10 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
             cur = a;
             it = items[a];
             const float* pr = prices + (int64_t)a * 6 * BATCH_MAX_M;
-            P = pr;
-            IP = pr + BATCH_MAX_M;
-            Qp = pr + 2 * BATCH_MAX_M;
-            IQ = pr + 3 * BATCH_MAX_M;
+            pp.P = pr;
+            pp.IP = pr + BATCH_MAX_M;
+            pq.P = pr + 2 * BATCH_MAX_M;
+            pq.IP = pr + 3 * BATCH_MAX_M;
             freep = __ballot(lane < it.m && pr[lane] == 0.f) != 0ull;
             freeq = __ballot(lane < it.m && pr[2 * BATCH_MAX_M + lane] == 0.f) != 0ull;
             if (lane < it.m) {
@@ -1244,48 +1307,51 @@ __global__ void __launch_bounds__(256, DEM ? 2 : 3) k_dual_batch(const BatchItem
                 tabs[wv][3][lane] = pr[5 * BATCH_MAX_M + lane];
             }
         }
-        // stage the tile in LDS: chunk ch of 16 bytes is row ch / Q, quad ch % Q
+        // stage the tile in LDS: chunk ch of 16 bytes is row ch / Q, quad
+        // ch % Q; the whole tile height is written, so rows past the
+        // problem's end are zero
         const int m = it.m;
         const int Q = m >> 2;
         const int lq = m == 4 ? 0 : m == 8 ? 1 : m == 16 ? 2 : 3;
-        const int S = m + ((Q & 1) ? 0 : 4);
-        const int valid = rows * Q;
+        const int S = batch_stride(m);
+        const int height = it.rows * Q;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < V; ++k) {
             const int ch = lane + 64 * k;
-            if (ch < valid)
+            if (ch < height)
                 *reinterpret_cast<float4*>(tl + (ch >> lq) * S + 4 * (ch & (Q - 1))) = pre[k];
         }
-        float2 wc[8];
-        float dm[8];
+        float2* wcl = reinterpret_cast<float2*>(tl + it.rows * S);
+        float* dml = tl + it.rows * (S + 2);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            wc[k] = wcn[k];
-            dm[k] = dmn[k];
+        for (int k = 0; k < JPL; ++k) {
+            if (64 * k < it.rows) {
+                wcl[64 * k + lane] = wcn[k];
+                if (DEM) dml[64 * k + lane] = dmn[k];
+            }
         }
         wave_sync();
         if (t + 1 < t1) load(t + 1);
         const bool prev = it.has_prev != 0;
-        const float* pt = tabs[wv][0];
-        const float* qt = tabs[wv][1];
         const float* st = tabs[wv][2];
         const float* sct = tabs[wv][3];
+        int* sl = wslot[wv];
         switch (m) {
         case 4:
-            batch_compute<4, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane, racc,
-                             vacc, uacc, duacc);
+            batch_compute<4, JPL, DEM, AF>(it, rows, tl, wcl, dml, hs, sl, pp, pq, st, sct, prev, freep,
+                                      freeq, lane, racc, vacc, uacc, duacc);
             break;
         case 8:
-            batch_compute<8, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane, racc,
-                             vacc, uacc, duacc);
+            batch_compute<8, JPL, DEM, AF>(it, rows, tl, wcl, dml, hs, sl, pp, pq, st, sct, prev, freep,
+                                      freeq, lane, racc, vacc, uacc, duacc);
             break;
         case 16:
-            batch_compute<16, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane,
-                              racc, vacc, uacc, duacc);
+            batch_compute<16, JPL, DEM, AF>(it, rows, tl, wcl, dml, hs, sl, pp, pq, st, sct, prev, freep,
+                                       freeq, lane, racc, vacc, uacc, duacc);
             break;
         default:
-            batch_compute<32, AF>(it, rows, tl, wc, dm, hs, P, IP, Qp, IQ, pt, qt, st, sct, prev, freep, freeq, lane,
-                              racc, vacc, uacc, duacc);
+            batch_compute<32, JPL, DEM, AF>(it, rows, tl, wcl, dml, hs, sl, pp, pq, st, sct, prev, freep,
+                                       freeq, lane, racc, vacc, uacc, duacc);
             break;
         }
     }
@@ -1828,26 +1894,65 @@ hipError_t launch_init(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu()
+template <bool DEM, bool AF, int TF>
+static int batch_occupancy(int lds_floats)
 {
-    static int occ = 0;
-    if (occ == 0) occ = occupancy_blocks(k_dual_batch<false, false>);
-    return occ;
+    int nb = 0;
+    const size_t lds = sizeof(float) * 4 * (size_t)lds_floats;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dual_batch<DEM, AF, TF>, 256, lds) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
 }
 
-hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
-                        const float* prices, const int* chunk, const int* segbase,
-                        const int* seg, const int* header, double* partial, double* out,
-                        unsigned* ticket, unsigned* flag, bool demands, bool alpha_fair)
+template <bool DEM, bool AF>
+static int batch_occupancy_tf(int tf, int lds_floats)
+{
+    return tf <= 1024   ? batch_occupancy<DEM, AF, 1024>(lds_floats)
+           : tf <= 2048 ? batch_occupancy<DEM, AF, 2048>(lds_floats)
+                        : batch_occupancy<DEM, AF, 4096>(lds_floats);
+}
+
+int batch_blocks_per_cu(int tf, bool demands, bool alpha_fair, int lds_floats)
+{
+    if (demands && alpha_fair) return batch_occupancy_tf<true, true>(tf, lds_floats);
+    if (demands) return batch_occupancy_tf<true, false>(tf, lds_floats);
+    if (alpha_fair) return batch_occupancy_tf<false, true>(tf, lds_floats);
+    return batch_occupancy_tf<false, false>(tf, lds_floats);
+}
+
+template <bool DEM, bool AF>
+static void launch_batch_tf(int tf, int lds_floats, int grid, hipStream_t st,
+                            const BatchItem* items, const float* prices, const int* chunk,
+                            const int* segbase, double* partial)
+{
+    const size_t lds = sizeof(float) * 4 * (size_t)lds_floats;
+    if (tf <= 1024)
+        k_dual_batch<DEM, AF, 1024><<<grid, 256, lds, st>>>(items, prices, chunk, segbase, partial,
+                                                            lds_floats);
+    else if (tf <= 2048)
+        k_dual_batch<DEM, AF, 2048><<<grid, 256, lds, st>>>(items, prices, chunk, segbase, partial,
+                                                            lds_floats);
+    else
+        k_dual_batch<DEM, AF, 4096><<<grid, 256, lds, st>>>(items, prices, chunk, segbase, partial,
+                                                            lds_floats);
+}
+
+hipError_t launch_batch(int tf, int lds_floats, int grid, int max_items, hipStream_t st,
+                        const BatchItem* items, const float* prices, const int* chunk,
+                        const int* segbase, const int* seg, const int* header, double* partial,
+                        double* out, unsigned* ticket, unsigned* flag, bool demands,
+                        bool alpha_fair)
 {
     if (demands && alpha_fair)
-        k_dual_batch<true, true><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+        launch_batch_tf<true, true>(tf, lds_floats, grid, st, items, prices, chunk, segbase, partial);
     else if (demands)
-        k_dual_batch<true, false><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+        launch_batch_tf<true, false>(tf, lds_floats, grid, st, items, prices, chunk, segbase, partial);
     else if (alpha_fair)
-        k_dual_batch<false, true><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+        launch_batch_tf<false, true>(tf, lds_floats, grid, st, items, prices, chunk, segbase, partial);
     else
-        k_dual_batch<false, false><<<grid, 256, 0, st>>>(items, prices, chunk, segbase, partial);
+        launch_batch_tf<false, false>(tf, lds_floats, grid, st, items, prices, chunk, segbase, partial);
     const int rgrid = max_items < 256 ? max_items : 256;
     k_batch_reduce<<<rgrid, 256, 0, st>>>(partial, seg, header, out, ticket, flag);
     return hipGetLastError();

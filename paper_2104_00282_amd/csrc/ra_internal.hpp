@@ -13,6 +13,7 @@
 
 #include "dev_loop.hpp"
 #include "host_pool.hpp"
+#include "ra_kernels.h"
 #include "resalloc.h"
 
 struct ra_ctx {
@@ -29,7 +30,12 @@ struct ra_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
-    std::map<std::string, int> batch_tuned;  // batch shape -> blocks per CU
+    // batched solver: tuned launch shapes by batch signature, a shape fixed
+    // by the caller (ra_batch_set_shape), and the record of the last tuning
+    std::map<std::string, ra::BatchTuned> batch_tuned;
+    bool batch_fixed = false;
+    ra::BatchTuned batch_fixed_shape;
+    std::string batch_tune_log;
     std::unique_ptr<ra::HostPool> pool;      // host threads of the batched solver
 };
 

@@ -38,9 +38,34 @@ inline int partial_cols(int m) { return m + 3; }
 // items[n_active] is a sentinel whose tile0 is the total tile count.
 constexpr int BATCH_MAX_M = 32;
 constexpr int BATCH_COLS = BATCH_MAX_M + 3;  // r_j (padded), net utility, U(X~), loss
-// A batched tile is BATCH_TILE_FLOATS floats of T: batch_rows(m) jobs.
-constexpr int BATCH_TILE_FLOATS = 2048;
-__host__ __device__ inline int batch_rows(int m) { return BATCH_TILE_FLOATS / m; }
+// Launch shape of a batched evaluation.  A tile is `rows[c]` consecutive jobs
+// of one problem of m class c (m = 4, 8, 16, 32 for c = 0..3): a multiple of
+// 64 (one job per lane and step) up to 64 x BATCH_MAX_JPL, holding at most
+// `tile_floats` floats of T, the per-wave register budget the kernel is
+// compiled for (1024, 2048 or 4096; 1024 only without m = 32 problems).
+// Blocks have four waves; `bpc` blocks per compute unit.
+constexpr int BATCH_MAX_JPL = 8;
+struct BatchShape {
+    int tile_floats = 2048;
+    int rows[4] = {512, 256, 128, 64};
+    int bpc = 0;  // 0: the most that fit
+};
+__host__ __device__ inline int batch_class(int m) { return m == 4 ? 0 : m == 8 ? 1 : m == 16 ? 2 : 3; }
+// LDS row stride of a staged tile row of m floats (padded when m / 4 is even,
+// so 16-byte row reads are conflict-free)
+__host__ __device__ inline int batch_stride(int m) { return m + (((m >> 2) & 1) ? 0 : 4); }
+// True when `rows` is a valid tile height for m under the budget tf.
+inline bool batch_rows_ok(int tf, int m, int rows)
+{
+    return rows >= 64 && rows % 64 == 0 && rows <= 64 * BATCH_MAX_JPL && rows * m <= tf;
+}
+// A launch shape with the per-job cost of each m class it was measured at
+// (ns per job, for the cost-balanced split of the tile space; 0 = not
+// measured, the split then weighs 4 m + 8 bytes per job).
+struct BatchTuned {
+    BatchShape shape;
+    double cost[4] = {0.0, 0.0, 0.0, 0.0};
+};
 struct BatchItem {
     const float* T;      // n x m row-major, 16-byte aligned
     const float2* prm;   // packed (w, c) per job
@@ -50,20 +75,24 @@ struct BatchItem {
     float eps;
     int has_prev;        // the pass also certifies the problem's previous prices
     const float* dem;    // per-job demands, or NULL
+    int rows;            // jobs per tile (BatchShape::rows of its m class)
 };
 
 // Batched evaluation: k_dual_batch (grid blocks of 4 waves; wave w covers
 // tiles [chunk[w], chunk[w+1]) and writes partial slots from segbase[w]) and
 // k_batch_reduce (problem a sums slots seg[2a]..seg[2a+1] into out[a][*]).
 // prices: per item 6 x BATCH_MAX_M floats (p, 1/p, q, 1/q, s, 1 - s);
-// header[0] = number of active items.
-int batch_blocks_per_cu();
+// header[0] = number of active items.  lds_floats: LDS floats per wave for a
+// staged tile, the largest rows x batch_stride(m) over the batch's m classes.
+// Blocks of k_dual_batch compiled for tile budget tf that fit on one compute
+// unit with lds_floats per wave.
+int batch_blocks_per_cu(int tf, bool demands, bool alpha_fair, int lds_floats);
 // With flag (host, fine-grained) and ticket (device counter, zero between
 // launches), out is host memory and the launch ends by setting *flag = 1.
-hipError_t launch_batch(int grid, int max_items, hipStream_t st, const BatchItem* items,
-                        const float* prices, const int* chunk, const int* segbase,
-                        const int* seg, const int* header, double* partial, double* out,
-                        unsigned* ticket = nullptr, unsigned* flag = nullptr,
+hipError_t launch_batch(int tf, int lds_floats, int grid, int max_items, hipStream_t st,
+                        const BatchItem* items, const float* prices, const int* chunk,
+                        const int* segbase, const int* seg, const int* header, double* partial,
+                        double* out, unsigned* ticket = nullptr, unsigned* flag = nullptr,
                         bool demands = false, bool alpha_fair = true);
 
 // Number of blocks one dual-kernel launch uses for n jobs with m resources

@@ -1181,7 +1181,9 @@ struct BatchWs {
     unsigned* ticket = nullptr;  // device block counter of the reduction
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    int graph_grid = 0;
+    int graph_grid = 0, graph_tf = 0, graph_lds = 0;
+    // the launch shape of the next rounds
+    int tf = 2048, lds_floats = 0;
     ~BatchWs()
     {
         // launches that use these buffers must have finished
@@ -1249,30 +1251,58 @@ void for_problems(ra::HostPool* pool, int A, const std::function<void(int, int)>
         fn(0, A);
 }
 
+// LDS floats per wave of a tile of `rows` rows for m resources (T staged
+// with the padded stride, then (w, c) and, with demands, d per row), a
+// multiple of 4 so that every wave's tile stays 16-byte aligned.
+int batch_lds_floats(int m, int rows, bool demands)
+{
+    const int f = rows * (ra::batch_stride(m) + 2 + (demands ? 1 : 0));
+    return (f + 3) & ~3;
+}
+
+// Fill the tables of one round for the active problems `act` (ascending) with
+// W waves: items, prices (next point and, if any, the point to certify),
+// per-wave tile chunks balanced by cost (T.cost, ns per job of each m class,
+// else 4 m + 8 bytes per job), partial slots.  force_prev: every problem
+// also certifies (its next point, with unit scales): the tuner's rounds do
+// the work of a solver round.  Sets ws.tf and ws.lds_floats.  Returns the
+// tile count.
 int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
                    const std::vector<ra::PriceLoop>& loops, const std::vector<int>& act, int W,
-                   std::vector<std::vector<double>>& p_eval, ra::HostPool* pool)
+                   std::vector<std::vector<double>>& p_eval, ra::HostPool* pool,
+                   const ra::BatchTuned& T, bool force_prev = false)
 {
     const int A = (int)act.size();
     ra::BatchItem* it = ws.items();
     float* pr = ws.prices();
-    std::vector<int64_t> tiles(A), cost(A);
-    int64_t tt = 0, C = 0;
+    std::vector<int64_t> tiles(A);
+    std::vector<double> cost(A);
+    int64_t tt = 0;
+    double C = 0.0;
+    int lds = 4;
+    for (int a = 0; a < A; ++a) {
+        const int m = probs[act[a]]->m;
+        lds = std::max(lds, batch_lds_floats(m, T.shape.rows[ra::batch_class(m)], ws.demands));
+    }
+    ws.tf = T.shape.tile_floats;
+    ws.lds_floats = lds;
     // each problem's record and price rows (independent per problem)
     for_problems(pool, A, [&](int lo, int hi) {
     for (int a = lo; a < hi; ++a) {
         const ra_problem* P = probs[act[a]];
         const ra::PriceLoop& L = loops[act[a]];
-        const int tr = ra::batch_rows(P->m);
+        const int cls = ra::batch_class(P->m);
+        const int tr = T.shape.rows[cls];
         tiles[a] = (P->n + tr - 1) / tr;
-        cost[a] = (int64_t)tr * (4 * P->m + 8);  // bytes per tile
+        cost[a] = (double)tr * (T.cost[cls] > 0.0 ? T.cost[cls] : (double)(4 * P->m + 8));
         it[a].T = static_cast<const float*>(P->T);
         it[a].prm = static_cast<const float2*>(P->prm);
         it[a].n = P->n;
         it[a].m = P->m;
+        it[a].rows = tr;
         it[a].eps = (float)P->eps;
         const ra::Point* prev = L.pending();
-        it[a].has_prev = prev ? 1 : 0;
+        it[a].has_prev = (prev || force_prev) ? 1 : 0;
         it[a].dem = static_cast<const float*>(P->dem);
         float* row = pr + (size_t)a * 6 * ra::BATCH_MAX_M;
         const std::vector<double>& nx = L.next();
@@ -1290,6 +1320,11 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
                 row[4 * ra::BATCH_MAX_M + j] = over ? (float)(P->R[j] / prev->r[j]) : 1.0f;
                 row[5 * ra::BATCH_MAX_M + j] =
                     over ? (float)((prev->r[j] - P->R[j]) / prev->r[j]) : 0.0f;
+            } else if (force_prev) {
+                row[2 * ra::BATCH_MAX_M + j] = pf;
+                row[3 * ra::BATCH_MAX_M + j] = row[ra::BATCH_MAX_M + j];
+                row[4 * ra::BATCH_MAX_M + j] = 1.0f;
+                row[5 * ra::BATCH_MAX_M + j] = 0.0f;
             }
         }
     }
@@ -1298,24 +1333,24 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
     for (int a = 0; a < A; ++a) {
         it[a].tile0 = (int)tt;
         tt += tiles[a];
-        C += tiles[a] * cost[a];
+        C += (double)tiles[a] * cost[a];
     }
     it[A].tile0 = (int)tt;
     // wave w starts at the first tile whose cumulative cost reaches w C / W
     int* ch = ws.chunk();
     {
         int a = 0;
-        int64_t cc = 0;  // cost before problem a
+        double cc = 0.0;  // cost before problem a
         for (int w = 0; w <= W; ++w) {
-            const double target = (double)C * (double)w / (double)W;
-            while (a < A && (double)(cc + tiles[a] * cost[a]) <= target) {
-                cc += tiles[a] * cost[a];
+            const double target = C * (double)w / (double)W;
+            while (a < A && cc + (double)tiles[a] * cost[a] <= target) {
+                cc += (double)tiles[a] * cost[a];
                 ++a;
             }
             if (a >= A || w == W) {
                 ch[w] = (int)tt;
             } else {
-                int64_t k = (int64_t)std::ceil((target - (double)cc) / (double)cost[a]);
+                int64_t k = (int64_t)std::ceil((target - cc) / cost[a]);
                 k = std::min<int64_t>(std::max<int64_t>(k, 0), tiles[a]);
                 ch[w] = it[a].tile0 + (int)k;
             }
@@ -1348,7 +1383,7 @@ ra_status batch_enqueue(ra_ctx* ctx, BatchWs& ws, int grid)
 {
     hipStream_t st = ctx->stream;
     RA_HIP(ctx, hipMemcpyAsync(ws.dtab, ws.htab, ws.tab_bytes, hipMemcpyHostToDevice, st));
-    RA_HIP(ctx, ra::launch_batch(grid, ws.B, st,
+    RA_HIP(ctx, ra::launch_batch(ws.tf, ws.lds_floats, grid, ws.B, st,
                                  reinterpret_cast<const ra::BatchItem*>(ws.dtab + ws.off_items),
                                  reinterpret_cast<const float*>(ws.dtab + ws.off_prices),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_chunk),
@@ -1363,7 +1398,8 @@ ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
 {
     __atomic_store_n(ws.hflag, 0u, __ATOMIC_RELEASE);
     if (use_graph && !ctx->timing) {
-        if (!ws.gexec || ws.graph_grid != grid) {
+        if (!ws.gexec || ws.graph_grid != grid || ws.graph_tf != ws.tf ||
+            ws.graph_lds != ws.lds_floats) {
             if (ws.gexec) (void)hipGraphExecDestroy(ws.gexec);
             if (ws.graph) (void)hipGraphDestroy(ws.graph);
             ws.gexec = nullptr;
@@ -1385,6 +1421,8 @@ ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
             }
             ws.graph = g;
             ws.graph_grid = grid;
+            ws.graph_tf = ws.tf;
+            ws.graph_lds = ws.lds_floats;
         }
         RA_HIP(ctx, hipGraphLaunch(ws.gexec, ctx->stream));
     } else {
@@ -1394,31 +1432,54 @@ ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
     return wait_flag(ctx, ws.hflag);
 }
 
-std::string batch_signature(const std::vector<ra_problem*>& probs)
+std::string batch_signature(const std::vector<ra_problem*>& probs, bool demands, bool alpha_fair)
 {
-    // number of problems, total MiB of T (rounded), and the m histogram
+    // number of problems, total MiB of T (rounded), the m histogram and the
+    // kernel variant
     int64_t bytes = 0;
     int hist[4] = {0, 0, 0, 0};
     for (const ra_problem* P : probs) {
         bytes += P->n * (int64_t)P->m * 4;
-        hist[P->m == 4 ? 0 : P->m == 8 ? 1 : P->m == 16 ? 2 : 3]++;
+        hist[ra::batch_class(P->m)]++;
     }
-    char buf[128];
-    snprintf(buf, sizeof(buf), "B%zu_MiB%lld_m%d.%d.%d.%d", probs.size(),
-             (long long)(bytes >> 20), hist[0], hist[1], hist[2], hist[3]);
+    char buf[160];
+    snprintf(buf, sizeof(buf), "B%zu_MiB%lld_m%d.%d.%d.%d_d%d_a%d", probs.size(),
+             (long long)(bytes >> 20), hist[0], hist[1], hist[2], hist[3], demands ? 1 : 0,
+             alpha_fair ? 1 : 0);
     return buf;
 }
 
+const int kBatchMs[4] = {4, 8, 16, 32};
+
+// A shape is usable for a batch when every m class present has a valid tile
+// height under the shape's budget.
+bool shape_fits(const ra::BatchShape& sh, const bool (&have)[4])
+{
+    if (sh.tile_floats != 1024 && sh.tile_floats != 2048 && sh.tile_floats != 4096) return false;
+    for (int c = 0; c < 4; ++c)
+        if (have[c] && !ra::batch_rows_ok(sh.tile_floats, kBatchMs[c], sh.rows[c])) return false;
+    return true;
+}
+
+// The tuning cache file (RESALLOC_TUNE_CACHE): one line per batch signature,
+// "signature tile_floats rows4 rows8 rows16 rows32 blocks_per_cu cost4 cost8
+// cost16 cost32".  Lines that do not parse are skipped.
 void tune_cache_load(ra_ctx* ctx)
 {
     const char* path = std::getenv("RESALLOC_TUNE_CACHE");
     if (!path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    char key[160];
-    int v = 0;
-    while (std::fscanf(f, "%159s %d", key, &v) == 2)
-        if (v > 0) ctx->batch_tuned.emplace(key, v);
+    char line[512];
+    while (std::fgets(line, sizeof(line), f)) {
+        char key[200];
+        ra::BatchTuned t;
+        if (std::sscanf(line, "%199s %d %d %d %d %d %d %lf %lf %lf %lf", key, &t.shape.tile_floats,
+                        &t.shape.rows[0], &t.shape.rows[1], &t.shape.rows[2], &t.shape.rows[3],
+                        &t.shape.bpc, &t.cost[0], &t.cost[1], &t.cost[2], &t.cost[3]) == 11 &&
+            t.shape.bpc >= 1)
+            ctx->batch_tuned.emplace(key, t);
+    }
     std::fclose(f);
 }
 
@@ -1428,8 +1489,172 @@ void tune_cache_store(const ra_ctx* ctx)
     if (!path) return;
     FILE* f = std::fopen(path, "w");
     if (!f) return;
-    for (const auto& kv : ctx->batch_tuned) std::fprintf(f, "%s %d\n", kv.first.c_str(), kv.second);
+    for (const auto& kv : ctx->batch_tuned) {
+        const ra::BatchTuned& t = kv.second;
+        std::fprintf(f, "%s %d %d %d %d %d %d %.6g %.6g %.6g %.6g\n", kv.first.c_str(),
+                     t.shape.tile_floats, t.shape.rows[0], t.shape.rows[1], t.shape.rows[2],
+                     t.shape.rows[3], t.shape.bpc, t.cost[0], t.cost[1], t.cost[2], t.cost[3]);
+    }
     std::fclose(f);
+}
+
+// LDS floats per wave that a batch's tiles need under shape T.
+int batch_lds_of(const std::vector<ra_problem*>& P, const std::vector<int>& act,
+                 const ra::BatchTuned& T, bool demands)
+{
+    int lds = 4;
+    for (int b : act)
+        lds = std::max(lds, batch_lds_floats(P[b]->m, T.shape.rows[ra::batch_class(P[b]->m)],
+                                             demands));
+    return lds;
+}
+
+// Autotuner of the batched launch shape.  For each tile budget (1024 floats
+// only without m = 32 problems, 2048, 4096) and each m class present, one
+// round of that class's problems alone is timed per tile height (64, 128,
+// 256, 512 rows within the budget) at the most resident blocks; the fastest
+// height gives the class's cost per job.  Then one round of the whole batch,
+// its tiles split by those costs, is timed per blocks-per-CU count, and the
+// budget and block count of the fastest whole round are kept.  Rounds are
+// timed with HIP events (one warm-up launch, then the best of two), at the
+// batch's first prices, every problem also certifying so that a round does
+// a solver round's work.  The candidates and their times are recorded as
+// JSON in ctx->batch_tune_log.
+ra_status batch_tune(ra_ctx* ctx, BatchWs& ws, const std::vector<ra_problem*>& P,
+                     const std::vector<ra::PriceLoop>& loops,
+                     std::vector<std::vector<double>>& p_eval, ra::HostPool* pool,
+                     const std::string& sig, ra::BatchTuned& out)
+{
+    const int B = (int)P.size();
+    bool have[4] = {false, false, false, false};
+    std::vector<int> by[4];
+    int64_t jobs[4] = {0, 0, 0, 0};
+    for (int b = 0; b < B; ++b) {
+        const int c = ra::batch_class(P[b]->m);
+        have[c] = true;
+        by[c].push_back(b);
+        jobs[c] += P[b]->n;
+    }
+    std::vector<int> all(B);
+    for (int b = 0; b < B; ++b) all[b] = b;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RA_HIP(ctx, hipEventCreate(&e0));
+    RA_HIP(ctx, hipEventCreate(&e1));
+    std::string log = "{\"signature\": \"" + sig + "\", \"candidates\": [";
+    bool first_entry = true;
+    char buf[256];
+    ra_status st = RA_OK;
+    // time one round of problems `act` under shape T at bpc blocks per CU
+    auto time_round = [&](const std::vector<int>& act, const ra::BatchTuned& T, int bpc,
+                          float& ms_out) -> ra_status {
+        const int grid = ctx->cus * bpc;
+        batch_fill(ws, P, loops, act, grid * 4, p_eval, pool, T, true);
+        float best = INFINITY;
+        for (int rep = 0; rep < 3; ++rep) {
+            RA_HIP(ctx, hipEventRecord(e0, ctx->stream));
+            ra_status s = batch_enqueue(ctx, ws, grid);
+            if (s != RA_OK) return s;
+            RA_HIP(ctx, hipEventRecord(e1, ctx->stream));
+            RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+            float ms = 0.f;
+            RA_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) best = std::min(best, ms);
+        }
+        ms_out = best;
+        return RA_OK;
+    };
+    auto occ_of = [&](const ra::BatchTuned& T, const std::vector<int>& act) {
+        const int lds = batch_lds_of(P, act, T, ws.demands);
+        // a launch of more blocks than fit would queue its waves behind the
+        // first ones and leave their chunks for a second pass
+        return std::max(1, std::min(8, ra::batch_blocks_per_cu(T.shape.tile_floats, ws.demands,
+                                                               ws.alpha_fair, lds)));
+    };
+    float best_all = INFINITY;
+    const int tfs[3] = {1024, 2048, 4096};
+    for (int tf : tfs) {
+        if (tf == 1024 && have[3]) continue;
+        ra::BatchTuned T;
+        T.shape.tile_floats = tf;
+        for (int c = 0; c < 4; ++c) {
+            if (!have[c]) continue;
+            float best_c = INFINITY;
+            int rows_c = 64;
+            for (int rows = 64; rows <= 64 * ra::BATCH_MAX_JPL; rows *= 2) {
+                if (!ra::batch_rows_ok(tf, kBatchMs[c], rows)) continue;
+                ra::BatchTuned Tc = T;
+                Tc.shape.rows[c] = rows;
+                const int occ = occ_of(Tc, by[c]);
+                float ms = 0.f;
+                st = time_round(by[c], Tc, occ, ms);
+                if (st != RA_OK) break;
+                snprintf(buf, sizeof(buf),
+                         "%s{\"tile_floats\": %d, \"m\": %d, \"rows\": %d, \"bpc\": %d, "
+                         "\"ms\": %.5f}",
+                         first_entry ? "" : ", ", tf, kBatchMs[c], rows, occ, ms);
+                log += buf;
+                first_entry = false;
+                if (ms < best_c) {
+                    best_c = ms;
+                    rows_c = rows;
+                }
+            }
+            if (st != RA_OK) break;
+            T.shape.rows[c] = rows_c;
+            // a class's time per job is trusted when its round gave every
+            // wave at least a job per lane; smaller rounds mostly time the
+            // launch
+            const int occ = occ_of(T, by[c]);
+            if (jobs[c] >= (int64_t)64 * 4 * ctx->cus * occ)
+                T.cost[c] = 1e6 * (double)best_c / (double)jobs[c];
+        }
+        if (st != RA_OK) break;
+        {
+            // classes without a trusted time: their bytes per job at the
+            // measured classes' mean time per byte (all zero when none was
+            // measured: the split then weighs bytes)
+            double nspb = 0.0;
+            int k = 0;
+            for (int c = 0; c < 4; ++c)
+                if (T.cost[c] > 0.0) {
+                    nspb += T.cost[c] / (double)(4 * kBatchMs[c] + 8);
+                    ++k;
+                }
+            for (int c = 0; c < 4; ++c)
+                if (T.cost[c] <= 0.0 && k > 0) T.cost[c] = nspb / k * (double)(4 * kBatchMs[c] + 8);
+        }
+        const int occ = occ_of(T, all);
+        for (int bpc = 1; bpc <= occ; ++bpc) {
+            float ms = 0.f;
+            st = time_round(all, T, bpc, ms);
+            if (st != RA_OK) break;
+            snprintf(buf, sizeof(buf),
+                     "%s{\"tile_floats\": %d, \"m\": 0, \"rows\": [%d, %d, %d, %d], \"bpc\": %d, "
+                     "\"ms\": %.5f}",
+                     first_entry ? "" : ", ", tf, T.shape.rows[0], T.shape.rows[1],
+                     T.shape.rows[2], T.shape.rows[3], bpc, ms);
+            log += buf;
+            first_entry = false;
+            if (ms < best_all) {
+                best_all = ms;
+                out = T;
+                out.shape.bpc = bpc;
+            }
+        }
+        if (st != RA_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RA_OK) return st;
+    snprintf(buf, sizeof(buf),
+             "], \"chosen\": {\"tile_floats\": %d, \"rows\": [%d, %d, %d, %d], \"bpc\": %d, "
+             "\"ms\": %.5f, \"cost_ns_per_job\": [%.5g, %.5g, %.5g, %.5g]}}",
+             out.shape.tile_floats, out.shape.rows[0], out.shape.rows[1], out.shape.rows[2],
+             out.shape.rows[3], out.shape.bpc, best_all, out.cost[0], out.cost[1], out.cost[2],
+             out.cost[3]);
+    log += buf;
+    ctx->batch_tune_log = log;
+    return RA_OK;
 }
 
 }  // namespace
@@ -1464,12 +1689,18 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
             return fail(ctx, RA_EINVAL, "tol_each[%d] must be >= 0", b);
         off[b + 1] = off[b] + m;
     }
-    int64_t total_tiles = 0;
+    bool have[4] = {false, false, false, false};
+    int64_t total_rows = 0;
     for (int b = 0; b < B; ++b) {
-        const int tr = ra::batch_rows(P[b]->m);
-        total_tiles += (P[b]->n + tr - 1) / tr;
+        have[ra::batch_class(P[b]->m)] = true;
+        total_rows += P[b]->n + 63;
     }
-    if (total_tiles >= ((int64_t)1 << 31))
+    if (ctx->batch_fixed && !shape_fits(ctx->batch_fixed_shape.shape, have))
+        return fail(ctx, RA_EINVAL,
+                    "the launch shape fixed by ra_batch_set_shape has no valid tile for an m "
+                    "class of this batch");
+    // tiles have at least 64 rows
+    if (total_rows / 64 >= ((int64_t)1 << 31))
         return fail(ctx, RA_EUNSUPPORTED, "batch has too many tiles");
     RA_HIP(ctx, hipSetDevice(ctx->dev));
     const auto t0 = std::chrono::steady_clock::now();
@@ -1494,8 +1725,8 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
         loops.emplace_back(P[b]->m, P[b]->n, P[b]->R.data(), ob, p0.data());
     }
 
-    const int occ = std::max(1, ra::batch_blocks_per_cu());
-    const int Wmax = ctx->cus * occ * 4;
+    // enough waves for any launch shape (at most 8 blocks of 4 waves per CU)
+    const int Wmax = ctx->cus * 8 * 4;
     BatchWs ws;
     if (batch_alloc(ctx, ws, B, Wmax) != RA_OK) return RA_ENOMEM;
     for (int b = 0; b < B; ++b) {
@@ -1520,43 +1751,35 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     ra::HostPool* pool = ctx->pool.get();
     std::vector<char> bad;
 
-    // grid: tuned per batch shape (timing one round per candidate)
-    if (ctx->batch_tuned.empty()) tune_cache_load(ctx);
-    const std::string sig = batch_signature(P);
-    int bpc = 0;
-    auto found = ctx->batch_tuned.find(sig);
-    if (found != ctx->batch_tuned.end()) bpc = std::min(found->second, occ);
-
+    // launch shape: fixed by the caller, cached for this batch signature, or
+    // tuned now (timing candidate rounds at the first prices)
     std::vector<int> act;
     std::vector<std::vector<double>> p_eval(B);
-    if (bpc == 0) {
-        act.resize(B);
-        for (int b = 0; b < B; ++b) act[b] = b;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        RA_HIP(ctx, hipEventCreate(&e0));
-        RA_HIP(ctx, hipEventCreate(&e1));
-        float best_ms = INFINITY;
-        for (int c = 1; c <= occ; ++c) {
-            const int grid = ctx->cus * c;
-            batch_fill(ws, P, loops, act, grid * 4, p_eval, pool);
-            for (int rep = 0; rep < 2; ++rep) {  // first run warms up
-                RA_HIP(ctx, hipEventRecord(e0, ctx->stream));
-                ra_status s = batch_enqueue(ctx, ws, grid);
-                if (s != RA_OK) return s;
-                RA_HIP(ctx, hipEventRecord(e1, ctx->stream));
-                RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
-            }
-            float ms = 0.f;
-            RA_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) {
-                best_ms = ms;
-                bpc = c;
-            }
+    ra::BatchTuned tuned;
+    if (ctx->batch_fixed) {
+        tuned = ctx->batch_fixed_shape;
+    } else {
+        if (ctx->batch_tuned.empty()) tune_cache_load(ctx);
+        const std::string sig = batch_signature(P, ws.demands, ws.alpha_fair);
+        auto found = ctx->batch_tuned.find(sig);
+        if (found != ctx->batch_tuned.end() && shape_fits(found->second.shape, have)) {
+            tuned = found->second;
+        } else {
+            ra_status s = batch_tune(ctx, ws, P, loops, p_eval, pool, sig, tuned);
+            if (s != RA_OK) return s;
+            ctx->batch_tuned[sig] = tuned;
+            tune_cache_store(ctx);
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        ctx->batch_tuned[sig] = bpc;
-        tune_cache_store(ctx);
+    }
+    int bpc = tuned.shape.bpc;
+    {
+        std::vector<int> all(B);
+        for (int b = 0; b < B; ++b) all[b] = b;
+        const int lds = batch_lds_of(P, all, tuned, ws.demands);
+        const int occ = std::max(1, std::min(8, ra::batch_blocks_per_cu(tuned.shape.tile_floats,
+                                                                        ws.demands,
+                                                                        ws.alpha_fair, lds)));
+        bpc = bpc >= 1 ? std::min(bpc, occ) : occ;
     }
     const int grid = ctx->cus * bpc;
 
@@ -1565,7 +1788,7 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
         for (int b = 0; b < B; ++b)
             if (!loops[b].done()) act.push_back(b);
         if (act.empty()) break;
-        batch_fill(ws, P, loops, act, grid * 4, p_eval, pool);
+        batch_fill(ws, P, loops, act, grid * 4, p_eval, pool, tuned);
         ra_status s = batch_run(ctx, ws, grid, graph);
         if (s != RA_OK) return s;
         // every active problem's price loop takes its step (independent per
@@ -1615,4 +1838,45 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
         }
     }
     return all ? RA_OK : RA_ENOTCONV;
+}
+
+extern "C" ra_status ra_batch_set_shape(ra_ctx* ctx, int32_t tile_floats, const int32_t* rows,
+                                        int32_t blocks_per_cu)
+{
+    if (!ctx || ctx->closed) return RA_EINVAL;
+    if (tile_floats == 0) {
+        ctx->batch_fixed = false;
+        return RA_OK;
+    }
+    if (tile_floats != 1024 && tile_floats != 2048 && tile_floats != 4096)
+        return fail(ctx, RA_EINVAL, "tile_floats must be 0, 1024, 2048 or 4096");
+    if (!rows) return fail(ctx, RA_EINVAL, "rows is required");
+    if (blocks_per_cu < 0 || blocks_per_cu > 8)
+        return fail(ctx, RA_EINVAL, "blocks_per_cu must be in [0, 8]");
+    ra::BatchTuned t;
+    t.shape.tile_floats = tile_floats;
+    for (int c = 0; c < 4; ++c) {
+        const int m = 4 << c;
+        if (rows[c] != 0 && !ra::batch_rows_ok(tile_floats, m, rows[c]))
+            return fail(ctx, RA_EINVAL,
+                        "rows[%d] = %d: a tile of m = %d needs a multiple of 64 rows, at most "
+                        "%d, with rows * m <= tile_floats (or 0: no such problems)",
+                        c, rows[c], m, 64 * ra::BATCH_MAX_JPL);
+        t.shape.rows[c] = rows[c];
+    }
+    t.shape.bpc = blocks_per_cu;
+    ctx->batch_fixed_shape = t;
+    ctx->batch_fixed = true;
+    return RA_OK;
+}
+
+extern "C" ra_status ra_batch_tuning(const ra_ctx* ctx, char* buf, size_t cap, size_t* len)
+{
+    if (!ctx) return RA_EINVAL;
+    const std::string& s = ctx->batch_tune_log;
+    if (len) *len = s.size();
+    if (!buf) return RA_OK;
+    if (cap < s.size() + 1) return RA_EINVAL;
+    std::memcpy(buf, s.c_str(), s.size() + 1);
+    return RA_OK;
 }

@@ -69,6 +69,8 @@ def test_null_arguments_rejected_without_device(lib):
     assert L.ra_get_allocation(None, None, None, None) == ra.RA_EINVAL
     assert L.ra_set_kernel_timing(None, 1) == ra.RA_EINVAL
     assert L.ra_last_error(None) == b""
+    assert L.ra_batch_set_shape(None, 2048, None, 0) == ra.RA_EINVAL
+    assert L.ra_batch_tuning(None, None, 0, None) == ra.RA_EINVAL
 
 
 def test_create_without_gpu_reports_device_error():

@@ -158,3 +158,143 @@ def test_batched_rejects_unsupported(ctx, torch):
         ra.batch_solve(p64)
     for pr in probs + p64:
         pr.close()
+
+
+def _larger_instances():
+    return [synth.random_small(n, m, seed=2000 + k, dtype=np.float32)
+            for k, (n, m) in enumerate([(200003, 4), (90001, 16), (60001, 32)])]
+
+
+def _two_pass_check(probs, insts, seed):
+    """Evaluate random prices p0 and certify them (two passes); g(p0) and
+    U(X~(p0)) of every problem against the oracle."""
+    import paper_2104_00282_amd as ra
+    rng = np.random.default_rng(seed)
+    p0 = [round_prices(0.2 + rng.random(I.m) * 2, np.float32) for I in insts]
+    ps, infos, st = ra.batch_solve(probs, p0=p0, tol_rel=0.0, max_evals=2)
+    for I, p, pi, inf in zip(insts, p0, ps, infos):
+        assert np.array_equal(pi, p)
+        d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+        U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, d.r, d.jobs)
+        scale = abs(float(p @ I.R)) + np.abs(d.jobs["v"]).sum()
+        assert abs(inf["g"] - d.g) <= 1e-5 * scale, (I.n, I.m, inf["g"], d.g)
+        assert abs(inf["U_lb"] - U) <= 1e-5 * (scale + abs(U)), (I.n, I.m, inf["U_lb"], U)
+
+
+# launch shapes: (tile floats, rows per tile for m = 4, 8, 16, 32, blocks per CU);
+# one block per CU with 64-row tiles gives every wave several tiles
+SHAPES = [
+    (1024, (256, 128, 64, 0), 0),
+    (1024, (64, 64, 64, 0), 1),
+    (2048, (512, 256, 128, 64), 0),
+    (2048, (64, 64, 64, 64), 1),
+    (2048, (128, 128, 64, 64), 2),
+    (4096, (512, 512, 256, 128), 0),
+    (4096, (64, 128, 256, 64), 1),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=["tf%d_r%s_b%d" % (s[0], "-".join(map(str, s[1])),
+                                                s[2]) for s in SHAPES])
+def test_batched_shapes_match_oracle(torch, shape):
+    """Every tile budget, tile heights from one to eight jobs per lane, and
+    grids of one block per CU: the evaluated and certified values match the
+    oracle (also with alpha-fair jobs)."""
+    import paper_2104_00282_amd as ra
+    tf, rows, bpc = shape
+    ctx = ra.Context(0)
+    try:
+        ctx.set_batch_shape(tf, rows, bpc)
+        # with three larger problems every wave gets several tiles
+        insts = [I for I in _batch_instances() + _larger_instances()
+                 if tf >= 2048 or I.m != 32]
+        print("shape %s: %d problems" % (shape, len(insts)), flush=True)
+        probs = _problems(ctx, torch, insts)
+        _two_pass_check(probs, insts, seed=6)
+        for pr in probs:
+            pr.close()
+        af = _with_alpha_fair([I for I in _batch_instances() if tf >= 2048 or I.m != 32][:5], 79)
+        probs = _problems(ctx, torch, af)
+        _two_pass_check(probs, af, seed=7)
+        for pr in probs:
+            pr.close()
+        assert ctx.batch_tuning() == {}  # a fixed shape is never tuned
+    finally:
+        ctx.close()
+
+
+def test_batched_shape_validation(torch):
+    import paper_2104_00282_amd as ra
+    ctx = ra.Context(0)
+    try:
+        for tf, rows in [(3000, (64, 64, 64, 64)), (2048, (100, 64, 64, 64)),
+                         (1024, (64, 64, 64, 64)), (2048, (512, 512, 64, 64)),
+                         (4096, (1024, 64, 64, 64))]:
+            with pytest.raises(ra.RAError) as e:
+                ctx.set_batch_shape(tf, rows)
+            assert e.value.status == ra.RA_EINVAL
+        with pytest.raises(ra.RAError):
+            ctx.set_batch_shape(2048, (64, 64, 64, 64), 9)
+        # a shape without a tile for m = 32 refuses batches that have such problems
+        ctx.set_batch_shape(1024, (256, 128, 64, 0))
+        probs = _problems(ctx, torch, [synth.random_small(100, 32, seed=4, dtype=np.float32)])
+        with pytest.raises(ra.RAError) as e:
+            ra.batch_solve(probs)
+        assert e.value.status == ra.RA_EINVAL
+        ctx.set_batch_shape(0)
+        ra.batch_solve(probs, max_iter=2)
+        for pr in probs:
+            pr.close()
+    finally:
+        ctx.close()
+
+
+def test_batched_tuner_record_and_cache(torch, tmp_path, monkeypatch):
+    """The autotuner times tile heights per m class and blocks per CU, records
+    its candidates, keeps the fastest whole round, and stores its choice in
+    the cache file, from which a new context takes it without tuning."""
+    import paper_2104_00282_amd as ra
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("RESALLOC_TUNE_CACHE", str(cache))
+    insts = _batch_instances()
+    ctx = ra.Context(0)
+    try:
+        probs = _problems(ctx, torch, insts)
+        ra.batch_solve(probs, max_iter=3)
+        rec = ctx.batch_tuning()
+        cands = rec["candidates"]
+        chosen = rec["chosen"]
+        for c in cands:
+            assert c["ms"] > 0
+        per_class = [c for c in cands if c["m"] != 0]
+        whole = [c for c in cands if c["m"] == 0]
+        # every budget (1024 excluded: the batch has m = 32 problems), every
+        # valid height of every class, every block count up to what fits
+        assert {c["tile_floats"] for c in cands} == {2048, 4096}
+        for tf in (2048, 4096):
+            for m in (4, 8, 16, 32):
+                hs = sorted(c["rows"] for c in per_class
+                            if c["tile_floats"] == tf and c["m"] == m)
+                assert hs == [r for r in (64, 128, 256, 512) if r * m <= tf], (tf, m, hs)
+        best = min(whole, key=lambda c: c["ms"])
+        assert chosen["tile_floats"] == best["tile_floats"]
+        assert chosen["rows"] == best["rows"] and chosen["bpc"] == best["bpc"]
+        # these classes are too small for a trusted time per job: the split
+        # weighs bytes (all costs zero)
+        assert chosen["cost_ns_per_job"] == [0, 0, 0, 0]
+        line = cache.read_text().split()
+        assert len(line) == 11 and int(line[1]) == chosen["tile_floats"]
+        assert [int(x) for x in line[2:6]] == chosen["rows"] and int(line[6]) == chosen["bpc"]
+        for pr in probs:
+            pr.close()
+    finally:
+        ctx.close()
+    ctx2 = ra.Context(0)
+    try:
+        probs = _problems(ctx2, torch, insts)
+        _two_pass_check(probs, insts, seed=8)
+        assert ctx2.batch_tuning() == {}  # taken from the cache file
+        for pr in probs:
+            pr.close()
+    finally:
+        ctx2.close()
