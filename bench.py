@@ -144,7 +144,8 @@ def batched_vs_loop(args):
     log("per-instance loop")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    loop_info = [pr.solve(tol_rel=float(tg), max_iter=max_iter, stall_evals=args.stall_evals)[1]
+    arm = dict(stall_evals=args.arm_stall_evals, stall_restarts=args.stall_restarts)
+    loop_info = [pr.solve(tol_rel=float(tg), max_iter=max_iter, **arm)[1]
                  for pr, tg in zip(probs, targets)]
     torch.cuda.synchronize()
     t_loop = time.perf_counter() - t0
@@ -152,8 +153,7 @@ def batched_vs_loop(args):
     log("batched")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, binfo, _ = ra.batch_solve(probs, tol_each=targets, max_iter=max_iter,
-                                 stall_evals=args.stall_evals)
+    _, binfo, _ = ra.batch_solve(probs, tol_each=targets, max_iter=max_iter, **arm)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
 
@@ -170,8 +170,9 @@ def batched_vs_loop(args):
                         "utilities, R_j = 0.3 n/m" % (len(insts), n_tot, ent),
             "targets": "max(1e-6, 1.5 x floor), floor from a %d-iteration reference run"
                        % args.floor_iters,
-            "stop": "target reached, or no 0.1%% gap improvement within %d evaluations"
-                    % args.stall_evals,
+            "stop": "target reached, or no 0.1%% gap improvement within %d evaluations %d "
+                    "times (the first %d restart from the best certified point)"
+                    % (args.arm_stall_evals, args.stall_restarts + 1, args.stall_restarts),
         },
         "loop_seconds": t_loop,
         "batched_seconds": t_batch,
@@ -223,7 +224,9 @@ def bench_warmstart(args):
     const = ws.constant_network(ctx, net, Y)
     log("evaluation: %d instances, n = %d" % (args.eval_count, args.eval_n))
     rows = ws.evaluate(ctx, net, args.eval_count, args.eval_n, m, seed0=synth_seed(200000),
-                       const_net=const, stall_evals=args.stall_evals, log=log)
+                       const_net=const, ref_stall_evals=args.stall_evals,
+                       stall_evals=args.arm_stall_evals, stall_restarts=args.stall_restarts,
+                       near_sigma=0.03, log=log)
     s = ws.summarize(rows)
     out = {
         "metric": "time to a 1e-4 relative gap, learned warm start vs cold start (also 1e-3 and "
@@ -246,6 +249,14 @@ def bench_warmstart(args):
                        "prediction; level floor_any)",
             "fallback": "cold restart when the certified gap has not fallen below the first "
                         "certificate within 5 certificates",
+            "ablations": "const: the training mean of log p as the prediction; near: the p = 1 "
+                         "reference run's prices times exp(0.03 z) (closer to p* than the "
+                         "network), with the learned start's first step",
+            "stop": "target reached, or no 0.1%% gap improvement within %d evaluations %d "
+                    "times (the first %d restart from the best certified point); reference "
+                    "runs: no improvement within %d evaluations"
+                    % (args.arm_stall_evals, args.stall_restarts + 1, args.stall_restarts,
+                       args.stall_evals),
         },
         "summary": s,
         "training": dict(tinfo, data_seconds=t_data,
@@ -303,7 +314,8 @@ def bench_solves(args):
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     _, info, _ = prob.solve(tol_rel=tol, max_iter=2 * args.floor_iters,
-                                            stall_evals=args.stall_evals, **kw)
+                                            stall_evals=args.arm_stall_evals,
+                                            stall_restarts=args.stall_restarts, **kw)
                     runs.append((time.perf_counter() - t0, info))
                 runs.sort(key=lambda r: r[0])
                 sec, info = runs[1]
@@ -334,8 +346,10 @@ def bench_solves(args):
         "config": {"workload": "small-log, mixed-16, roofline-64 single-instance solves",
                    "targets": "max(tol, 1.5 x floor), tol 1e-8 (small-log) / 1e-6, floor from a "
                               "%d-iteration reference run" % args.floor_iters,
-                   "stop": "target reached, or no 0.1%% gap improvement within %d evaluations"
-                           % args.stall_evals},
+                   "stop": "target reached, or no 0.1%% gap improvement within %d evaluations "
+                           "%d times (the first %d restart from the best certified point)"
+                           % (args.arm_stall_evals, args.stall_restarts + 1,
+                              args.stall_restarts)},
         "solves": rows,
     }
     ctx.close()
@@ -764,7 +778,8 @@ def time_to_gap(prob, torch, args):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 _, info, _ = prob.solve(tol_rel=tol, max_iter=2 * args.floor_iters,
-                                        stall_evals=args.stall_evals, **kw)
+                                        stall_evals=args.arm_stall_evals,
+                                        stall_restarts=args.stall_restarts, **kw)
                 runs.append((time.perf_counter() - t0, info))
             runs.sort(key=lambda r: r[0])
             sec, info = runs[1]
@@ -798,7 +813,12 @@ def main():
     ap.add_argument("--scale-n", type=int, default=800_000_000,
                     help="jobs of the scale workload (m = 64; 8e8 is 205 GB of T)")
     ap.add_argument("--floor-iters", type=int, default=300)
-    ap.add_argument("--stall-evals", type=int, default=100)
+    ap.add_argument("--stall-evals", type=int, default=100,
+                    help="stall window of the long reference runs that set the gap floors")
+    ap.add_argument("--arm-stall-evals", type=int, default=30,
+                    help="stall window of the timed solves")
+    ap.add_argument("--stall-restarts", type=int, default=5,
+                    help="stalls of a timed solve that restart from its best certified point")
     ap.add_argument("--train-count", type=int, default=20000)
     ap.add_argument("--train-n", type=int, default=100000)
     ap.add_argument("--eval-count", type=int, default=1000)

@@ -194,6 +194,12 @@ typedef struct {
                                 still be queued on the context's stream when the
                                 call returns.  ra_batch_solve and
                                 ra_solve_learned ignore it.  0 or 1              */
+    int32_t stall_restarts;  /* >= 0, with stall_evals > 0: the first this many
+                                stalls restart the update from the best certified
+                                point with an empty L-BFGS memory and the first
+                                step of init_step (a new approach to the optimum,
+                                which can certify a tighter gap) instead of
+                                stopping; the next stall stops                    */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
@@ -216,7 +222,7 @@ typedef struct {
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
  * stall_evals = 0 (off), init_step = 0 (default step), tol_abs = 0 (off),
- * device_loop = 0. */
+ * device_loop = 0, stall_restarts = 0. */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
 /* Per-job demands (§7, "Extensions and variations"): the usage limit becomes

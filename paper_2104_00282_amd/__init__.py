@@ -154,11 +154,12 @@ class Problem:
 
     def solve(self, p0=None, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, method=0, use_graph=True,
               verbose=False, max_evals=0, stall_evals=0, init_step=0.0, paper_init=False,
-              tol_abs=0.0, device_loop=False):
+              tol_abs=0.0, device_loop=False, stall_restarts=0):
         """Price discovery; returns (p, info dict, status).  paper_init starts
         from the paper's data-dependent prices (ra_init_prices) unless p0 is
         given."""
         o = ra_solve_opts_default()
+        o.stall_restarts = stall_restarts
         o.init_step = init_step
         o.tol_abs = tol_abs
         o.device_loop = 1 if device_loop else 0
@@ -226,9 +227,11 @@ class Problem:
         return p
 
     def solve_learned(self, mlp, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, use_graph=True,
-                      max_evals=0, stall_evals=0, fallback_window=5, init_step=0.0):
+                      max_evals=0, stall_evals=0, fallback_window=5, init_step=0.0,
+                      stall_restarts=0):
         """Price discovery from the network's predicted prices (ra_solve_learned)."""
         o = ra_solve_opts_default()
+        o.stall_restarts = stall_restarts
         o.init_step = init_step
         o.tol_rel = tol_rel
         o.max_iter = max_iter
@@ -255,7 +258,7 @@ class Problem:
 
 def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lbfgs_mem=10,
                 method=0, use_graph=True, max_evals=0, stall_evals=0, init_step=0.0,
-                paper_init=False, tol_abs=0.0):
+                paper_init=False, tol_abs=0.0, stall_restarts=0):
     """Solve several Problems of one Context together (ra_batch_solve).
     Returns (list of price arrays, list of info dicts, status)."""
     if not problems:
@@ -272,6 +275,7 @@ def batch_solve(problems, p0=None, tol_rel=1e-6, tol_each=None, max_iter=500, lb
     o.stall_evals = stall_evals
     o.init_step = init_step
     o.tol_abs = tol_abs
+    o.stall_restarts = stall_restarts
     ms = [pr.m for pr in problems]
     offs = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
     p = np.ones(int(offs[-1]))

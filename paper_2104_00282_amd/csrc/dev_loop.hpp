@@ -2,7 +2,7 @@
 // the reduction kernel that follows each dual pass takes the step), so that a
 // solve is a replayed graph of passes with no host round trip between them.  The update is the host PriceLoop's (price_loop.hpp): projected
 // L-BFGS on g/n with Armijo backtracking, the projected subgradient fallback,
-// one-pass-late certificates, stall and budget stops.  Lane j of the wave
+// one-pass-late certificates, stall stops and restarts, budget stops.  Lane j of the wave
 // holds coordinate j (m <= 64, the vectorised kernels' classes).
 #pragma once
 
@@ -27,7 +27,7 @@ struct DevPoint {
 // loop reaches it.
 struct DevLoop {
     // ---- header: written by the host before the first pass
-    int m, mem, method, max_iter, max_evals, stall_evals;
+    int m, mem, method, max_iter, max_evals, stall_evals, stall_restarts;
     double n, tol_rel, tol_abs, init_step;
     double R[DL_MAX_M];
     double pe[DL_MAX_M];  // prices of the pass in flight, as rounded for it
@@ -36,7 +36,7 @@ struct DevLoop {
     int done;             // set when the loop has ended: later kernels return at once
     int error;            // 1: non-finite dual value, usage or gap
     int have_pend, npairs, head, ls, evals, iters, fallbacks, sg_steps, improved_at, ncert,
-        stalled, converged;
+        stalled, converged, restarts;
     double lam;
     // ---- result: written by the step that ends the loop
     double res_p[DL_MAX_M];

@@ -194,6 +194,7 @@ struct Step {
     // take the evaluated point into the L-BFGS state machine.
     __device__ void feed(double g, double rj, double sdu)
     {
+        bool restart = false;
         if (L->have_pend && !L->pend.certified) {
             DevPoint& e = L->pend;
             const double pq = wsum(on ? e.p[j] * (L->R[j] - e.r[j]) : 0.0);
@@ -212,9 +213,14 @@ struct Step {
                 return;
             }
             if (L->stall_evals > 0 && L->evals - L->improved_at >= L->stall_evals) {
-                L->stalled = 1;
-                L->state = 4;
-                return;
+                if (L->restarts < L->stall_restarts && (L->state == 1 || L->state == 2)) {
+                    L->restarts += 1;  // restart from the best point once e is taken in
+                    restart = true;
+                } else {
+                    L->stalled = 1;
+                    L->state = 4;
+                    return;
+                }
             }
         }
         // the evaluated point
@@ -234,6 +240,15 @@ struct Step {
         L->evals += 1;
         L->have_pend = 1;
         const int was = L->state;
+        if (restart) {
+            // a new window from the best certified point (the point just
+            // evaluated is still certified by the next pass)
+            L->improved_at = L->evals;
+            copy_point(L->cur, L->best);
+            L->npairs = 0;
+            start_iteration();
+            return;
+        }
         if (was == 0) {
             copy_point(L->cur, e);
             start_iteration();

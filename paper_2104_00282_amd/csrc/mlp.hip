@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -194,63 +195,133 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 }
 
 // --------------------------------------------------------------- features --
-// Block j < m: column j of the sampled rows.  Each sample gets the 32-bit key
-// (kind << 31) | bits(value) (values are >= 0, so key order is (kind, value)
-// order); the nearest-rank quantiles of each kind are the keys of global
-// rank r in that order, found by a radix select (4 passes of 8 bits, all six
-// ranks at once) instead of a full sort.  Also the FP64 column sum and
-// R_j / n.  Block m: the weight histograms.
-__global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
-                                                   const float2* __restrict__ prm, int64_t n,
-                                                   int m, const double* __restrict__ R,
-                                                   float* __restrict__ feat)
+// Two kernels.  k_feat_gather: sample k < S is row floor(k n / S); each
+// thread of many small blocks reads one sampled row (all m entries, so the
+// scattered row reads are spread over many compute units) and its packed
+// utility, writes the 32-bit key (kind << 31) | bits(value) of every entry
+// to keys[j][k] (values are >= 0, so key order is (kind, value) order), and
+// each block writes its FP64 column sums, its count of log jobs and its
+// weight-histogram counts.  k_feat_select, block j < m: column j's keys
+// from memory into LDS; the nearest-rank quantiles of each kind are the
+// keys of given global rank in that order, found by a radix select (4
+// passes of 8 bits, all six ranks at once) instead of a full sort; the
+// column's partial sums in block order give its mean.  Block m: the weight
+// histograms from the block counts.
+constexpr int FEAT_GATHER_THREADS = 64;
+constexpr int FEAT_GATHER_BLOCKS = FEAT_SAMPLE / FEAT_GATHER_THREADS;
+
+// Layout of the features scratch (ctx->feat_ws): keys [64][FEAT_SAMPLE],
+// then per gather block m FP64 column sums (stride 64), one log-job count
+// and 16 histogram counts.
+constexpr size_t FEAT_KEYS_BYTES = sizeof(unsigned) * 64 * FEAT_SAMPLE;
+constexpr size_t FEAT_SUMS_BYTES = sizeof(double) * 64 * FEAT_GATHER_BLOCKS;
+constexpr size_t FEAT_CNT_BYTES = sizeof(int) * 17 * FEAT_GATHER_BLOCKS;
+constexpr size_t FEAT_WS_BYTES = FEAT_KEYS_BYTES + FEAT_SUMS_BYTES + FEAT_CNT_BYTES;
+
+__global__ void __launch_bounds__(FEAT_GATHER_THREADS) k_feat_gather(
+    const float* __restrict__ T, const float2* __restrict__ prm, int64_t n, int m,
+    unsigned* __restrict__ keys, double* __restrict__ sums, int* __restrict__ cnts)
+{
+    __shared__ double cs[64][FEAT_GATHER_THREADS / 64 + 1];
+    __shared__ int hc[17];
+    const int S = (int)(n < FEAT_SAMPLE ? n : FEAT_SAMPLE);
+    const int tid = threadIdx.x;
+    const int k = blockIdx.x * FEAT_GATHER_THREADS + tid;
+    if (tid < 17) hc[tid] = 0;
+    __syncthreads();
+    const bool on = k < S;
+    const int64_t i = on ? ((int64_t)k * n) / S : 0;
+    const float2 wc = on ? prm[i] : make_float2(0.f, 0.f);
+    const unsigned kind = __builtin_signbit(wc.y) ? 0u : 1u;
+    if (on) {
+        int bin = (int)floorf((wc.x - 0.5f) / 0.1875f);
+        bin = bin < 0 ? 0 : (bin > 7 ? 7 : bin);
+        atomicAdd(&hc[kind * 8 + bin], 1);
+        if (kind == 0u) atomicAdd(&hc[16], 1);
+    }
+    const float* row = T + i * m;
+    for (int j = 0; j < m; ++j) {
+        const float v = on ? row[j] : 0.f;  // consecutive entries: one cache line per row
+        // -0 and +0 share a key
+        const unsigned bits = v == 0.f ? 0u : __float_as_uint(v);
+        if (on) keys[(int64_t)j * FEAT_SAMPLE + k] = (kind << 31) | (bits & 0x7fffffffu);
+        // the block's column sum, lanes in order (wave sum by butterfly)
+        double s = (double)v;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if ((tid & 63) == 0) cs[j][tid >> 6] = s;
+    }
+    __syncthreads();
+    if (tid < m) {
+        double s = 0.0;
+        for (int w = 0; w < FEAT_GATHER_THREADS / 64; ++w) s += cs[tid][w];
+        sums[(int64_t)blockIdx.x * 64 + tid] = s;
+    }
+    if (tid < 17) cnts[blockIdx.x * 17 + tid] = hc[tid];
+}
+
+__global__ void __launch_bounds__(1024) k_feat_select(const unsigned* __restrict__ keys,
+                                                      const double* __restrict__ sums,
+                                                      const int* __restrict__ cnts, int64_t n,
+                                                      int m, const double* __restrict__ R,
+                                                      float* __restrict__ feat)
 {
     __shared__ unsigned key[FEAT_SAMPLE];
-    __shared__ double red[1024];
-    __shared__ int cnt[16];
-    __shared__ unsigned hist[6][256];
+    __shared__ unsigned hist[2][6][256];
     __shared__ unsigned tpre[6], trank[6];
-    __shared__ int tgrp[6], tvalid[6], n0s;
+    __shared__ int tvalid[6], n0s;
+    __shared__ double colsum;
     const int S = (int)(n < FEAT_SAMPLE ? n : FEAT_SAMPLE);
+    const int nb = (S + FEAT_GATHER_THREADS - 1) / FEAT_GATHER_THREADS;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int j = blockIdx.x;
     if (j == m) {
-        if (tid < 16) cnt[tid] = 0;
-        __syncthreads();
-        for (int k = tid; k < S; k += 1024) {
-            const int64_t i = ((int64_t)k * n) / S;
-            const float2 wc = prm[i];
-            const int kind = __builtin_signbit(wc.y) ? 0 : 1;
-            int bin = (int)floorf((wc.x - 0.5f) / 0.1875f);
-            bin = bin < 0 ? 0 : (bin > 7 ? 7 : bin);
-            atomicAdd(&cnt[kind * 8 + bin], 1);
+        // wave b < 16: bin b of the weight histograms, its lanes striding
+        // over the gather blocks (integer sums)
+        if (wv < 16) {
+            int c = 0;
+            for (int b = lane; b < nb; b += 64) c += cnts[b * 17 + wv];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+            if (lane == 0) feat[8 * m + wv] = (float)c / (float)S;
         }
-        __syncthreads();
-        if (tid < 16) feat[8 * m + tid] = (float)cnt[tid] / (float)S;
         return;
     }
-    if (tid == 0) n0s = 0;
-    __syncthreads();
-    double s = 0.0;
-    int c0 = 0;
-    for (int k = tid; k < S; k += 1024) {
-        const int64_t i = ((int64_t)k * n) / S;
-        const float v = T[i * m + j];
-        const unsigned kind = __builtin_signbit(prm[i].y) ? 0u : 1u;
-        // -0 and +0 share a key
-        const unsigned bits = v == 0.f ? 0u : __float_as_uint(v);
-        key[k] = (kind << 31) | (bits & 0x7fffffffu);
-        s += (double)v;
-        c0 += kind == 0u ? 1 : 0;
+    // the column's keys, all loads of a thread issued before their stores
+    {
+        unsigned v[FEAT_SAMPLE / 1024];
+#pragma unroll
+        for (int u = 0; u < FEAT_SAMPLE / 1024; ++u) {
+            const int k = tid + 1024 * u;
+            v[u] = k < S ? keys[(int64_t)j * FEAT_SAMPLE + k] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < FEAT_SAMPLE / 1024; ++u) {
+            const int k = tid + 1024 * u;
+            if (k < S) key[k] = v[u];
+        }
     }
-    red[tid] = s;
-    atomicAdd(&n0s, c0);
-    __syncthreads();
-    for (int h = 512; h > 0; h >>= 1) {
-        if (tid < h) red[tid] += red[tid + h];
-        __syncthreads();
+    // wave 0: the number of log jobs and the column sum over the gather
+    // blocks (lanes stride over the blocks, then a butterfly: a fixed order)
+    if (wv == 0) {
+        int c = 0;
+        double cs = 0.0;
+        for (int b = lane; b < nb; b += 64) {
+            c += cnts[b * 17 + 16];
+            cs += sums[(int64_t)b * 64 + j];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            c += __shfl_xor(c, off);
+            cs += __shfl_xor(cs, off);
+        }
+        if (lane == 0) {
+            n0s = c;
+            colsum = cs;
+        }
     }
+    __syncthreads();
     if (tid == 0) {
         const int n0 = n0s;
         const double qs[3] = {0.1, 0.5, 0.9};
@@ -266,35 +337,37 @@ __global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
             }
         }
     }
+    for (int e = tid; e < 6 * 256; e += 1024) (&hist[0][0][0])[e] = 0u;
+    __syncthreads();
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
         const unsigned hmask = pass == 0 ? 0u : (0xffffffffu << (shift + 8));
-        for (int e = tid; e < 6 * 256; e += 1024) (&hist[0][0])[e] = 0u;
-        __syncthreads();
-        if (tid == 0) {
-            // ranks whose key prefixes agree share one histogram
-            for (int t = 0; t < 6; ++t) {
-                int g = t;
-                for (int u = 0; u < t; ++u)
-                    if (tgrp[u] == u && tpre[u] == tpre[t]) {
-                        g = u;
-                        break;
-                    }
-                tgrp[t] = g;
-            }
+        unsigned(*hs)[256] = hist[pass & 1];
+        // ranks whose key prefixes agree share one histogram (every thread
+        // forms the grouping itself)
+        int grp[6];
+        unsigned pre[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            pre[t] = tpre[t];
+            grp[t] = t;
         }
-        __syncthreads();
+#pragma unroll
+        for (int t = 1; t < 6; ++t)
+#pragma unroll
+            for (int u = t - 1; u >= 0; --u)
+                if (grp[u] == u && pre[u] == pre[t]) grp[t] = u;
         for (int k = tid; k < S; k += 1024) {
             const unsigned kv = key[k];
             const unsigned d = (kv >> shift) & 255u;
 #pragma unroll
             for (int t = 0; t < 6; ++t)
-                if (tgrp[t] == t && (kv & hmask) == tpre[t]) atomicAdd(&hist[t][d], 1u);
+                if (grp[t] == t && (kv & hmask) == pre[t]) atomicAdd(&hs[t][d], 1u);
         }
         __syncthreads();
         if (wv < 6 && tvalid[wv]) {
             // wave t: the digit bin holding rank trank[t] of its prefix group
-            const unsigned* h = hist[tgrp[wv]];
+            const unsigned* h = hs[grp[wv]];
             unsigned c[4], ls = 0u;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -321,6 +394,10 @@ __global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
                 tpre[wv] = tpre[wv] | ((unsigned)bsel << shift);
                 trank[wv] = r - acc;
             }
+        } else if (wv >= 6) {
+            // the other histogram buffer, for the next pass
+            for (int e = tid - 6 * 64; e < 6 * 256; e += 1024 - 6 * 64)
+                (&hist[(pass + 1) & 1][0][0])[e] = 0u;
         }
         __syncthreads();
     }
@@ -328,15 +405,18 @@ __global__ void __launch_bounds__(1024) k_features(const float* __restrict__ T,
         for (int t = 0; t < 6; ++t)
             feat[8 * j + t] = tvalid[t] ? __uint_as_float(tpre[t] & 0x7fffffffu) : 0.f;
         feat[8 * j + 6] = (float)(R[j] / (double)n);
-        const double mean = red[0] / (double)S;
+        const double mean = colsum / (double)S;
         feat[8 * j + 7] = (float)log(mean > 1e-30 ? mean : 1e-30);
     }
 }
 
 // Forward of one feature row in one block (the warm-start prediction):
-// standardise, two ReLU layers, output layer, de-standardise.  One wave per
-// output unit at a time, lanes striding over the inputs (rows of W are
-// contiguous), wave sums by butterfly.  y receives the log-prices.
+// standardise, two ReLU layers, output layer, de-standardise.  Each output
+// row of a layer gets 16 consecutive threads; thread s reads the 16-byte
+// chunks s, s + 16, ... of the row of W (rows are contiguous), so that 16
+// threads read 256 consecutive bytes per load; the 16 partial sums meet by
+// butterfly.  Rows not 16-byte aligned, or of a length not a multiple of 4,
+// are read one float per thread at a time.  y receives the log-prices.
 __global__ void __launch_bounds__(1024) k_forward1(const float* __restrict__ P, int64_t oW1,
                                                    int64_t ob1, int64_t oW2, int64_t ob2,
                                                    int64_t oW3, int64_t ob3,
@@ -344,22 +424,39 @@ __global__ void __launch_bounds__(1024) k_forward1(const float* __restrict__ P, 
                                                    int O, const float* __restrict__ x,
                                                    float* __restrict__ y)
 {
-    extern __shared__ float fsh[];
+    extern __shared__ __attribute__((aligned(16))) float fsh[];
     float* xs = fsh;
     float* h1 = fsh + D;
     float* h2 = h1 + H;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+    const int tid = threadIdx.x;
     for (int k = tid; k < D; k += blockDim.x) xs[k] = (x[k] - norm[k]) / norm[D + k];
     __syncthreads();
+    constexpr int G = 16;
+    const int s = tid & (G - 1);
+    const int rows_per_pass = (int)blockDim.x / G;
     auto layer = [&](const float* W, const float* bias, const float* in, int K, int N, float* out,
                      bool relu) {
-        for (int r = wv; r < N; r += nw) {
-            const float* w = W + (int64_t)r * K;
+        const bool vec = (K & 3) == 0 && ((uintptr_t)W & 15) == 0 && ((uintptr_t)in & 15) == 0;
+        for (int r0 = 0; r0 < N; r0 += rows_per_pass) {
+            const int r = r0 + tid / G;
             float acc = 0.f;
-            for (int k = lane; k < K; k += 64) acc += w[k] * in[k];
+            if (r < N) {
+                const float* w = W + (int64_t)r * K;
+                if (vec) {
+                    const float4* w4 = reinterpret_cast<const float4*>(w);
+                    const float4* i4 = reinterpret_cast<const float4*>(in);
+                    const int K4 = K >> 2;
+                    for (int c = s; c < K4; c += G) {
+                        const float4 a = w4[c], b = i4[c];
+                        acc += a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+                    }
+                } else {
+                    for (int k = s; k < K; k += G) acc += w[k] * in[k];
+                }
+            }
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-            if (lane == 0) {
+            for (int off = 1; off < G; off <<= 1) acc += __shfl_xor(acc, off);
+            if (r < N && s == 0) {
                 const float v = acc + bias[r];
                 out[r] = relu ? fmaxf(v, 0.f) : v;
             }
@@ -473,9 +570,18 @@ namespace ra {
 ra_status features_into(ra_problem* P, float* feat)
 {
     ra_ctx* ctx = P->ctx;
-    k_features<<<P->m + 1, 1024, 0, ctx->stream>>>(static_cast<const float*>(P->T),
-                                                   static_cast<const float2*>(P->prm), P->n,
-                                                   P->m, P->Rdev, feat);
+    if (!ctx->feat_ws) RA_HIP(ctx, hipMalloc(&ctx->feat_ws, FEAT_WS_BYTES));
+    char* ws = static_cast<char*>(ctx->feat_ws);
+    unsigned* keys = reinterpret_cast<unsigned*>(ws);
+    double* sums = reinterpret_cast<double*>(ws + FEAT_KEYS_BYTES);
+    int* cnts = reinterpret_cast<int*>(ws + FEAT_KEYS_BYTES + FEAT_SUMS_BYTES);
+    const int S = (int)std::min<int64_t>(P->n, FEAT_SAMPLE);
+    const int nb = (S + FEAT_GATHER_THREADS - 1) / FEAT_GATHER_THREADS;
+    k_feat_gather<<<nb, FEAT_GATHER_THREADS, 0, ctx->stream>>>(
+        static_cast<const float*>(P->T), static_cast<const float2*>(P->prm), P->n, P->m, keys,
+        sums, cnts);
+    k_feat_select<<<P->m + 1, 1024, 0, ctx->stream>>>(keys, sums, cnts, P->n, P->m, P->Rdev,
+                                                      feat);
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
 }

@@ -18,7 +18,10 @@
 // a0 = 0.1 |p|_inf / |q|_inf, is taken instead (the fallback of §5); method 1
 // uses only that step.  With stall_evals > 0 the loop also ends when the best
 // certified relative gap has not improved by 0.1 % within that many passes
-// (the column-scaling recovery has a floor, see ra_solve).
+// (the column-scaling recovery has a floor, see ra_solve); with
+// stall_restarts = k > 0 the first k such stalls instead restart the update
+// from the best certified point with an empty memory (a new path to p*,
+// with new chances of a tighter certificate), and a new window begins.
 #pragma once
 
 #include <algorithm>
@@ -58,6 +61,7 @@ public:
     // sdu_prev = sum_i [u(t_i) - u(t~_i)] of pending() (ignored if none).
     void feed(const std::vector<double>& p_eval, double g, const double* r, double sdu_prev)
     {
+        bool restart = false;
         if (have_pend_ && !pend_.certified) {
             certify(pend_, sdu_prev);
             last_cert_ = pend_;
@@ -71,9 +75,15 @@ public:
                 return;
             }
             if (o_.stall_evals > 0 && evals_ - improved_at_ >= o_.stall_evals) {
-                stalled_ = true;  // the best gap stopped improving: end here
-                state_ = DONE;
-                return;
+                if (restarts_ < o_.stall_restarts && (state_ == LINE_SEARCH ||
+                                                      state_ == SUBGRADIENT)) {
+                    ++restarts_;  // restart from the best point once e is taken in
+                    restart = true;
+                } else {
+                    stalled_ = true;  // the best gap stopped improving: end here
+                    state_ = DONE;
+                    return;
+                }
             }
         }
         // the evaluated point, built in a member so that its vectors keep
@@ -93,6 +103,15 @@ public:
         const State was = state_;
         pend_ = e;
         have_pend_ = true;
+        if (restart) {
+            // a new window from the best certified point (the point just
+            // evaluated is still certified by the next pass)
+            improved_at_ = evals_;
+            cur_ = best_;
+            npairs_ = 0;
+            start_iteration();
+            return;
+        }
         switch (was) {
         case INIT:
             cur_ = e;
@@ -152,6 +171,7 @@ public:
     int iters() const { return iters_; }
     int evals() const { return evals_; }
     int fallbacks() const { return fallbacks_; }
+    int restarts() const { return restarts_; }
     bool stalled() const { return stalled_; }
     // The point certified by the last feed (valid when ncertified() grew).
     const Point& last_certified() const { return last_cert_; }
@@ -288,7 +308,7 @@ private:
     std::vector<double> step_, y_, q_;
     int npairs_ = 0, head_ = 0, ls_ = 0;
     double lam_ = 1.0;
-    int evals_ = 0, iters_ = 0, fallbacks_ = 0, sg_steps_ = 0;
+    int evals_ = 0, iters_ = 0, fallbacks_ = 0, sg_steps_ = 0, restarts_ = 0;
     int improved_at_ = 0;
     bool stalled_ = false;
 };

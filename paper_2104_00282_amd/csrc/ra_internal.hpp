@@ -37,6 +37,7 @@ struct ra_ctx {
     ra::BatchTuned batch_fixed_shape;
     std::string batch_tune_log;
     std::unique_ptr<ra::HostPool> pool;      // host threads of the batched solver
+    void* feat_ws = nullptr;  // warm-start features: sampled keys and block partials
 };
 
 struct ra_problem {

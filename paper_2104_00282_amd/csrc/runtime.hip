@@ -369,6 +369,7 @@ static void free_ctx(ra_ctx* ctx)
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    (void)hipFree(ctx->feat_ws);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -629,6 +630,7 @@ void ra_solve_opts_default(ra_solve_opts* o)
     o->init_step = 0.0;
     o->tol_abs = 0.0;
     o->device_loop = 0;
+    o->stall_restarts = 0;
 }
 
 static bool valid_opts(const ra_solve_opts& o)
@@ -637,7 +639,7 @@ static bool valid_opts(const ra_solve_opts& o)
            o.lbfgs_mem >= 1 && o.lbfgs_mem <= 64 && (o.method == 0 || o.method == 1) &&
            (o.init >= 0 && o.init <= 2) && o.init_step >= 0.0 && o.init_step <= 10.0 &&
            o.tol_abs >= 0.0 && std::isfinite(o.tol_abs) &&
-           (o.device_loop == 0 || o.device_loop == 1);
+           (o.device_loop == 0 || o.device_loop == 1) && o.stall_restarts >= 0;
 }
 
 namespace {
@@ -755,6 +757,7 @@ ra_status solve_device(ra_problem* P, const ra_solve_opts& o, const std::vector<
     h->max_iter = o.max_iter;
     h->max_evals = o.max_evals;
     h->stall_evals = o.stall_evals;
+    h->stall_restarts = o.stall_restarts;
     h->n = (double)P->n;
     h->tol_rel = o.tol_rel;
     h->tol_abs = o.tol_abs;

@@ -103,7 +103,8 @@ LEVELS = (1e-3, 1e-4, "floor", "floor_any")
 
 
 def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters=300,
-             stall_evals=100, max_iter=500, fallback_window=5, levels=LEVELS, log=None):
+             ref_stall_evals=100, stall_evals=30, stall_restarts=5, max_iter=500,
+             fallback_window=5, levels=LEVELS, near_sigma=0.0, log=None):
     """Cold start (p = 1), the paper's data-dependent start and the learned
     warm start (and optionally a constant predictor) on fresh instances, to each
     relative-gap level of `levels` separately ("floor" = max(1e-6, 1.5 x the
@@ -112,7 +113,15 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
     same with the smallest gap of three long reference runs, from p = 1, from
     the paper's start and from the network's prediction, so that no start's
     own path defines the target). Returns a list of per-instance dicts
-    {"floor_gap": g, "floor_any_gap": g, level: {arm: info, "target": tol}}."""
+    {"floor_gap": g, "floor_any_gap": g, level: {arm: info, "target": tol}}.
+    The reference runs stop when their best gap has not improved within
+    ref_stall_evals passes; the timed arms, all alike, when it has not
+    improved within stall_evals passes for the (stall_restarts + 1)-th time,
+    the earlier stalls restarting the update from the best certified point.
+    near_sigma > 0 adds the arm "near": a start at the p = 1 reference run's
+    prices times exp(near_sigma z), z standard normal (seeded per instance),
+    closer to p* than any prediction, which shows how much a target tied to
+    one start's own path favours that start."""
     import synth
 
     rows = []
@@ -122,16 +131,16 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
         for k in range(gn):
             T, w, c, kind, R = synth.warmstart_device(n, m, seed=seed0 + g0 + k)
             probs.append(Problem(ctx, T, w, c, kind, R, 1e-3, validate=False))
-        _, ref, _ = batch_solve(probs, tol_rel=0.0, max_iter=floor_iters,
-                                stall_evals=stall_evals)
+        pref, ref, _ = batch_solve(probs, tol_rel=0.0, max_iter=floor_iters,
+                                   stall_evals=ref_stall_evals)
         refs = [ref]
         if "floor_any" in levels:
             _, rp, _ = batch_solve(probs, tol_rel=0.0, max_iter=floor_iters,
-                                   stall_evals=stall_evals, paper_init=True)
+                                   stall_evals=ref_stall_evals, paper_init=True)
             # the learned solve's empty-memory step is 2 % of max p
             preds = [pr.predict_prices(net) for pr in probs]
             _, rw, _ = batch_solve(probs, p0=preds, tol_rel=0.0, max_iter=floor_iters,
-                                   stall_evals=stall_evals, init_step=0.02)
+                                   stall_evals=ref_stall_evals, init_step=0.02)
             refs += [rp, rw]
         for k, (pr, rf) in enumerate(zip(probs, ref)):
             pr.solve(max_iter=0)  # capture the evaluation graph outside the timings
@@ -145,16 +154,18 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
                 else:
                     tol = float(lv)
                 arms = {}
-                arms["cold"] = pr.solve(tol_rel=tol, max_iter=max_iter, stall_evals=stall_evals)[1]
-                arms["warm"] = pr.solve_learned(net, tol_rel=tol, max_iter=max_iter,
-                                                stall_evals=stall_evals,
-                                                fallback_window=fallback_window)[1]
-                arms["paper"] = pr.solve(tol_rel=tol, max_iter=max_iter, stall_evals=stall_evals,
-                                         paper_init=True)[1]
+                kw = dict(tol_rel=tol, max_iter=max_iter, stall_evals=stall_evals,
+                          stall_restarts=stall_restarts)
+                arms["cold"] = pr.solve(**kw)[1]
+                arms["warm"] = pr.solve_learned(net, fallback_window=fallback_window, **kw)[1]
+                arms["paper"] = pr.solve(paper_init=True, **kw)[1]
+                if near_sigma > 0:
+                    z = np.random.default_rng(seed0 + g0 + k).standard_normal(m)
+                    arms["near"] = pr.solve(p0=np.asarray(pref[k]) * np.exp(near_sigma * z),
+                                            init_step=0.02, **kw)[1]
                 if const_net is not None:
-                    arms["const"] = pr.solve_learned(const_net, tol_rel=tol, max_iter=max_iter,
-                                                     stall_evals=stall_evals,
-                                                     fallback_window=fallback_window)[1]
+                    arms["const"] = pr.solve_learned(const_net, fallback_window=fallback_window,
+                                                     **kw)[1]
                 arms["target"] = tol
                 row[str(lv)] = arms
             rows.append(row)
@@ -177,7 +188,7 @@ def summarize(rows, levels=LEVELS):
             return np.array([r[key][arm][k] for r in rows], dtype=np.float64)
 
         lvl = {}
-        for arm in ("cold", "warm", "paper", "const"):
+        for arm in ("cold", "warm", "paper", "const", "near"):
             if arm not in rows[0][key]:
                 continue
             lvl[arm] = {
@@ -196,6 +207,9 @@ def summarize(rows, levels=LEVELS):
         if "const" in lvl:
             lvl["const_speedup_total"] = (lvl["cold"]["seconds_total"] /
                                           lvl["const"]["seconds_total"])
+        if "near" in lvl:
+            lvl["near_speedup_total"] = (lvl["cold"]["seconds_total"] /
+                                         lvl["near"]["seconds_total"])
         if lv in ("floor", "floor_any"):
             lvl["targets_at_1e-6"] = int(sum(r[key]["target"] <= 1e-6 for r in rows))
         out[key] = lvl

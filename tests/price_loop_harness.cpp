@@ -31,7 +31,9 @@ int main(int argc, char** argv)
     o.use_graph = 0;
     o.verbose = 0;
     o.max_evals = !std::strcmp(mode, "budget") ? 7 : 0;
-    o.stall_evals = !std::strcmp(mode, "stall") ? 25 : 0;
+    const bool stall = !std::strcmp(mode, "stall") || !std::strcmp(mode, "stall_restart");
+    o.stall_evals = stall ? 25 : 0;
+    o.stall_restarts = !std::strcmp(mode, "stall_restart") ? 3 : 0;
     o.init_step = 0.0;
     o.tol_abs = 0.0;
     if (!std::strcmp(mode, "subgradient")) o.max_iter = 400;
@@ -39,6 +41,8 @@ int main(int argc, char** argv)
     ra::PriceLoop L(m, n, R.data(), o, p0.data());
     const double f0 = 2.0;
     int calls = 0;
+    bool restart_ok = true;
+    int restart_checks = 0;
     while (!L.done() && calls < 100000) {
         const std::vector<double>& p = L.next();
         std::vector<double> r(m);
@@ -50,7 +54,7 @@ int main(int argc, char** argv)
             // inconsistent gradient: wrong sign on one coordinate
             if (!std::strcmp(mode, "badgrad") && j == 0) gj = -gj;
             // stall: a small wobble keeps the loop moving around the minimiser
-            if (!std::strcmp(mode, "stall")) gj += 1e-3 * std::sin(7.0 * calls + j);
+            if (stall) gj += 1e-3 * std::sin(7.0 * calls + j);
             r[j] = R[j] - (double)n * gj;
             const double ps = std::max(c[j], 0.0);
             dist += (p[j] - ps) * (p[j] - ps);
@@ -67,19 +71,39 @@ int main(int argc, char** argv)
             }
             // gap(prev) = 50 n |prev - pstar|^2 (+ a floor in stall mode)
             double want = 50.0 * (double)n * dprev;
-            if (!std::strcmp(mode, "stall")) want += 1.0;
+            if (stall) want += 1.0;
             sdu = want - pq;
         }
+        const int rs0 = L.restarts();
         L.feed(p, f * (double)n, r.data(), sdu);
         ++calls;
+        if (L.restarts() > rs0 && !L.done()) {
+            // a restart: the next point is the projected steepest-descent
+            // step from the best certified point with the empty-memory length
+            const ra::Point& b = L.result();
+            double pi = 0.0, gi = 0.0;
+            for (int j = 0; j < m; ++j) {
+                pi = std::max(pi, std::fabs(b.p[j]));
+                gi = std::max(gi, std::fabs(b.grad[j]));
+            }
+            const double lam = 0.1 * pi / gi;
+            bool ok = b.certified;
+            for (int j = 0; j < m; ++j) {
+                const double want = std::max(b.p[j] - lam * b.grad[j], 0.0);
+                ok = ok && std::fabs(L.next()[j] - want) <= 1e-12 * (1.0 + std::fabs(want));
+            }
+            restart_ok = restart_ok && ok;
+            ++restart_checks;
+        }
         (void)dist;
     }
     const ra::Point& res = L.result();
     double err = 0.0;
     for (int j = 0; j < m; ++j) err = std::max(err, std::fabs(res.p[j] - std::max(c[j], 0.0)));
     std::printf("done=%d converged=%d stalled=%d iters=%d evals=%d fallbacks=%d calls=%d "
-                "rel=%.3e err=%.3e\n",
+                "rel=%.3e err=%.3e restarts=%d restart_checks=%d restart_ok=%d\n",
                 (int)L.done(), (int)L.converged(), (int)L.stalled(), L.iters(), L.evals(),
-                L.fallbacks(), calls, res.rel, err);
+                L.fallbacks(), calls, res.rel, err, L.restarts(), restart_checks,
+                (int)restart_ok);
     return 0;
 }

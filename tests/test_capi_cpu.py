@@ -54,8 +54,8 @@ def test_status_strings_and_defaults(lib):
     assert ra.ra_status_string(99) == "unknown status"
     o = ra.ra_solve_opts_default()
     assert (o.tol_rel, o.max_iter, o.lbfgs_mem, o.method, o.init, o.use_graph, o.max_evals,
-            o.stall_evals, o.init_step, o.tol_abs, o.device_loop) == \
-        (1e-6, 500, 10, 0, 0, 1, 0, 0, 0.0, 0.0, 0)
+            o.stall_evals, o.init_step, o.tol_abs, o.device_loop, o.stall_restarts) == \
+        (1e-6, 500, 10, 0, 0, 1, 0, 0, 0.0, 0.0, 0, 0)
 
 
 def test_null_arguments_rejected_without_device(lib):

@@ -138,6 +138,28 @@ def test_stall_stop(ctx, torch):
     assert info["rel_gap"] == pytest.approx(ih["rel_gap"], rel=0.5, abs=1e-6)
 
 
+@pytest.mark.parametrize("budget", [10, 16, 24])
+def test_stall_restarts_match_host(ctx, torch, budget):
+    """Started at a solved problem's prices, the certified gap cannot improve,
+    so with a window of 3 passes the loops stall every few passes: the first
+    two stalls restart from the best certified point, the third stops.  The
+    device loop takes the host loop's passes, with iterates equal to rounding,
+    and both end at least as tight as without restarts."""
+    I = synth.random_small(20000, 16, seed=509, dtype=np.float32)
+    prob = _problem(ctx, torch, I)
+    p0, _, _ = prob.solve(tol_rel=0.0, max_iter=200, stall_evals=40)
+    kw = dict(p0=p0, tol_rel=0.0, max_iter=300, max_evals=budget, stall_evals=3)
+    ph, ih, sh = prob.solve(stall_restarts=2, **kw)
+    pd, idv, sd = prob.solve(stall_restarts=2, device_loop=True, **kw)
+    pn, inr, _ = prob.solve(**kw)
+    assert sh == sd == 5  # RA_ENOTCONV: tol_rel = 0 is never met
+    assert inr["dual_evals"] < ih["dual_evals"] <= budget
+    assert idv["dual_evals"] == ih["dual_evals"] and idv["iters"] == ih["iters"]
+    assert np.allclose(pd, ph, rtol=1e-6, atol=0)
+    assert idv["rel_gap"] == pytest.approx(ih["rel_gap"], rel=1e-4, abs=1e-9)
+    assert ih["rel_gap"] <= inr["rel_gap"] * (1 + 1e-12)
+
+
 def test_demands_scalar_and_vector(ctx, torch):
     n, m = 40000, 16
     I = synth.random_small(n, m, seed=509, dtype=np.float32)

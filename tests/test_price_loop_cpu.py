@@ -53,6 +53,19 @@ def test_stall_stop(harness):
     assert d["stalled"] == 1 and d["converged"] == 0 and d["evals"] < 200
 
 
+def test_stall_restarts(harness):
+    """With stall_restarts = 3 the first three stalls restart the update from
+    the best certified point (empty memory: a projected steepest-descent step
+    of the default length), and the fourth stops the loop."""
+    base = run(harness, "stall")
+    d = run(harness, "stall_restart")
+    assert base["restarts"] == 0
+    assert d["restarts"] == 3 and d["restart_checks"] == 3 and d["restart_ok"] == 1
+    assert d["stalled"] == 1 and d["converged"] == 0
+    assert d["evals"] > base["evals"] + 3 * 25 - 1
+    assert d["rel"] <= base["rel"]
+
+
 def test_inconsistent_gradient_falls_back(harness):
     d = run(harness, "badgrad")
     assert d["done"] == 1 and d["fallbacks"] > 0
