@@ -396,8 +396,8 @@ __device__ __forceinline__ void coop_walk(Seg<float>& S, bool walking, float ama
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
         const int G0 = W > 32 ? 1 : W > 16 ? 2 : W > 8 ? 4 : W > 4 ? 8 : 16;
         const int G = G0 < GMAX ? G0 : GMAX;
-        float bn, bd;
-        int jn;
+        float bn = 1.f, bd = 0.f;
+        int jn = -1;
         if (G == 1) {
             // more than 32 walkers: every lane scans its own row (no ranking)
             coop_scan_part<M, 1>(tile + lane * RS, 0, S.ahi, S.phi, px, bn, bd, jn);

@@ -370,6 +370,7 @@ static void free_ctx(ra_ctx* ctx)
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     (void)hipFree(ctx->feat_ws);
+    ctx->batch_ws.reset();  // waits for its launches on the stream
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -676,10 +677,10 @@ bool device_loop_applies(const ra_problem* P, const ra_solve_opts& o)
 // The price block of a vectorised pass at prices p (no previous point), in
 // the layout of PriceArgs<m>: p, 1/p, q, 1/q, s, 1 - s (m floats each), then
 // has_prev.
-std::vector<float> first_price_args(int m, const std::vector<double>& p, std::vector<double>& pe,
-                                    const std::vector<double>& R, double& pR)
+void first_price_args(int m, const std::vector<double>& p, std::vector<double>& pe,
+                      const std::vector<double>& R, double& pR, std::vector<float>& a)
 {
-    std::vector<float> a(6 * (size_t)m + 1, 0.f);
+    a.assign(6 * (size_t)m + 1, 0.f);
     pR = 0.0;
     pe.resize(m);
     for (int j = 0; j < m; ++j) {
@@ -693,7 +694,7 @@ std::vector<float> first_price_args(int m, const std::vector<double>& p, std::ve
         pe[j] = (double)pf;
         pR += (double)pf * R[j];
     }
-    return a;  // the last word (has_prev) stays 0
+    // the last word (has_prev) stays 0
 }
 
 ra_status capture_dev_loop(ra_problem* P)
@@ -765,7 +766,8 @@ ra_status solve_device(ra_problem* P, const ra_solve_opts& o, const std::vector<
     for (int j = 0; j < m; ++j) h->R[j] = P->R[j];
     std::vector<double> pe;
     double pR = 0.0;
-    const std::vector<float> a = first_price_args(m, p0, pe, P->R, pR);
+    std::vector<float> a;
+    first_price_args(m, p0, pe, P->R, pR, a);
     for (int j = 0; j < m; ++j) h->pe[j] = pe[j];
     h->pR = pR;
     h->lam = 1.0;
@@ -1185,6 +1187,7 @@ struct BatchWs {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_grid = 0, graph_tf = 0, graph_lds = 0;
+    bool graph_dem = false, graph_af = false;  // kernel variant of the captured graph
     // the launch shape of the next rounds
     int tf = 2048, lds_floats = 0;
     ~BatchWs()
@@ -1402,7 +1405,8 @@ ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
     __atomic_store_n(ws.hflag, 0u, __ATOMIC_RELEASE);
     if (use_graph && !ctx->timing) {
         if (!ws.gexec || ws.graph_grid != grid || ws.graph_tf != ws.tf ||
-            ws.graph_lds != ws.lds_floats) {
+            ws.graph_lds != ws.lds_floats || ws.graph_dem != ws.demands ||
+            ws.graph_af != ws.alpha_fair) {
             if (ws.gexec) (void)hipGraphExecDestroy(ws.gexec);
             if (ws.graph) (void)hipGraphDestroy(ws.graph);
             ws.gexec = nullptr;
@@ -1426,6 +1430,8 @@ ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
             ws.graph_grid = grid;
             ws.graph_tf = ws.tf;
             ws.graph_lds = ws.lds_floats;
+            ws.graph_dem = ws.demands;
+            ws.graph_af = ws.alpha_fair;
         }
         RA_HIP(ctx, hipGraphLaunch(ws.gexec, ctx->stream));
     } else {
@@ -1728,10 +1734,21 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
         loops.emplace_back(P[b]->m, P[b]->n, P[b]->R.data(), ob, p0.data());
     }
 
-    // enough waves for any launch shape (at most 8 blocks of 4 waves per CU)
+    // enough waves for any launch shape (at most 8 blocks of 4 waves per CU);
+    // the workspace (device tables, partial slots, pinned results, captured
+    // graph) stays with the context for later batches of at most its size
     const int Wmax = ctx->cus * 8 * 4;
-    BatchWs ws;
-    if (batch_alloc(ctx, ws, B, Wmax) != RA_OK) return RA_ENOMEM;
+    BatchWs* wsp = static_cast<BatchWs*>(ctx->batch_ws.get());
+    if (!wsp || wsp->B < B || wsp->Wmax != Wmax) {
+        ctx->batch_ws.reset();
+        std::shared_ptr<BatchWs> nw = std::make_shared<BatchWs>();
+        if (batch_alloc(ctx, *nw, B, Wmax) != RA_OK) return RA_ENOMEM;
+        ctx->batch_ws = nw;
+        wsp = nw.get();
+    }
+    BatchWs& ws = *wsp;
+    ws.demands = false;
+    ws.alpha_fair = false;
     for (int b = 0; b < B; ++b) {
         ws.demands = ws.demands || P[b]->dem != nullptr;
         ws.alpha_fair = ws.alpha_fair || P[b]->alpha_fair;

@@ -298,3 +298,30 @@ def test_batched_tuner_record_and_cache(torch, tmp_path, monkeypatch):
             pr.close()
     finally:
         ctx2.close()
+
+
+def test_batched_workspace_reuse_across_variants(torch):
+    """One context runs batches of different sizes and kernel variants (with
+    and without alpha-fair jobs, a larger batch after a smaller one): its
+    reused workspace and captured graph give every batch its own variant's
+    results, checked against the oracle."""
+    import paper_2104_00282_amd as ra
+    ctx = ra.Context(0)
+    try:
+        base = _batch_instances()
+        for k, (sel, af) in enumerate([(slice(0, 4), False), (slice(0, 4), True),
+                                       (slice(0, 12), False), (slice(2, 7), True),
+                                       (slice(0, 12), True)]):
+            insts = base[sel]
+            if af:
+                insts = _with_alpha_fair([synth.random_small(I.n, I.m, seed=3000 + j,
+                                                             dtype=np.float32)
+                                          for j, I in enumerate(insts)], 80 + k)
+            print("workspace reuse: batch %d (%d problems, alpha-fair %s)" % (k, len(insts), af),
+                  flush=True)
+            probs = _problems(ctx, torch, insts)
+            _two_pass_check(probs, insts, seed=20 + k)
+            for pr in probs:
+                pr.close()
+    finally:
+        ctx.close()
