@@ -107,6 +107,30 @@ def test_warm_start_and_subgradient(ctx, torch):
     assert info3["rel_gap"] < gap0 and info3["fell_back"] == info3["iters"]
 
 
+def test_checkpoint_resume(ctx, torch):
+    """The prices are the whole state of the method (§5: the first price
+    vector can be anything): a solve stopped after a few iterations and
+    resumed from its returned prices reaches the tolerance, and the
+    certificate of the resumed solve holds under the oracle."""
+    I = synth.random_small(30000, 8, seed=47, dtype=np.float32, log_frac=1.0)
+    prob = _problem(ctx, torch, I)
+    p_full, i_full, _ = prob.solve(tol_rel=1e-4, max_iter=300)
+    assert i_full["converged"] == 1
+    p_cut, i_cut, st_cut = prob.solve(tol_rel=1e-4, max_iter=3)
+    assert i_cut["converged"] == 0 and i_cut["iters"] == 3
+    p_res, i_res, st_res = prob.solve(p0=p_cut, tol_rel=1e-4, max_iter=300)
+    assert i_res["converged"] == 1 and i_res["rel_gap"] <= 1e-4
+    # resuming costs about what the rest of the uninterrupted solve costs
+    assert i_cut["dual_evals"] + i_res["dual_evals"] <= 2 * i_full["dual_evals"] + 10
+    d = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p_res, per_job=True)
+    U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, d.r, d.jobs)
+    assert abs(i_res["g"] - d.g) <= 1e-5 * (abs(d.g) + abs(U))
+    assert abs(i_res["U_lb"] - U) <= 1e-5 * (abs(d.g) + abs(U))
+    # the oracle's gap at the returned prices: the tolerance, up to the FP32
+    # rounding of the two sums (1e-5 of each)
+    assert (d.g - U) / max(abs(d.g), abs(U)) <= 1e-4 + 2e-5 * (abs(d.g) + abs(U)) / abs(d.g)
+
+
 def test_allocation_matches_certificate(ctx, torch):
     I = synth.random_small(30000, 8, seed=45, dtype=np.float32)
     prob = _problem(ctx, torch, I)
