@@ -1244,9 +1244,6 @@ ra_status batch_alloc(ra_ctx* ctx, BatchWs& ws, int B, int Wmax)
     return RA_OK;
 }
 
-// Fill the tables of one round for the active problems `act` (ascending) with
-// W waves: items, prices (next point and, if any, the point to certify),
-// byte-balanced per-wave tile chunks, partial slots.  Returns the tile count.
 // Spread per-problem work over the context's host threads when there is
 // enough of it; fn(lo, hi) handles problems [lo, hi).
 void for_problems(ra::HostPool* pool, int A, const std::function<void(int, int)>& fn)
