@@ -202,13 +202,13 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_warmstart(args):
+def warmstart_run(args):
     """Learned warm start: train the network on `train_count` instances
     (n = train_n, m = 16) solved by the batched solver, then compare time to
     each fresh instance's gap target (n = eval_n) from p = 1 and from the
     network's prediction (with the cold-restart fallback), plus a constant
-    predictor (the training mean) as ablation."""
-    import torch
+    predictor (the training mean) as ablation.  Returns the JSON line as a
+    dict."""
     import paper_2104_00282_amd as ra
     from paper_2104_00282_amd import warmstart as ws
 
@@ -265,7 +265,31 @@ def bench_warmstart(args):
     net.close()
     const.close()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_warmstart(args):
+    """The learned warm start (warmstart_run) as its own JSON line."""
+    print(json.dumps(warmstart_run(args)), flush=True)
+
+
+def warmstart_digest(res):
+    """The learned-start figures the default benchmark line carries: per gap
+    level, warm-vs-cold speedup in total time, instances reaching the target
+    per arm, median passes, fallback rate."""
+    s = res["summary"]
+    out = {"workload": res["config"]["workload"], "stop": res["config"]["stop"],
+           "floor_median": s["floor_median"], "floor_any_median": s.get("floor_any_median")}
+    for lv in ("0.001", "0.0001", "floor", "floor_any"):
+        L = s[lv]
+        out["to_" + lv] = {
+            "speedup_total": L["speedup_total"], "speedup_median": L["speedup_median"],
+            "reached": {a: L[a]["reached"] for a in ("cold", "warm", "paper", "const", "near")
+                        if a in L},
+            "passes_median": {a: L[a]["evals_median"] for a in ("cold", "warm") if a in L},
+            "fallback_rate": L["fallback_rate"],
+        }
+    return out
 
 
 def bench_solves(args):
@@ -798,6 +822,8 @@ def main():
                     help="skip the time-to-gap leg of the default workload")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-loop leg of the default workload")
+    ap.add_argument("--no-warmstart", action="store_true",
+                    help="skip the learned-warm-start leg of the default workload")
     ap.add_argument("--n", type=int, default=10_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy used to scale the HBM counters")
@@ -959,6 +985,11 @@ def main():
             "speedup", "loop_seconds", "batched_seconds", "loop_reached", "batched_reached",
             "floor_median", "targets_at_1e-6")}
         out["config"]["batched_vs_loop"]["workload"] = b["config"]["workload"]
+    if not args.no_warmstart:
+        # the learned warm start (1,000 fresh n = 1e6, m = 16 instances),
+        # outside the timed region: time to each gap level, warm vs cold
+        log("learned warm start")
+        out["config"]["learned_warm_start"] = warmstart_digest(warmstart_run(args))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(p2)
