@@ -226,7 +226,7 @@ def warmstart_run(args):
     rows = ws.evaluate(ctx, net, args.eval_count, args.eval_n, m, seed0=synth_seed(200000),
                        const_net=const, ref_stall_evals=args.stall_evals,
                        stall_evals=args.arm_stall_evals, stall_restarts=args.stall_restarts,
-                       near_sigma=0.03, log=log)
+                       warm_stall_restarts=args.warm_stall_restarts, near_sigma=0.03, log=log)
     s = ws.summarize(rows)
     out = {
         "metric": "time to a 1e-4 relative gap, learned warm start vs cold start (also 1e-3 and "
@@ -248,7 +248,9 @@ def warmstart_run(args):
                        "three reference runs (from p = 1, the paper's start and the network's "
                        "prediction; level floor_any)",
             "fallback": "cold restart when the certified gap has not fallen below the first "
-                        "certificate within 5 certificates",
+                        "certificate within 5 certificates, or (learned solves) when the warm "
+                        "run stalls short of the target after %d restarts"
+                        % args.warm_stall_restarts,
             "ablations": "const: the training mean of log p as the prediction; near: the p = 1 "
                          "reference run's prices times exp(0.03 z) (closer to p* than the "
                          "network), with the learned start's first step",
@@ -279,6 +281,7 @@ def warmstart_digest(res):
     per arm, median passes, fallback rate."""
     s = res["summary"]
     out = {"workload": res["config"]["workload"], "stop": res["config"]["stop"],
+           "fallback": res["config"]["fallback"],
            "floor_median": s["floor_median"], "floor_any_median": s.get("floor_any_median")}
     for lv in ("0.001", "0.0001", "floor", "floor_any"):
         L = s[lv]
@@ -288,6 +291,7 @@ def warmstart_digest(res):
                         if a in L},
             "passes_median": {a: L[a]["evals_median"] for a in ("cold", "warm") if a in L},
             "fallback_rate": L["fallback_rate"],
+            "stall_fallback_rate": L["stall_fallback_rate"],
         }
     return out
 
@@ -845,6 +849,9 @@ def main():
                     help="stall window of the timed solves")
     ap.add_argument("--stall-restarts", type=int, default=5,
                     help="stalls of a timed solve that restart from its best certified point")
+    ap.add_argument("--warm-stall-restarts", type=int, default=2,
+                    help="learned solves: stall restarts of the warm run before it hands over "
+                         "to a cold solve (-1: never)")
     ap.add_argument("--train-count", type=int, default=20000)
     ap.add_argument("--train-n", type=int, default=100000)
     ap.add_argument("--eval-count", type=int, default=1000)

@@ -200,6 +200,15 @@ typedef struct {
                                 step of init_step (a new approach to the optimum,
                                 which can certify a tighter gap) instead of
                                 stopping; the next stall stops                    */
+    int32_t warm_stall_restarts; /* ra_solve_learned only (others ignore it):
+                                -1 = off; >= 0: the warm run restarts on its first
+                                this many stalls, and if it stalls once more
+                                without meeting the tolerance, a cold solve from
+                                p = 1 with stall_restarts follows (another path
+                                to the optimum, another chance of a tight
+                                certificate); the result is the better certified
+                                point of the two runs, and max_evals bounds
+                                their passes together                            */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
@@ -215,14 +224,17 @@ typedef struct {
     double U_lb;             /* U(X~) at the returned prices (lower bound)           */
     double rel_gap;          /* (g - U_lb) / max(|g|, |U_lb|)                         */
     double seconds;          /* wall time of the call                                */
-    int32_t restarted;       /* 1 if a learned warm start was abandoned for p = 1    */
-    int32_t warm_evals;      /* passes spent on an abandoned warm start              */
+    int32_t restarted;       /* a learned warm start was followed by a solve from
+                                p = 1: 1 = abandoned after fallback_window
+                                certificates, 2 = it stalled (warm_stall_restarts);
+                                0 otherwise                                       */
+    int32_t warm_evals;      /* passes of the warm run when restarted != 0           */
 } ra_solve_info;
 
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
  * stall_evals = 0 (off), init_step = 0 (default step), tol_abs = 0 (off),
- * device_loop = 0, stall_restarts = 0. */
+ * device_loop = 0, stall_restarts = 0, warm_stall_restarts = -1 (off). */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
 /* Per-job demands (§7, "Extensions and variations"): the usage limit becomes
@@ -396,7 +408,10 @@ ra_status ra_mlp_load(ra_ctx *ctx, const char *path, ra_mlp **out);
  * point (or any value is non-finite), the warm
  * run is abandoned and the solve restarts from p = 1 (info->restarted = 1,
  * info->warm_evals = passes spent before the restart, included in
- * dual_evals and seconds).  The network's out_dim must equal the problem's m. */
+ * dual_evals and seconds).  With opts->warm_stall_restarts >= 0, a warm run
+ * that stalls short of the tolerance is followed by a solve from p = 1 in the
+ * same way (info->restarted = 2).  The network's out_dim must equal the
+ * problem's m. */
 ra_status ra_solve_learned(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp,
                            const ra_solve_opts *opts, int32_t fallback_window, double *p_out,
                            ra_solve_info *info);

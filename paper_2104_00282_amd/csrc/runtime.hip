@@ -632,6 +632,7 @@ void ra_solve_opts_default(ra_solve_opts* o)
     o->tol_abs = 0.0;
     o->device_loop = 0;
     o->stall_restarts = 0;
+    o->warm_stall_restarts = -1;
 }
 
 static bool valid_opts(const ra_solve_opts& o)
@@ -640,7 +641,8 @@ static bool valid_opts(const ra_solve_opts& o)
            o.lbfgs_mem >= 1 && o.lbfgs_mem <= 64 && (o.method == 0 || o.method == 1) &&
            (o.init >= 0 && o.init <= 2) && o.init_step >= 0.0 && o.init_step <= 10.0 &&
            o.tol_abs >= 0.0 && std::isfinite(o.tol_abs) &&
-           (o.device_loop == 0 || o.device_loop == 1) && o.stall_restarts >= 0;
+           (o.device_loop == 0 || o.device_loop == 1) && o.stall_restarts >= 0 &&
+           o.warm_stall_restarts >= -1;
 }
 
 namespace {
@@ -1049,21 +1051,22 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
     bool warm_ok = true;
     for (double v : p0) warm_ok = warm_ok && std::isfinite(v) && v >= 0.0;
     int warm_evals = 0;
-    bool restarted = !warm_ok;
+    // 1: the warm run was abandoned early (or could not start), 2: it stalled
+    int restarted = warm_ok ? 0 : 1;
     std::vector<double> pe, rr;
     double gv = 0.0, sdu = 0.0;
-    const ra::Point* out = nullptr;
     // a predicted start is expected within a few percent of p*: the first
     // step is kept to that scale so that it does not undo the prediction
     ra_solve_opts ow = o;
     if (ow.init_step == 0.0) ow.init_step = 0.02;
+    if (o.warm_stall_restarts >= 0) ow.stall_restarts = o.warm_stall_restarts;
     ra::PriceLoop W(m, P->n, P->R.data(), ow, warm_ok ? p0.data() : std::vector<double>(m, 1.0).data());
     if (warm_ok) {
         double rel0 = INFINITY;
         while (!W.done()) {
             st = run_pass(P, W.next(), W.pending(), graph, pe, gv, rr, sdu);
             if (st == RA_ENUMERIC) {
-                restarted = true;
+                restarted = 1;
                 break;
             }
             if (st != RA_OK) return st;
@@ -1071,22 +1074,27 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
             if (W.ncertified() == 1 && !std::isfinite(rel0)) rel0 = W.last_certified().rel;
             if (W.ncertified() >= window && !W.done()) {
                 const double best = W.result().certified ? W.result().rel : INFINITY;
-                if (!(best < rel0)) restarted = true;  // the gap did not fall: go cold
+                if (!(best < rel0)) restarted = 1;  // the gap did not fall: go cold
                 break;
             }
         }
-        warm_evals = W.evals();
         if (!restarted) {
             while (!W.done()) {
                 st = run_pass(P, W.next(), W.pending(), graph, pe, gv, rr, sdu);
                 if (st != RA_OK) return st;
                 W.feed(pe, gv, rr.data(), sdu);
             }
-            out = &W.result();
+            // a warm run that stalled short of the tolerance hands over to a
+            // cold solve while the pass budget lasts
+            if (o.warm_stall_restarts >= 0 && W.stalled() && !W.converged() &&
+                (o.max_evals == 0 || W.evals() < o.max_evals))
+                restarted = 2;
         }
+        warm_evals = W.evals();
     }
     ra_solve_opts oc = o;
     oc.init = 0;
+    if (restarted && o.max_evals > 0) oc.max_evals = o.max_evals - warm_evals;  // >= 1
     std::vector<double> ones(m, 1.0);
     ra::PriceLoop C(m, P->n, P->R.data(), oc, ones.data());
     if (restarted) {
@@ -1095,23 +1103,31 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
             if (st != RA_OK) return st;
             C.feed(pe, gv, rr.data(), sdu);
         }
-        out = &C.result();
     }
     RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    const ra::PriceLoop& L = restarted ? C : W;
+    // the outcome: the warm run's, the cold run's after an early abandon, and
+    // after a stall the better certified point of the two
+    const ra::PriceLoop* L = restarted ? &C : &W;
+    if (restarted == 2) {
+        const ra::Point& a = W.result();
+        const ra::Point& b = C.result();
+        if (!C.converged() && a.certified && (!b.certified || a.rel <= b.rel)) L = &W;
+    }
+    const ra::Point* out = &L->result();
     for (int j = 0; j < m; ++j) p_out[j] = out->p[j];
-    const bool conv = L.converged();
+    const bool conv = L->converged();
     if (info) {
-        info->iters = L.iters();
-        info->dual_evals = L.evals() + (restarted ? warm_evals : 0);
-        info->fell_back = L.fallbacks();
+        // a run that never started counts zero
+        info->iters = W.iters() + C.iters();
+        info->dual_evals = W.evals() + C.evals();
+        info->fell_back = W.fallbacks() + C.fallbacks();
         info->converged = conv ? 1 : 0;
         info->g = out->g;
         info->U_lb = out->certified ? out->U : NAN;
         info->rel_gap = out->certified ? out->rel : INFINITY;
         info->seconds =
             std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        info->restarted = restarted ? 1 : 0;
+        info->restarted = restarted;
         info->warm_evals = restarted ? warm_evals : 0;
     }
     return conv ? RA_OK : RA_ENOTCONV;

@@ -103,8 +103,8 @@ LEVELS = (1e-3, 1e-4, "floor", "floor_any")
 
 
 def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters=300,
-             ref_stall_evals=100, stall_evals=30, stall_restarts=5, max_iter=500,
-             fallback_window=5, levels=LEVELS, near_sigma=0.0, log=None):
+             ref_stall_evals=100, stall_evals=30, stall_restarts=5, warm_stall_restarts=2,
+             max_iter=500, fallback_window=5, levels=LEVELS, near_sigma=0.0, log=None):
     """Cold start (p = 1), the paper's data-dependent start and the learned
     warm start (and optionally a constant predictor) on fresh instances, to each
     relative-gap level of `levels` separately ("floor" = max(1e-6, 1.5 x the
@@ -117,7 +117,10 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
     The reference runs stop when their best gap has not improved within
     ref_stall_evals passes; the timed arms, all alike, when it has not
     improved within stall_evals passes for the (stall_restarts + 1)-th time,
-    the earlier stalls restarting the update from the best certified point.
+    the earlier stalls restarting the update from the best certified point;
+    the learned solves (warm and const) restart warm_stall_restarts times and
+    then, if still short of the target, continue with the cold solve
+    (warm_stall_restarts = -1: no such fallback).
     near_sigma > 0 adds the arm "near": a start at the p = 1 reference run's
     prices times exp(near_sigma z), z standard normal (seeded per instance),
     closer to p* than any prediction, which shows how much a target tied to
@@ -157,7 +160,8 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
                 kw = dict(tol_rel=tol, max_iter=max_iter, stall_evals=stall_evals,
                           stall_restarts=stall_restarts)
                 arms["cold"] = pr.solve(**kw)[1]
-                arms["warm"] = pr.solve_learned(net, fallback_window=fallback_window, **kw)[1]
+                arms["warm"] = pr.solve_learned(net, fallback_window=fallback_window,
+                                                warm_stall_restarts=warm_stall_restarts, **kw)[1]
                 arms["paper"] = pr.solve(paper_init=True, **kw)[1]
                 if near_sigma > 0:
                     z = np.random.default_rng(seed0 + g0 + k).standard_normal(m)
@@ -165,6 +169,7 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
                                             init_step=0.02, **kw)[1]
                 if const_net is not None:
                     arms["const"] = pr.solve_learned(const_net, fallback_window=fallback_window,
+                                                     warm_stall_restarts=warm_stall_restarts,
                                                      **kw)[1]
                 arms["target"] = tol
                 row[str(lv)] = arms
@@ -197,11 +202,13 @@ def summarize(rows, levels=LEVELS):
                 "evals_median": float(np.median(col(arm, "dual_evals"))),
                 "evals_mean": float(np.mean(col(arm, "dual_evals"))),
                 "reached": int(col(arm, "converged").sum()),
-                "restarted": int(col(arm, "restarted").sum()),
+                "restarted": int((col(arm, "restarted") > 0).sum()),
+                "stall_fallbacks": int((col(arm, "restarted") == 2).sum()),
             }
         lvl["speedup_total"] = lvl["cold"]["seconds_total"] / lvl["warm"]["seconds_total"]
         lvl["speedup_median"] = float(np.median(col("cold", "seconds") / col("warm", "seconds")))
         lvl["fallback_rate"] = lvl["warm"]["restarted"] / len(rows)
+        lvl["stall_fallback_rate"] = lvl["warm"]["stall_fallbacks"] / len(rows)
         lvl["paper_speedup_total"] = lvl["cold"]["seconds_total"] / lvl["paper"]["seconds_total"]
         lvl["warm_vs_paper_total"] = lvl["paper"]["seconds_total"] / lvl["warm"]["seconds_total"]
         if "const" in lvl:

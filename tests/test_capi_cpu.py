@@ -47,6 +47,38 @@ def test_binding_names_match_header():
     assert set(_capi.PROTOTYPES) == set(declared_functions())
 
 
+def test_binding_structs_match_header_layout(tmp_path):
+    """The ctypes mirrors of ra_solve_opts and ra_solve_info have the C
+    compiler's size and field offsets (a field added to one side only would
+    shift every later field)."""
+    from paper_2104_00282_amd import _capi
+    structs = (_capi.ra_solve_opts, _capi.ra_solve_info)
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "resalloc.h"',
+             "int main(void) {"]
+    for st in structs:
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (st.__name__, st.__name__))
+        for f, _ in st._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));'
+                         % (st.__name__, f, st.__name__, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src),
+                           "-o", exe])
+    got = dict(l.split() for l in subprocess.check_output([exe], text=True).splitlines())
+    for st in structs:
+        assert int(got[st.__name__]) == ctypes.sizeof(st), st.__name__
+        for f, _ in st._fields_:
+            assert int(got["%s.%s" % (st.__name__, f)]) == getattr(st, f).offset, (st, f)
+    # and every field the header declares is mirrored, in order
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    for st in structs:
+        body = re.search(r"typedef struct \{([^}]*)\}\s*%s;" % st.__name__, text).group(1)
+        names = re.findall(r"\b(\w+)\s*;", body)
+        assert names == [f for f, _ in st._fields_], st.__name__
+
+
 def test_status_strings_and_defaults(lib):
     import paper_2104_00282_amd as ra
     assert ra.ra_status_string(ra.RA_OK) == "ok"
@@ -54,8 +86,8 @@ def test_status_strings_and_defaults(lib):
     assert ra.ra_status_string(99) == "unknown status"
     o = ra.ra_solve_opts_default()
     assert (o.tol_rel, o.max_iter, o.lbfgs_mem, o.method, o.init, o.use_graph, o.max_evals,
-            o.stall_evals, o.init_step, o.tol_abs, o.device_loop, o.stall_restarts) == \
-        (1e-6, 500, 10, 0, 0, 1, 0, 0, 0.0, 0.0, 0, 0)
+            o.stall_evals, o.init_step, o.tol_abs, o.device_loop, o.stall_restarts,
+            o.warm_stall_restarts) == (1e-6, 500, 10, 0, 0, 1, 0, 0, 0.0, 0.0, 0, 0, -1)
 
 
 def test_null_arguments_rejected_without_device(lib):

@@ -37,10 +37,10 @@ def test_trained_network_gains_over_cold_start():
     lv = s["0.001"]
     assert lv["warm"]["evals_median"] < lv["cold"]["evals_median"]
     assert lv["warm"]["reached"] >= lv["cold"]["reached"] - 1
-    # at the floor-bound target the arms restart from their best certified
-    # point when they stall, so they reach it about as often
+    # at the floor-bound target a learned solve that stalls short of it hands
+    # over to the cold solve, so it reaches every target the cold arm reaches
     lf = s["floor_any"]
-    assert lf["warm"]["reached"] >= lf["cold"]["reached"] - 2
+    assert lf["warm"]["reached"] >= lf["cold"]["reached"]
     # certificates of warm solves, re-evaluated by the oracle on a host copy:
     # at the evaluation size of the test and at the full evaluation size of
     # the learned-start configuration (n = 1e6, m = 16)
