@@ -207,6 +207,28 @@ __device__ __forceinline__ int scan_next(const Row& a, int mm, const Px& px, F a
     return jn;
 }
 
+// Next envelope vertex after a free vertex (ac, 0): the smallest slope
+// p_j / (a_j - ac) over a_j > ac is the largest key (a_j - ac) * (1/p_j),
+// one subtraction and one product per entry instead of scan_next's
+// cross-multiplied comparison.  Keys of a_j <= ac are <= 0 and never win;
+// a free resource has a_j <= ac (the free vertex has the largest free a_j),
+// so its key is -inf or NaN and never wins either.  Lowest j on equal keys;
+// -1 if no resource lies beyond ac.
+template <int M, class Row, class Px>
+__device__ __forceinline__ int scan_next_free(const Row& a, const Px& px, float ac)
+{
+    float best = 0.f;
+    int jn = -1;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const float key = (a.get(j) - ac) * px.inv(j);
+        const bool b = key > best;
+        best = b ? key : best;
+        jn = b ? j : jn;
+    }
+    return jn;
+}
+
 // Maximiser of u(t) minus the cost on the envelope segment from (alo, plo) to
 // (ahi, phi) (§4.2), of slope alpha = (phi - plo) / (ahi - alo):
 //   log, eq. e-opt-t-log: clip((u')^{-1}(alpha), alo, ahi) with
@@ -494,9 +516,10 @@ __device__ __forceinline__ Seg<float> first_segment(const Row& a, const Px& px, 
 // resource with the largest throughput a_F (scan_first's rule), found by a
 // pass over the free entries alone (the index test is wave-uniform) that
 // also takes the row's largest throughput; when the maximiser passes a_F,
-// the next vertex from (a_F, 0) comes from one scan_next, which a later
-// walk round would otherwise do.  Rows with no free throughput (a_j = 0 on
-// every free resource) take the first vertex by efficiency per price.
+// the next vertex from (a_F, 0) comes from one scan, which a later
+// walk round would otherwise do (scan_next_free).  Rows with no free
+// throughput (a_j = 0 on every free resource) take the first vertex by
+// efficiency per price.
 // Every lane of the wave must call it together.
 template <int M, bool AF, class Row, class Px>
 __device__ __forceinline__ Seg<float> free_start(const Row& a, const Px& px, float w, float c,
@@ -524,7 +547,7 @@ __device__ __forceinline__ Seg<float> free_start(const Row& a, const Px& px, flo
     Seg<float> S = first_segment<AF>(a, px, j1, amax, w, c, caplin, eps, walking);
     const bool from_free = walking & (jF >= 0);
     if (__ballot(from_free) != 0ull) {
-        const int jn = scan_next<float, M>(a, M, px, S.ahi, S.phi);
+        const int jn = scan_next_free<M>(a, px, S.ahi);
         if (from_free) {
             if (jn < 0) {
                 walking = false;
