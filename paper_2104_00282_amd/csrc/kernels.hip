@@ -1391,6 +1391,18 @@ __global__ void __launch_bounds__(256, batch_min_blocks(TF, DEM))
 // *flag = 1.
 constexpr int BATCH_RED_GROUPS = 7;  // 7 x 35 lanes of a 256-lane block
 
+// A round's table from pinned host memory (read over the bus, each 16-byte
+// word once) to device memory: a kernel launch, which queues behind the
+// stream's earlier work without holding the host, unlike a small
+// host-to-device copy.
+__global__ void __launch_bounds__(256) k_copy_table(const uint4* __restrict__ src,
+                                                    uint4* __restrict__ dst, int64_t n16)
+{
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n16;
+         k += (int64_t)gridDim.x * 256)
+        dst[k] = src[k];
+}
+
 __global__ void __launch_bounds__(256) k_batch_reduce(const double* __restrict__ partial,
                                                       const int* __restrict__ seg,
                                                       const int* __restrict__ header,
@@ -1978,6 +1990,17 @@ hipError_t launch_batch(int tf, int lds_floats, int grid, int max_items, hipStre
         launch_batch_tf<false, false>(tf, lds_floats, grid, st, items, prices, chunk, segbase, partial);
     const int rgrid = max_items < 256 ? max_items : 256;
     k_batch_reduce<<<rgrid, 256, 0, st>>>(partial, seg, header, out, ticket, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_table(const void* host_src, void* dst, size_t bytes, hipStream_t st)
+{
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return hipSuccess;
+    const int64_t want = (n16 + 255) / 256;
+    const int grid = (int)(want < 256 ? want : 256);
+    k_copy_table<<<grid, 256, 0, st>>>(static_cast<const uint4*>(host_src), static_cast<uint4*>(dst),
+                                       n16);
     return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ struct ra_ctx {
     ra::BatchTuned batch_fixed_shape;
     std::string batch_tune_log;
     std::shared_ptr<void> batch_ws;  // the batched solver's workspace, reused by later batches
+    std::shared_ptr<void> batch_ws2;  // the second group's workspace (batches of 16 or more)
     std::unique_ptr<ra::HostPool> pool;      // host threads of the batched solver
     void* feat_ws = nullptr;  // warm-start features: sampled keys and block partials
 };

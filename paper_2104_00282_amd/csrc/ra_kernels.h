@@ -94,6 +94,9 @@ hipError_t launch_batch(int tf, int lds_floats, int grid, int max_items, hipStre
                         const int* segbase, const int* seg, const int* header, double* partial,
                         double* out, unsigned* ticket = nullptr, unsigned* flag = nullptr,
                         bool demands = false, bool alpha_fair = true);
+// Copy `bytes` (a multiple of 16) from pinned, device-visible host memory to
+// device memory with a kernel on stream st.
+hipError_t launch_copy_table(const void* host_src, void* dst, size_t bytes, hipStream_t st);
 
 // Number of blocks one dual-kernel launch uses for n jobs with m resources
 // (dv: with per-job demand vectors).

@@ -371,6 +371,7 @@ static void free_ctx(ra_ctx* ctx)
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     (void)hipFree(ctx->feat_ws);
     ctx->batch_ws.reset();  // waits for its launches on the stream
+    ctx->batch_ws2.reset();
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -1188,8 +1189,14 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 struct BatchWs {
     int B = 0, Wmax = 0;
+    // table sections (offsets into htab / dtab) of the current layout;
+    // tab_bytes is the allocation, tab_used what a round copies
     size_t off_items = 0, off_prices = 0, off_chunk = 0, off_segbase = 0, off_seg = 0,
-           off_header = 0, tab_bytes = 0;
+           off_header = 0, tab_bytes = 0, tab_used = 0;
+    // compact: each round lays its table out for its own wave and problem
+    // counts (the copy then moves only what the round uses); otherwise the
+    // layout is the fixed one of the allocation, as a captured graph needs
+    bool compact = false;
     char* dtab = nullptr;
     char* htab = nullptr;
     double* partial = nullptr;
@@ -1224,6 +1231,26 @@ struct BatchWs {
     int* segbase() { return reinterpret_cast<int*>(htab + off_segbase); }
     int* seg() { return reinterpret_cast<int*>(htab + off_seg); }
     int* header() { return reinterpret_cast<int*>(htab + off_header); }
+    // section offsets for W waves and A problems: header, chunk (W + 1),
+    // segbase (W + 1), seg (2 A), items (A + 1), prices (A rows of
+    // 6 BATCH_MAX_M floats)
+    void layout(int W, int A)
+    {
+        size_t o = 0;
+        off_header = o;
+        o = align16(o + sizeof(int) * 4);
+        off_chunk = o;
+        o = align16(o + sizeof(int) * (size_t)(W + 1));
+        off_segbase = o;
+        o = align16(o + sizeof(int) * (size_t)(W + 1));
+        off_seg = o;
+        o = align16(o + sizeof(int) * 2 * (size_t)A);
+        off_items = o;
+        o = align16(o + sizeof(ra::BatchItem) * (size_t)(A + 1));
+        off_prices = o;
+        o = align16(o + sizeof(float) * 6 * ra::BATCH_MAX_M * (size_t)A);
+        tab_used = o;
+    }
 };
 
 ra_status batch_alloc(ra_ctx* ctx, BatchWs& ws, int B, int Wmax)
@@ -1232,22 +1259,12 @@ ra_status batch_alloc(ra_ctx* ctx, BatchWs& ws, int B, int Wmax)
     ws.st_sync = ctx->stream;
     ws.B = B;
     ws.Wmax = Wmax;
-    size_t o = 0;
-    ws.off_items = o;
-    o = align16(o + sizeof(ra::BatchItem) * (size_t)(B + 1));
-    ws.off_prices = o;
-    o = align16(o + sizeof(float) * 6 * ra::BATCH_MAX_M * (size_t)B);
-    ws.off_chunk = o;
-    o = align16(o + sizeof(int) * (size_t)(Wmax + 1));
-    ws.off_segbase = o;
-    o = align16(o + sizeof(int) * (size_t)(Wmax + 1));
-    ws.off_seg = o;
-    o = align16(o + sizeof(int) * 2 * (size_t)B);
-    ws.off_header = o;
-    o = align16(o + sizeof(int) * 4);
-    ws.tab_bytes = o;
+    // the fixed layout is the largest: every compact one fits in it
+    ws.layout(Wmax, B);
+    ws.tab_bytes = ws.tab_used;
     RA_HIP(ctx, hipMalloc(&ws.dtab, ws.tab_bytes));
-    RA_HIP(ctx, hipHostMalloc((void**)&ws.htab, ws.tab_bytes, hipHostMallocDefault));
+    // coherent: the table copy kernel reads it over the bus
+    RA_HIP(ctx, hipHostMalloc((void**)&ws.htab, ws.tab_bytes, hipHostMallocCoherent));
     std::memset(ws.htab, 0, ws.tab_bytes);
     RA_HIP(ctx, hipMalloc(&ws.partial,
                           sizeof(double) * ra::BATCH_COLS * (size_t)(Wmax + B)));
@@ -1292,6 +1309,10 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
                    const ra::BatchTuned& T, bool force_prev = false)
 {
     const int A = (int)act.size();
+    if (ws.compact)
+        ws.layout(W, A);
+    else
+        ws.layout(ws.Wmax, ws.B);
     ra::BatchItem* it = ws.items();
     float* pr = ws.prices();
     std::vector<int64_t> tiles(A);
@@ -1401,8 +1422,17 @@ int64_t batch_fill(BatchWs& ws, const std::vector<ra_problem*>& probs,
 ra_status batch_enqueue(ra_ctx* ctx, BatchWs& ws, int grid)
 {
     hipStream_t st = ctx->stream;
-    RA_HIP(ctx, hipMemcpyAsync(ws.dtab, ws.htab, ws.tab_bytes, hipMemcpyHostToDevice, st));
-    RA_HIP(ctx, ra::launch_batch(ws.tf, ws.lds_floats, grid, ws.B, st,
+    // a compact round's table is copied by a kernel (launched without
+    // holding the host); a captured graph keeps its copy node
+    if (ws.compact)
+        RA_HIP(ctx, ra::launch_copy_table(ws.htab, ws.dtab, ws.tab_used, st));
+    else
+        RA_HIP(ctx, hipMemcpyAsync(ws.dtab, ws.htab, ws.tab_used, hipMemcpyHostToDevice, st));
+    // the reduction takes a block per active problem (up to 256); every
+    // block raises a system-wide fence, so a compact round launches no idle
+    // ones (a captured graph keeps the capacity)
+    const int red_items = ws.compact ? std::max(1, ws.header()[0]) : ws.B;
+    RA_HIP(ctx, ra::launch_batch(ws.tf, ws.lds_floats, grid, red_items, st,
                                  reinterpret_cast<const ra::BatchItem*>(ws.dtab + ws.off_items),
                                  reinterpret_cast<const float*>(ws.dtab + ws.off_prices),
                                  reinterpret_cast<const int*>(ws.dtab + ws.off_chunk),
@@ -1413,10 +1443,14 @@ ra_status batch_enqueue(ra_ctx* ctx, BatchWs& ws, int grid)
     return RA_OK;
 }
 
-ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
+// Queue one round (table copy, batched kernel, reduction) on the context's
+// stream, from a captured graph when use_graph (fixed layout only), and
+// return without waiting: the round raises ws.hflag when its results are in
+// ws.hout.
+ra_status batch_launch(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
 {
     __atomic_store_n(ws.hflag, 0u, __ATOMIC_RELEASE);
-    if (use_graph && !ctx->timing) {
+    if (use_graph && !ctx->timing && !ws.compact) {
         if (!ws.gexec || ws.graph_grid != grid || ws.graph_tf != ws.tf ||
             ws.graph_lds != ws.lds_floats || ws.graph_dem != ws.demands ||
             ws.graph_af != ws.alpha_fair) {
@@ -1447,12 +1481,11 @@ ra_status batch_run(ra_ctx* ctx, BatchWs& ws, int grid, bool use_graph)
             ws.graph_af = ws.alpha_fair;
         }
         RA_HIP(ctx, hipGraphLaunch(ws.gexec, ctx->stream));
-    } else {
-        ra_status s = batch_enqueue(ctx, ws, grid);
-        if (s != RA_OK) return s;
+        return RA_OK;
     }
-    return wait_flag(ctx, ws.hflag);
+    return batch_enqueue(ctx, ws, grid);
 }
+
 
 std::string batch_signature(const std::vector<ra_problem*>& probs, bool demands, bool alpha_fair)
 {
@@ -1472,6 +1505,9 @@ std::string batch_signature(const std::vector<ra_problem*>& probs, bool demands,
 }
 
 const int kBatchMs[4] = {4, 8, 16, 32};
+
+// batches of at least this many problems run as two interleaved groups
+const int kBatchGroupsMin = 16;
 
 // A shape is usable for a batch when every m class present has a valid tile
 // height under the shape's budget.
@@ -1750,23 +1786,42 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     // enough waves for any launch shape (at most 8 blocks of 4 waves per CU);
     // the workspace (device tables, partial slots, pinned results, captured
     // graph) stays with the context for later batches of at most its size
+    // Batches of kBatchGroupsMin problems or more run as two groups whose
+    // rounds alternate on the stream, each with a workspace of its own: while
+    // the GPU runs one group's round, the host takes the other group's
+    // results, steps its price loops and queues its next round, so that the
+    // host's work and the launch latency hide behind the other group's
+    // kernels.  These rounds are launched directly with compact tables.  A
+    // smaller batch is one group, replayed from a captured graph.
     const int Wmax = ctx->cus * 8 * 4;
-    BatchWs* wsp = static_cast<BatchWs*>(ctx->batch_ws.get());
-    if (!wsp || wsp->B < B || wsp->Wmax != Wmax) {
-        ctx->batch_ws.reset();
-        std::shared_ptr<BatchWs> nw = std::make_shared<BatchWs>();
-        if (batch_alloc(ctx, *nw, B, Wmax) != RA_OK) return RA_ENOMEM;
-        ctx->batch_ws = nw;
-        wsp = nw.get();
+    const int NG = B >= kBatchGroupsMin ? 2 : 1;
+    BatchWs* wss[2] = {nullptr, nullptr};
+    for (int g = 0; g < NG; ++g) {
+        std::shared_ptr<void>& slot = g == 0 ? ctx->batch_ws : ctx->batch_ws2;
+        BatchWs* wsp = static_cast<BatchWs*>(slot.get());
+        if (!wsp || wsp->B < B || wsp->Wmax != Wmax) {
+            slot.reset();
+            std::shared_ptr<BatchWs> nw = std::make_shared<BatchWs>();
+            if (batch_alloc(ctx, *nw, B, Wmax) != RA_OK) return RA_ENOMEM;
+            slot = nw;
+            wsp = nw.get();
+        }
+        wss[g] = wsp;
     }
-    BatchWs& ws = *wsp;
+    BatchWs& ws = *wss[0];
     ws.demands = false;
     ws.alpha_fair = false;
     for (int b = 0; b < B; ++b) {
         ws.demands = ws.demands || P[b]->dem != nullptr;
         ws.alpha_fair = ws.alpha_fair || P[b]->alpha_fair;
     }
-    const bool graph = o.use_graph && ctx->stream != nullptr;
+    const bool graph = NG == 1 && o.use_graph && ctx->stream != nullptr;
+    ws.compact = !graph;
+    if (NG == 2) {
+        wss[1]->demands = ws.demands;
+        wss[1]->alpha_fair = ws.alpha_fair;
+        wss[1]->compact = true;
+    }
 
     // host threads for the per-problem work between rounds (created once per
     // context, for batches large enough to use them)
@@ -1786,7 +1841,6 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
 
     // launch shape: fixed by the caller, cached for this batch signature, or
     // tuned now (timing candidate rounds at the first prices)
-    std::vector<int> act;
     std::vector<std::vector<double>> p_eval(B);
     ra::BatchTuned tuned;
     if (ctx->batch_fixed) {
@@ -1816,38 +1870,80 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     }
     const int grid = ctx->cus * bpc;
 
-    for (;;) {
-        act.clear();
-        for (int b = 0; b < B; ++b)
-            if (!loops[b].done()) act.push_back(b);
-        if (act.empty()) break;
-        batch_fill(ws, P, loops, act, grid * 4, p_eval, pool, tuned);
-        ra_status s = batch_run(ctx, ws, grid, graph);
+    // the groups: problems by size, dealt 0 1 1 0 0 1 ... so that both
+    // groups get about half of the work; each group's members ascending
+    std::vector<int> members[2];
+    {
+        std::vector<int> order(B);
+        for (int b = 0; b < B; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return P[x]->n * (int64_t)P[x]->m > P[y]->n * (int64_t)P[y]->m;
+        });
+        for (int k = 0; k < B; ++k) members[NG == 2 ? ((k + 1) >> 1) & 1 : 0].push_back(order[k]);
+        for (int g = 0; g < NG; ++g) std::sort(members[g].begin(), members[g].end());
+    }
+    std::vector<int> gact[2];
+    std::vector<std::vector<double>> gp_eval[2];
+    bool queued[2] = {false, false};
+    for (int g = 0; g < NG; ++g) gp_eval[g].resize(members[g].size());
+    // fill and queue group g's next round, if it has active problems
+    auto queue_round = [&](int g) -> ra_status {
+        std::vector<int>& A = gact[g];
+        A.clear();
+        for (int b : members[g])
+            if (!loops[b].done()) A.push_back(b);
+        queued[g] = !A.empty();
+        if (!queued[g]) return RA_OK;
+        batch_fill(*wss[g], P, loops, A, grid * 4, gp_eval[g], pool, tuned);
+        return batch_launch(ctx, *wss[g], grid, graph);
+    };
+    // wait for group g's round and step the price loop of each of its
+    // problems (independent per problem); a non-finite dual value is
+    // reported for the first such problem after all have been visited
+    auto take_round = [&](int g) -> ra_status {
+        BatchWs& wg = *wss[g];
+        ra_status s = wait_flag(ctx, wg.hflag);
         if (s != RA_OK) return s;
-        // every active problem's price loop takes its step (independent per
-        // problem); a non-finite dual value is reported for the first such
-        // problem after all have been visited
-        const int A = (int)act.size();
-        bad.assign(A, 0);
-        for_problems(pool, A, [&](int lo, int hi) {
+        const std::vector<int>& A = gact[g];
+        const int nA = (int)A.size();
+        bad.assign(nA, 0);
+        for_problems(pool, nA, [&](int lo, int hi) {
             double rr[ra::BATCH_MAX_M];
             for (int a = lo; a < hi; ++a) {
-                const int b = act[a];
+                const int b = A[a];
                 const ra_problem* Pb = P[b];
-                const double* row = ws.hout + (size_t)a * ra::BATCH_COLS;
+                const double* row = wg.hout + (size_t)a * ra::BATCH_COLS;
                 double pR = 0.0;
-                for (int j = 0; j < Pb->m; ++j) pR += p_eval[a][j] * Pb->R[j];
+                for (int j = 0; j < Pb->m; ++j) pR += gp_eval[g][a][j] * Pb->R[j];
                 const double gv = pR + row[ra::BATCH_MAX_M];
                 if (!std::isfinite(gv)) {
                     bad[a] = 1;
                     continue;
                 }
                 for (int j = 0; j < Pb->m; ++j) rr[j] = row[j];
-                loops[b].feed(p_eval[a], gv, rr, row[ra::BATCH_MAX_M + 2]);
+                loops[b].feed(gp_eval[g][a], gv, rr, row[ra::BATCH_MAX_M + 2]);
             }
         });
-        for (int a = 0; a < A; ++a)
-            if (bad[a]) return fail(ctx, RA_ENUMERIC, "problem %d: non-finite dual value", act[a]);
+        for (int a = 0; a < nA; ++a)
+            if (bad[a]) return fail(ctx, RA_ENUMERIC, "problem %d: non-finite dual value", A[a]);
+        return RA_OK;
+    };
+    {
+        ra_status s = RA_OK;
+        for (int g = 0; g < NG && s == RA_OK; ++g) s = queue_round(g);
+        while (s == RA_OK && (queued[0] || queued[1])) {
+            for (int g = 0; g < NG && s == RA_OK; ++g) {
+                if (!queued[g]) continue;
+                s = take_round(g);
+                if (s == RA_OK) s = queue_round(g);
+            }
+        }
+        if (s != RA_OK) {
+            // a round of the other group may still be queued: let it finish
+            // before the workspaces are touched again
+            (void)hipStreamSynchronize(ctx->stream);
+            return s;
+        }
     }
     // the last reduction may still be retiring after its flag
     RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
