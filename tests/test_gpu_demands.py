@@ -116,6 +116,34 @@ def test_batched_pass_with_demands(ctx, torch):
         pr.close()
 
 
+def test_batched_two_groups_with_demands(ctx, torch):
+    """20 problems (two interleaved groups of rounds), every other one with
+    demands: the kernel variant with demands runs every problem, those
+    without at unit demands; g(p0) and U(X~(p0)) against the oracle."""
+    import paper_2104_00282_amd as ra
+    sizes = [(1000, 4), (5003, 16), (777, 32), (20000, 8), (64, 4), (3001, 8), (12000, 16),
+             (900, 32), (1, 8), (40000, 4)] * 2
+    insts, ds, probs = [], [], []
+    for k, (n, m) in enumerate(sizes):
+        I = synth.random_small(n, m, seed=760 + k, dtype=np.float32)
+        d = _demands(n, 790 + k).astype(np.float32).astype(np.float64) if k % 2 == 0 else None
+        insts.append(I)
+        ds.append(d)
+        probs.append(_problem(ctx, torch, I, d))
+    rng = np.random.default_rng(751)
+    p0 = [round_prices(0.2 + rng.random(I.m) * 2, np.float32) for I in insts]
+    _, infos, _ = ra.batch_solve(probs, p0=p0, tol_rel=0.0, max_evals=2)
+    for I, d, p, inf in zip(insts, ds, p0, infos):
+        ref = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True, d=d)
+        U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, ref.r, ref.jobs)
+        scale = abs(float(p @ I.R)) + np.abs(ref.jobs["v"]).sum()
+        assert abs(inf["g"] - ref.g) <= 1e-5 * scale, (I.n, I.m, d is not None)
+        assert abs(inf["U_lb"] - U) <= 1e-5 * (scale + abs(U)), (I.n, I.m, d is not None)
+        assert inf["dual_evals"] == 2
+    for pr in probs:
+        pr.close()
+
+
 def test_removing_and_rejecting_demands(ctx, torch):
     """Removing demands restores the results of a problem that never had
     them, bit for bit; invalid demands are rejected and leave none."""
