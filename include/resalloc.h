@@ -304,8 +304,11 @@ ra_status ra_get_allocation(ra_ctx *ctx, const ra_problem *prob, const double *p
  * round evaluates all problems still running in one persistent kernel launch
  * (problems laid end to end in tiles of consecutive jobs, each wavefront
  * streaming a contiguous share of the tiles, the shares balanced by the
- * measured cost per job of each m class), replayed from one captured HIP
- * graph per round.  The launch shape (the tile height of each m class, the
+ * measured cost per job of each m class).  Below 16 problems each round
+ * covers all of them and is replayed from one captured HIP graph; from 16 on,
+ * the problems form two groups of about equal work whose rounds alternate on
+ * the context's stream, so that the host steps one group's price loops while
+ * the other group's round runs (use_graph is then ignored).  The launch shape (the tile height of each m class, the
  * tile budget the kernel is compiled for, blocks per compute unit) is chosen
  * by an autotuner that times candidate rounds at the first prices of a new
  * batch signature (number of problems, MiB of T, m classes, kernel variant);
