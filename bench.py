@@ -226,7 +226,8 @@ def warmstart_run(args):
     rows = ws.evaluate(ctx, net, args.eval_count, args.eval_n, m, seed0=synth_seed(200000),
                        const_net=const, ref_stall_evals=args.stall_evals,
                        stall_evals=args.arm_stall_evals, stall_restarts=args.stall_restarts,
-                       warm_stall_restarts=args.warm_stall_restarts, near_sigma=0.03, log=log)
+                       warm_stall_restarts=args.warm_stall_restarts,
+                       warm_stall_evals=args.warm_stall_evals, near_sigma=0.03, log=log)
     s = ws.summarize(rows)
     out = {
         "metric": "time to a 1e-4 relative gap, learned warm start vs cold start (also 1e-3 and "
@@ -249,8 +250,8 @@ def warmstart_run(args):
                        "prediction; level floor_any)",
             "fallback": "cold restart when the certified gap has not fallen below the first "
                         "certificate within 5 certificates, or (learned solves) when the warm "
-                        "run stalls short of the target after %d restarts"
-                        % args.warm_stall_restarts,
+                        "run stalls short of the target after %d restarts (its stall window: %d "
+                        "evaluations)" % (args.warm_stall_restarts, args.warm_stall_evals),
             "ablations": "const: the training mean of log p as the prediction; near: the p = 1 "
                          "reference run's prices times exp(0.03 z) (closer to p* than the "
                          "network), with the learned start's first step",
@@ -852,6 +853,8 @@ def main():
     ap.add_argument("--warm-stall-restarts", type=int, default=2,
                     help="learned solves: stall restarts of the warm run before it hands over "
                          "to a cold solve (-1: never)")
+    ap.add_argument("--warm-stall-evals", type=int, default=20,
+                    help="learned solves: the warm run's stall window")
     ap.add_argument("--train-count", type=int, default=20000)
     ap.add_argument("--train-n", type=int, default=100000)
     ap.add_argument("--eval-count", type=int, default=1000)

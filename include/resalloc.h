@@ -209,6 +209,11 @@ typedef struct {
                                 certificate); the result is the better certified
                                 point of the two runs, and max_evals bounds
                                 their passes together                            */
+    int32_t warm_stall_evals; /* ra_solve_learned only: > 0: the warm run's stall
+                                window instead of stall_evals (a short one ends a
+                                warm path that stalls sooner, for the cold solve
+                                that follows with warm_stall_restarts >= 0);
+                                0 = stall_evals                                  */
 } ra_solve_opts;
 
 /* Outcome of a solve. */
@@ -234,7 +239,8 @@ typedef struct {
 /* Defaults: tol_rel = 1e-6, max_iter = 500, lbfgs_mem = 10, method = 0,
  * init = 0, use_graph = 1, verbose = 0, max_evals = 0 (no limit),
  * stall_evals = 0 (off), init_step = 0 (default step), tol_abs = 0 (off),
- * device_loop = 0, stall_restarts = 0, warm_stall_restarts = -1 (off). */
+ * device_loop = 0, stall_restarts = 0, warm_stall_restarts = -1 (off),
+ * warm_stall_evals = 0 (stall_evals). */
 void ra_solve_opts_default(ra_solve_opts *opts);
 
 /* Per-job demands (§7, "Extensions and variations"): the usage limit becomes

@@ -228,14 +228,16 @@ class Problem:
 
     def solve_learned(self, mlp, tol_rel=1e-6, max_iter=500, lbfgs_mem=10, use_graph=True,
                       max_evals=0, stall_evals=0, fallback_window=5, init_step=0.0,
-                      stall_restarts=0, warm_stall_restarts=-1):
+                      stall_restarts=0, warm_stall_restarts=-1, warm_stall_evals=0):
         """Price discovery from the network's predicted prices (ra_solve_learned).
         warm_stall_restarts >= 0: the warm run's own stall restarts, after which
         a warm run that stalls short of tol_rel is followed by a solve from
-        p = 1 (info["restarted"] == 2)."""
+        p = 1 (info["restarted"] == 2); warm_stall_evals > 0: the warm run's
+        own stall window."""
         o = ra_solve_opts_default()
         o.stall_restarts = stall_restarts
         o.warm_stall_restarts = warm_stall_restarts
+        o.warm_stall_evals = warm_stall_evals
         o.init_step = init_step
         o.tol_rel = tol_rel
         o.max_iter = max_iter

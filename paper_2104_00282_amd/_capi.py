@@ -39,7 +39,7 @@ class ra_solve_opts(ctypes.Structure):
                 ("init", _i32), ("use_graph", _i32), ("verbose", _i32), ("max_evals", _i32),
                 ("stall_evals", _i32), ("init_step", _d), ("tol_abs", _d),
                 ("device_loop", _i32), ("stall_restarts", _i32),
-                ("warm_stall_restarts", _i32)]
+                ("warm_stall_restarts", _i32), ("warm_stall_evals", _i32)]
 
 
 class ra_solve_info(ctypes.Structure):

@@ -634,6 +634,7 @@ void ra_solve_opts_default(ra_solve_opts* o)
     o->device_loop = 0;
     o->stall_restarts = 0;
     o->warm_stall_restarts = -1;
+    o->warm_stall_evals = 0;
 }
 
 static bool valid_opts(const ra_solve_opts& o)
@@ -643,7 +644,7 @@ static bool valid_opts(const ra_solve_opts& o)
            (o.init >= 0 && o.init <= 2) && o.init_step >= 0.0 && o.init_step <= 10.0 &&
            o.tol_abs >= 0.0 && std::isfinite(o.tol_abs) &&
            (o.device_loop == 0 || o.device_loop == 1) && o.stall_restarts >= 0 &&
-           o.warm_stall_restarts >= -1;
+           o.warm_stall_restarts >= -1 && o.warm_stall_evals >= 0;
 }
 
 namespace {
@@ -1061,6 +1062,7 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
     ra_solve_opts ow = o;
     if (ow.init_step == 0.0) ow.init_step = 0.02;
     if (o.warm_stall_restarts >= 0) ow.stall_restarts = o.warm_stall_restarts;
+    if (o.warm_stall_evals > 0) ow.stall_evals = o.warm_stall_evals;
     ra::PriceLoop W(m, P->n, P->R.data(), ow, warm_ok ? p0.data() : std::vector<double>(m, 1.0).data());
     if (warm_ok) {
         double rel0 = INFINITY;

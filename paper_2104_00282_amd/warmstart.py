@@ -104,7 +104,8 @@ LEVELS = (1e-3, 1e-4, "floor", "floor_any")
 
 def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters=300,
              ref_stall_evals=100, stall_evals=30, stall_restarts=5, warm_stall_restarts=2,
-             max_iter=500, fallback_window=5, levels=LEVELS, near_sigma=0.0, log=None):
+             warm_stall_evals=20, max_iter=500, fallback_window=5, levels=LEVELS, near_sigma=0.0,
+             log=None):
     """Cold start (p = 1), the paper's data-dependent start and the learned
     warm start (and optionally a constant predictor) on fresh instances, to each
     relative-gap level of `levels` separately ("floor" = max(1e-6, 1.5 x the
@@ -118,9 +119,10 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
     ref_stall_evals passes; the timed arms, all alike, when it has not
     improved within stall_evals passes for the (stall_restarts + 1)-th time,
     the earlier stalls restarting the update from the best certified point;
-    the learned solves (warm and const) restart warm_stall_restarts times and
-    then, if still short of the target, continue with the cold solve
-    (warm_stall_restarts = -1: no such fallback).
+    the learned solves (warm and const) stall after warm_stall_evals passes
+    without improvement, restart warm_stall_restarts times and then, if still
+    short of the target, continue with the cold solve (warm_stall_restarts =
+    -1: no such fallback).
     near_sigma > 0 adds the arm "near": a start at the p = 1 reference run's
     prices times exp(near_sigma z), z standard normal (seeded per instance),
     closer to p* than any prediction, which shows how much a target tied to
@@ -160,17 +162,16 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
                 kw = dict(tol_rel=tol, max_iter=max_iter, stall_evals=stall_evals,
                           stall_restarts=stall_restarts)
                 arms["cold"] = pr.solve(**kw)[1]
-                arms["warm"] = pr.solve_learned(net, fallback_window=fallback_window,
-                                                warm_stall_restarts=warm_stall_restarts, **kw)[1]
+                lw = dict(fallback_window=fallback_window, warm_stall_restarts=warm_stall_restarts,
+                          warm_stall_evals=warm_stall_evals)
+                arms["warm"] = pr.solve_learned(net, **lw, **kw)[1]
                 arms["paper"] = pr.solve(paper_init=True, **kw)[1]
                 if near_sigma > 0:
                     z = np.random.default_rng(seed0 + g0 + k).standard_normal(m)
                     arms["near"] = pr.solve(p0=np.asarray(pref[k]) * np.exp(near_sigma * z),
                                             init_step=0.02, **kw)[1]
                 if const_net is not None:
-                    arms["const"] = pr.solve_learned(const_net, fallback_window=fallback_window,
-                                                     warm_stall_restarts=warm_stall_restarts,
-                                                     **kw)[1]
+                    arms["const"] = pr.solve_learned(const_net, **lw, **kw)[1]
                 arms["target"] = tol
                 row[str(lv)] = arms
             rows.append(row)

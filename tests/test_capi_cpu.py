@@ -87,7 +87,8 @@ def test_status_strings_and_defaults(lib):
     o = ra.ra_solve_opts_default()
     assert (o.tol_rel, o.max_iter, o.lbfgs_mem, o.method, o.init, o.use_graph, o.max_evals,
             o.stall_evals, o.init_step, o.tol_abs, o.device_loop, o.stall_restarts,
-            o.warm_stall_restarts) == (1e-6, 500, 10, 0, 0, 1, 0, 0, 0.0, 0.0, 0, 0, -1)
+            o.warm_stall_restarts, o.warm_stall_evals) == \
+        (1e-6, 500, 10, 0, 0, 1, 0, 0, 0.0, 0.0, 0, 0, -1, 0)
 
 
 def test_null_arguments_rejected_without_device(lib):

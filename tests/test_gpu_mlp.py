@@ -167,9 +167,10 @@ def test_learned_solve_warm_and_fallback(ctx, torch):
 
 def test_learned_solve_stall_fallback(ctx, torch):
     """With warm_stall_restarts set, a warm run that stalls short of the
-    tolerance is followed by the cold solve ra_solve would run; the result is
-    the better certified point of the two runs, and both runs' passes are
-    counted (and bounded together by max_evals)."""
+    tolerance (with its own stall window, warm_stall_evals) is followed by
+    the cold solve ra_solve would run; the result is the better certified
+    point of the two runs, and both runs' passes are counted (and bounded
+    together by max_evals)."""
     import paper_2104_00282_amd as ra
     m = 8
     I = synth.warmstart_instance(200000, m=m, seed=4243)
@@ -181,10 +182,11 @@ def test_learned_solve_stall_fallback(ctx, torch):
     params[-m:] = (np.log(p_star) + 0.1 * z).astype(np.float32)
     net.set_params(params)
     kw = dict(tol_rel=0.0, max_iter=300, stall_evals=10, stall_restarts=1)
-    p_w, w, _ = pr.solve_learned(net, **kw)  # the warm run alone
+    p_w, w, _ = pr.solve_learned(net, **dict(kw, stall_evals=6))  # the warm run alone
     assert w["restarted"] == 0 and w["converged"] == 0
     p_c, c, _ = pr.solve(**kw)
-    p, info, st = pr.solve_learned(net, warm_stall_restarts=1, **kw)
+    fb = dict(warm_stall_restarts=1, warm_stall_evals=6)
+    p, info, st = pr.solve_learned(net, **fb, **kw)
     assert st == ra.RA_ENOTCONV and info["restarted"] == 2 and info["converged"] == 0
     assert info["warm_evals"] == w["dual_evals"]
     assert info["dual_evals"] == w["dual_evals"] + c["dual_evals"]
@@ -192,14 +194,15 @@ def test_learned_solve_stall_fallback(ctx, torch):
     best_p, best = (p_w, w) if w["rel_gap"] <= c["rel_gap"] else (p_c, c)
     assert info["rel_gap"] == best["rel_gap"] and np.array_equal(p, best_p)
     # a warm run that meets the tolerance is not followed by anything
-    _, ok, _ = pr.solve_learned(net, warm_stall_restarts=1,
-                                **dict(kw, tol_rel=max(1e-4, 2 * w["rel_gap"])))
+    _, ok, _ = pr.solve_learned(net, **fb, **dict(kw, tol_rel=max(1e-4, 2 * w["rel_gap"])))
     assert ok["restarted"] == 0 and ok["converged"] == 1
     # the pass budget covers both runs
     budget = w["dual_evals"] + 5
-    _, capped, _ = pr.solve_learned(net, warm_stall_restarts=1, max_evals=budget, **kw)
+    _, capped, _ = pr.solve_learned(net, max_evals=budget, **fb, **kw)
     assert capped["restarted"] == 2 and capped["dual_evals"] <= budget
     with pytest.raises(ra.RAError):
         pr.solve_learned(net, warm_stall_restarts=-2)
+    with pytest.raises(ra.RAError):
+        pr.solve_learned(net, warm_stall_evals=-1)
     net.close()
     pr.close()
