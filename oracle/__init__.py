@@ -46,7 +46,7 @@ _p = ctypes.c_void_p
 
 class _Job(ctypes.Structure):
     _fields_ = [("t", _d), ("v", _d), ("jlo", _i32), ("jhi", _i32), ("xlo", _d), ("xhi", _d),
-                ("j1", _i32), ("margin1", _d)]
+                ("j1", _i32), ("margin1", _d), ("marginx", _d)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -83,6 +83,8 @@ def lib():
                                 ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(SolveInfo)]
         L.orc_dual_eval_d.restype = ctypes.c_int
         L.orc_dual_eval_d.argtypes = L.orc_dual_eval.argtypes + [_p, ctypes.c_int]
+        L.orc_dual_eval_m.restype = ctypes.c_int
+        L.orc_dual_eval_m.argtypes = L.orc_dual_eval.argtypes + [_p, _p, ctypes.c_int]
         L.orc_solve_d.restype = ctypes.c_int
         L.orc_solve_d.argtypes = L.orc_solve.argtypes + [_p, ctypes.c_int]
         L.orc_init_prices.restype = ctypes.c_int
@@ -116,7 +118,7 @@ def cost(a, p, t):
 
 
 def subproblem(a, p, kind, w, c, eps):
-    """One job's optimum: dict(t, v, jlo, jhi, xlo, xhi, j1, margin1)."""
+    """One job's optimum: dict(t, v, jlo, jhi, xlo, xhi, j1, margin1, marginx)."""
     a = np.ascontiguousarray(a, dtype=np.float64)
     p = np.ascontiguousarray(p, dtype=np.float64)
     J = _Job()
@@ -176,16 +178,17 @@ def dual_eval(T, w, c, kind, eps, R, p, per_job=False, d=None):
     sv = ctypes.c_double()
     r = np.zeros(m)
     jobs = None
-    outs = [None] * 8
+    outs = [None] * 9
     if per_job:
         jobs = {
             "jlo": np.empty(n, np.int32), "jhi": np.empty(n, np.int32),
             "xlo": np.empty(n), "xhi": np.empty(n), "t": np.empty(n), "v": np.empty(n),
-            "j1": np.empty(n, np.int32), "margin1": np.empty(n),
+            "j1": np.empty(n, np.int32), "margin1": np.empty(n), "marginx": np.empty(n),
         }
-        outs = [jobs[k] for k in ("jlo", "jhi", "xlo", "xhi", "t", "v", "j1", "margin1")]
+        outs = [jobs[k] for k in ("jlo", "jhi", "xlo", "xhi", "t", "v", "j1", "margin1",
+                                  "marginx")]
     dd, dc = _demands(d, n, m)
-    rc = lib().orc_dual_eval_d(n, m, tdt, _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
+    rc = lib().orc_dual_eval_m(n, m, tdt, _ptr(T), _ptr(w), _ptr(c), _ptr(kind), float(eps),
                                _ptr(R), _ptr(p), ctypes.byref(g), _ptr(r), ctypes.byref(sv),
                                *[_ptr(o) for o in outs], _ptr(dd), dc)
     if rc != 0:

@@ -140,7 +140,36 @@ typedef struct {
     double xlo, xhi;   /* allocation on jlo / jhi                           */
     int32_t j1;        /* argmax_j a_j/p_j (first lower-envelope vertex)   */
     double margin1;    /* (k(1) - k(2)) / k(1) over keys k_j = a_j / p_j   */
+    double marginx;    /* (v(1) - v(2)) / max(1, |v(1)|), v(2) the best net
+                          utility of a candidate whose allocation differs
+                          from the optimum's (+inf if none): how far the job
+                          is from a tie between allocations                  */
 } orc_job;
+
+/* A candidate allocation: shares x[s] on resources j[s] (j = -1: unused). */
+typedef struct {
+    int32_t j[2];
+    double x[2];
+} orc_alloc;
+
+static double alloc_share(const orc_alloc *A, int j)
+{
+    double s = 0.0;
+    for (int k = 0; k < 2; ++k)
+        if (A->j[k] == j) s += A->x[k];
+    return s;
+}
+
+/* Two allocations differ when some resource's share differs by more than
+ * 1e-9 (shares lie in [0, 1]). */
+static int alloc_differs(const orc_alloc *A, const orc_alloc *B)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (A->j[k] >= 0 && fabs(A->x[k] - alloc_share(B, A->j[k])) > 1e-9) return 1;
+        if (B->j[k] >= 0 && fabs(B->x[k] - alloc_share(A, B->j[k])) > 1e-9) return 1;
+    }
+    return 0;
+}
 
 /* Algorithm 1 (§4.2) by enumeration of every basic feasible segment. */
 void orc_subproblem(int m, const double *a, const double *p, int kind, double w, double c,
@@ -150,6 +179,12 @@ void orc_subproblem(int m, const double *a, const double *p, int kind, double w,
     double best_v = orc_utility(kind, w, c, eps, 0.0);
     double best_t = 0.0, bxlo = 0.0, bxhi = 0.0;
     int bjlo = -1, bjhi = -1;
+    /* the best allocation so far, and the best value among the candidates
+     * whose allocation differs from it (a candidate with the same
+     * allocation has the same value, so the second value only needs the
+     * old best when a different candidate takes over) */
+    orc_alloc best_x = {{-1, -1}, {0.0, 0.0}};
+    double second_v = -INFINITY;
 
     for (int k = -1; k < m; ++k) {
         double ak = (k < 0) ? 0.0 : a[k];
@@ -163,16 +198,26 @@ void orc_subproblem(int m, const double *a, const double *p, int kind, double w,
             double xl = (t - ak) / (al - ak);
             double cost = pk * xk + pl * xl;  /* eq. e-optcostij */
             double v = orc_utility(kind, w, c, eps, t) - cost;
+            orc_alloc cx = {{k >= 0 && xk != 0.0 ? k : -1, xl != 0.0 ? l : -1},
+                            {k >= 0 ? xk : 0.0, xl}};
+            const int differs = alloc_differs(&cx, &best_x);
             if (v > best_v) {
+                if (differs && best_v > second_v) second_v = best_v;
                 best_v = v;
                 best_t = t;
                 bjlo = k;
                 bjhi = l;
                 bxlo = (k < 0) ? 0.0 : xk;
                 bxhi = xl;
+                best_x = cx;
+            } else if (differs && v > second_v) {
+                second_v = v;
             }
         }
     }
+    out->marginx = (second_v == -INFINITY)
+                       ? INFINITY
+                       : (best_v - second_v) / (fabs(best_v) > 1.0 ? fabs(best_v) : 1.0);
     out->t = best_t;
     out->v = best_v;
     out->jlo = bjlo;
@@ -232,11 +277,28 @@ static inline double demand(const double *d, int dcols, int64_t i, int j)
     return dcols == 1 ? d[i] : d[i * dcols + j];
 }
 
+int orc_dual_eval_m(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                    const uint8_t *kind, double eps, const double *R, const double *p, double *g,
+                    double *r, double *sumv_out, int32_t *jlo, int32_t *jhi, double *xlo,
+                    double *xhi, double *tout, double *vout, int32_t *j1, double *margin1,
+                    double *marginx, const double *d, int dcols);
+
 int orc_dual_eval_d(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
                     const uint8_t *kind, double eps, const double *R, const double *p, double *g,
                     double *r, double *sumv_out, int32_t *jlo, int32_t *jhi, double *xlo,
                     double *xhi, double *tout, double *vout, int32_t *j1, double *margin1,
                     const double *d, int dcols)
+{
+    return orc_dual_eval_m(n, m, tdt, T, w, c, kind, eps, R, p, g, r, sumv_out, jlo, jhi, xlo,
+                           xhi, tout, vout, j1, margin1, NULL, d, dcols);
+}
+
+/* orc_dual_eval_d, also returning each job's allocation margin (marginx). */
+int orc_dual_eval_m(int64_t n, int m, int tdt, const void *T, const void *w, const void *c,
+                    const uint8_t *kind, double eps, const double *R, const double *p, double *g,
+                    double *r, double *sumv_out, int32_t *jlo, int32_t *jhi, double *xlo,
+                    double *xhi, double *tout, double *vout, int32_t *j1, double *margin1,
+                    double *marginx, const double *d, int dcols)
 {
     int64_t nchunks = (n + ORC_CHUNK - 1) / ORC_CHUNK;
     double *part = (double *)calloc((size_t)(nchunks > 0 ? nchunks : 1) * (size_t)(m + 1),
@@ -264,6 +326,7 @@ int orc_dual_eval_d(int64_t n, int m, int tdt, const void *T, const void *w, con
             if (vout) vout[i] = J.v;
             if (j1) j1[i] = J.j1;
             if (margin1) margin1[i] = J.margin1;
+            if (marginx) marginx[i] = J.marginx;
         }
     }
     double sv = 0.0;

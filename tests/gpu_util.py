@@ -151,14 +151,43 @@ class Pairs:
         return X
 
 
+def clear_of_ties(J, margin=1e-6):
+    """Jobs whose optimum is clear of ties (R14): the oracle's first-vertex
+    margin and its allocation margin (how far the best allocation's value is
+    from that of any different candidate) both above `margin`."""
+    return (J["margin1"] > margin) & (J["marginx"] > margin)
+
+
+def check_clear_allocations(J, jp, xp, tol):
+    """Every job clear of ties has the oracle's allocation: each share of
+    either support within tol (abs), whatever the order of the two ends.
+    jp, xp: the GPU's (n, 2) support and shares.  Returns the clear share."""
+    clear = clear_of_ties(J)
+    rows = np.nonzero(clear)[0]
+    G = Pairs(jp[rows, 0], jp[rows, 1], xp[rows, 0], xp[rows, 1])
+    O = Pairs(J["jlo"][rows], J["jhi"][rows], J["xlo"][rows], J["xhi"][rows])
+    loc = np.arange(rows.size)
+    dx = np.zeros(rows.size)
+    for src in (G, O):
+        for k in range(2):
+            idx = src.j[:, k]
+            dx = np.maximum(dx, np.abs(G.share(loc, idx) - O.share(loc, idx)))
+    bad = np.nonzero(dx > tol)[0]
+    assert bad.size == 0, ("%d jobs clear of ties have another allocation than the oracle's "
+                           "(first: job %d)" % (bad.size, rows[bad[0]]))
+    return float(clear.mean())
+
+
 def compare_dual(I, p, out, tol, max_mismatch_frac=1e-3, min_clear=0.99, ref=None):
     """Element-by-element parity of one GPU dual evaluation with the oracle.
 
     - j1 equal to the exact (FP64) argmax of a_ij / p_j wherever the oracle's
       efficiency-per-price margin exceeds 1e-6 (at least min_clear of the
       jobs), and within 1e-6 of the best key on the near-ties;
-    - per-job allocation equal (abs tol) except for near-ties, where the
-      GPU's allocation must be feasible and optimal to within tol;
+    - per-job allocation equal (abs tol) on every job clear of ties (the
+      oracle's first-vertex margin and allocation margin both above 1e-6);
+      elsewhere it may differ, but must be feasible and optimal to within
+      tol, on at most max_mismatch_frac of the jobs;
     - r equal to the oracle's r with the GPU's near-tie choices substituted;
     - g and U(X~) equal to relative tol (check_relative).
     ref: the oracle's per-job evaluation at p, if already computed.
@@ -187,6 +216,10 @@ def compare_dual(I, p, out, tol, max_mismatch_frac=1e-3, min_clear=0.99, ref=Non
             idx = src.j[:, k]
             dx = np.maximum(dx, np.abs(G.share(rows, idx) - O.share(rows, idx)))
     mism = np.nonzero(dx > tol)[0]
+    clear_x = clear_of_ties(J)
+    bad = mism[clear_x[mism]]
+    assert bad.size == 0, ("%d jobs clear of ties have another allocation than the oracle's "
+                           "(first: job %d)" % (bad.size, bad[0]))
     if mism.size:
         Xg = G.dense(mism, m)
         vg, _ = job_values(I.T[mism], p, I.kind[mism], I.w[mism].astype(np.float64),
@@ -224,5 +257,6 @@ def compare_dual(I, p, out, tol, max_mismatch_frac=1e-3, min_clear=0.99, ref=Non
         if mism.size == 0:
             U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, ref.r, J)
             check_relative(out["lower_bound"], U, uabs, tol, "U(X~)")
-    return {"mismatched": int(mism.size), "g": out["g"], "g_ref": ref.g,
+    return {"mismatched": int(mism.size), "clear_of_ties": float(clear_x.mean()),
+            "g": out["g"], "g_ref": ref.g,
             "j1_near_ties": near, "j1_vs_element_type_argmax": mirror}

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import check_first_vertex
+from gpu_util import check_clear_allocations, check_first_vertex
 
 pytestmark = pytest.mark.gpu
 
@@ -73,6 +73,8 @@ def test_c_consumer(tmp_path, n, m, log_frac):
     same = (out["j_pair"][:, 1] == ref.jobs["jhi"]) & \
         np.isclose(out["x_pair"][:, 1], ref.jobs["xhi"], atol=1e-4)
     assert same.mean() >= 0.999
+    check_clear_allocations(ref.jobs, np.asarray(out["j_pair"], np.int64),
+                            np.asarray(out["x_pair"], np.float64), 1e-4)
 
     # the solve's certificate, re-evaluated by the oracle at the returned prices
     assert 0.0 <= out["rel_gap"] <= 1e-2

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import check_first_vertex, round_prices, to_device
+from gpu_util import check_clear_allocations, check_first_vertex, round_prices, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,7 @@ def _check_eval(I, D, p, out, tol):
     xp = out["x_pair"].cpu().numpy().astype(np.float64)
     same = (jp[:, 1] == ref.jobs["jhi"]) & np.isclose(xp[:, 1], ref.jobs["xhi"], atol=1e-4)
     assert same.mean() >= 0.999
+    check_clear_allocations(ref.jobs, jp, xp, 1e-4)
     # j1 at the prices d_i * p: the kernel forms 1/(d_ij p_j) with the
     # hardware reciprocal (about 1 ulp), which no CPU code reproduces bit for
     # bit, so it is compared with the exact argmax wherever that is not a

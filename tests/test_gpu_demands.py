@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import round_prices, to_device
+from gpu_util import check_clear_allocations, round_prices, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,7 @@ def test_dual_eval_with_demands(ctx, torch, m, dtype):
         xp = out["x_pair"].cpu().numpy().astype(np.float64)
         same = (jp[:, 1] == ref.jobs["jhi"]) & np.isclose(xp[:, 1], ref.jobs["xhi"], atol=1e-4)
         assert same.mean() >= 0.999
+        check_clear_allocations(ref.jobs, jp, xp, 1e-4)
     pr.close()
 
 

@@ -872,3 +872,104 @@ def test_margin1_is_the_relative_price_change_that_moves_the_argmax():
             assert (int(np.argmax(T[i] / q)) == j1) == stays, (i, mu, f)
         checked += 1
     assert checked > 300
+
+
+def _u(kind, w, c, eps, t):
+    return w * math.log(t + eps) if kind == LOG else w * min(t, c)
+
+
+def _numeric_candidates(a, p, kind, w, c, eps):
+    """Every candidate allocation of one job with its net utility: the origin
+    and, for each pair of ends (origin or resource k, resource l) with
+    a_k < a_l, the best point of that segment found by a bounded scalar
+    search over t (the allocation then follows from eq. e-xixj).  Returns a
+    list of (value, {resource: share})."""
+    from scipy.optimize import minimize_scalar
+    m = len(a)
+    out = [(_u(kind, w, c, eps, 0.0), {})]
+    ends = [(-1, 0.0, 0.0)] + [(k, a[k], p[k]) for k in range(m)]
+    for k, ak, pk in ends:
+        for l in range(m):
+            al, pl = a[l], p[l]
+            if not ak < al:
+                continue
+
+            def neg(t):
+                xl = (t - ak) / (al - ak)
+                xk = (al - t) / (al - ak)
+                return -(_u(kind, w, c, eps, t) - pk * xk - pl * xl)
+
+            res = minimize_scalar(neg, bounds=(ak, al), method="bounded",
+                                  options={"xatol": 1e-13})
+            best_t, best_f = res.x, res.fun
+            for t in (ak, al):  # the bounded search may stop just inside an end
+                if neg(t) < best_f:
+                    best_t, best_f = t, neg(t)
+            xl = (best_t - ak) / (al - ak)
+            xk = (al - best_t) / (al - ak)
+            x = {}
+            if k >= 0 and xk > 0:
+                x[k] = xk
+            if xl > 0:
+                x[l] = x.get(l, 0.0) + xl
+            out.append((-best_f, x))
+    return out
+
+
+def _margin_numeric(a, p, kind, w, c, eps, best_x, same_tol=1e-6):
+    cands = _numeric_candidates(a, p, kind, w, c, eps)
+    v1 = max(v for v, _ in cands)
+    keys = set(best_x)
+    diff = [v for v, x in cands
+            if any(abs(x.get(j, 0.0) - best_x.get(j, 0.0)) > same_tol for j in keys | set(x))]
+    if not diff:
+        return math.inf
+    return (v1 - max(diff)) / max(1.0, abs(v1))
+
+
+@pytest.mark.parametrize("kind", [LOG, CAPLIN])
+def test_marginx_against_a_numeric_search_of_every_candidate(kind):
+    """The allocation margin (how far a job's optimum is from a tie with a
+    different allocation) against candidates found by a bounded scalar search
+    on every segment, on random jobs with up to four resources."""
+    rng = np.random.default_rng(2300 + kind)
+    checked = 0
+    for trial in range(150):
+        m = int(rng.integers(1, 5))
+        a = np.round(0.1 + 2 * rng.random(m), 3)
+        p = np.round(0.1 + rng.random(m), 3)
+        w, c = 0.5 + rng.random(), 0.2 + 2 * rng.random()
+        J = oracle.subproblem(a, p, kind, w, c, 1e-3)
+        best_x = {}
+        if J["jlo"] >= 0 and J["xlo"] > 0:
+            best_x[J["jlo"]] = J["xlo"]
+        if J["jhi"] >= 0 and J["xhi"] > 0:
+            best_x[J["jhi"]] = best_x.get(J["jhi"], 0.0) + J["xhi"]
+        want = _margin_numeric(a, p, kind, w, c, 1e-3, best_x)
+        if math.isinf(want):
+            assert math.isinf(J["marginx"]), (a, p, w, c, J)
+        else:
+            assert J["marginx"] == pytest.approx(want, abs=2e-6), (a, p, w, c, J, want)
+            checked += 1
+    assert checked > 100
+
+
+def test_marginx_special_cases():
+    # equal efficiencies a_j / p_j: the log optimum t = 0.5 can be bought on
+    # resource 0 alone (x = 0.5) or on resource 1 alone (x = 0.25) at the
+    # same cost: a tie between allocations
+    J = oracle.subproblem(np.array([1.0, 2.0]), np.array([1.0, 2.0]), LOG, 0.501, 0.0, 1e-3)
+    assert J["marginx"] == pytest.approx(0.0, abs=1e-12)
+    # nothing to buy: the origin is the only allocation
+    J = oracle.subproblem(np.array([0.0, 0.0]), np.array([1.0, 1.0]), LOG, 1.0, 0.0, 1e-3)
+    assert math.isinf(J["marginx"])
+    # one resource, interior log optimum: the other candidate is the origin,
+    # so the margin is (v* - w log eps) / max(1, |v*|), v* from a 1-D search
+    from scipy.optimize import minimize_scalar
+    a, pr, w, eps = 2.0, 0.7, 1.3, 1e-3
+    res = minimize_scalar(lambda x: -(w * math.log(a * x + eps) - pr * x), bounds=(0.0, 1.0),
+                          method="bounded", options={"xatol": 1e-13})
+    vstar = -res.fun
+    J = oracle.subproblem(np.array([a]), np.array([pr]), LOG, w, 0.0, eps)
+    assert J["marginx"] == pytest.approx((vstar - w * math.log(eps)) / max(1.0, abs(vstar)),
+                                         abs=1e-7)
