@@ -784,6 +784,50 @@ def bench_pass_curve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_scan_forms(args):
+    """The first-vertex scan (argmax_j a_ij / p_j) over the roofline
+    instance's rows (n x 64, staged through LDS as in the dual kernel) with
+    1, 2, 4, 8 or 16 lanes of a wavefront per job: the mean time of one pass
+    for each mapping, and how many jobs' vertices differ from the one-lane
+    mapping.  Prices: those of a 5-pass cold solve."""
+    import torch
+    import synth
+    import paper_2104_00282_amd as ra
+
+    n, m = args.n, 64
+    log("generating roofline instance n=%d m=%d" % (n, m))
+    I = synth.roofline_64(n=n, m=m)
+    dev = torch.device("cuda:0")
+    T = torch.from_numpy(I.T).to(dev)
+    w = torch.from_numpy(I.w).to(dev)
+    c = torch.from_numpy(I.c).to(dev)
+    kind = torch.from_numpy(I.kind).to(dev)
+    ctx = ra.Context(0)
+    prob = ra.Problem(ctx, T, w, c, kind, I.R, I.eps, validate=False)
+    read_ms = ra.ra_stream_read_ms(ctx.handle, T.data_ptr(), n * m * 4, 150)
+    p, _, _ = prob.solve(tol_rel=0.0, max_iter=5, max_evals=5)
+    p = np.maximum(p, 1e-6)  # the probe takes positive prices
+    j_ref = torch.empty(n, dtype=torch.int16, device=dev)
+    j_g = torch.empty(n, dtype=torch.int16, device=dev)
+    ms, diff = {}, {}
+    for G in (1, 2, 4, 8, 16):
+        out = j_ref if G == 1 else j_g
+        ms[G] = ra.ra_probe_first_vertex_ms(ctx.handle, T.data_ptr(), n, p, G, 20, out.data_ptr())
+        if G > 1:
+            diff[G] = int((j_g != j_ref).sum().item())
+        log("%d lanes per job: %.4f ms" % (G, ms[G]))
+    bytes_ = n * m * 4
+    res = {"metric": "first-vertex scan pass by lanes per job (n x 64 FP32, LDS-staged tiles)",
+           "n": n, "m": m,
+           "ms": {str(g): v for g, v in ms.items()},
+           "GB/s": {str(g): bytes_ / (v / 1e3) / 1e9 for g, v in ms.items()},
+           "jobs_differing_from_one_lane": {str(g): v for g, v in diff.items()},
+           "read_ceiling_ms": read_ms}
+    prob.close()
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def synth_seed(offset):
     import synth
     return synth.BASE_SEED + offset
@@ -834,7 +878,8 @@ def main():
                     help="only run the plain copy used to scale the HBM counters")
     ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
                                            "batch-rounds", "e1", "demand-vectors", "demands",
-                                           "alpha-fair", "dual-evals", "scale", "pass-curve"],
+                                           "alpha-fair", "dual-evals", "scale", "pass-curve",
+                                           "scan-forms"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
@@ -868,7 +913,7 @@ def main():
         return
     if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1",
                          "demand-vectors", "demands", "alpha-fair", "dual-evals", "scale",
-                         "pass-curve"):
+                         "pass-curve", "scan-forms"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
@@ -876,7 +921,8 @@ def main():
          "solves": bench_solves, "batch-rounds": bench_batch_rounds,
          "e1": bench_e1, "demand-vectors": bench_extension, "demands": bench_extension,
          "alpha-fair": bench_extension, "dual-evals": bench_dual_evals,
-         "scale": bench_scale, "pass-curve": bench_pass_curve}[args.workload](args)
+         "scale": bench_scale, "pass-curve": bench_pass_curve,
+         "scan-forms": bench_scan_forms}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "

@@ -439,6 +439,21 @@ ra_status ra_predict_prices(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp, do
  * fraction can be compared with.  Errors: RA_EINVAL, RA_EDEVICE. */
 ra_status ra_stream_read_ms(ra_ctx *ctx, const void *buf, int64_t bytes, int32_t reps, double *ms);
 
+/* Measurement aid for the mapping of the first-vertex scan (§4.1: the first
+ * envelope vertex of job i is argmax_j a_ij / p_j) onto a wavefront: over
+ * the rows of an n x 64 FP32 matrix T (device, row-major, 16-byte aligned,
+ * n a positive multiple of 64), staged through LDS in 64-row tiles as the
+ * dual kernel stages them, each job's vertex is found by lanes_per_job
+ * lanes (1, 2, 4, 8 or 16) that scan contiguous parts of its row and join
+ * them with a shuffle argmax (lower index on equal keys).  p: host, 64
+ * prices > 0 (the keys use their FP32 reciprocals).  j1: device, n int16,
+ * receives the vertices.  ms: mean time of one pass over `reps` passes after
+ * 3 untimed ones, HIP events on the context's stream.
+ * Errors: RA_EINVAL, RA_EDEVICE. */
+ra_status ra_probe_first_vertex_ms(ra_ctx *ctx, const float *T, int64_t n, const double *p,
+                                   int32_t lanes_per_job, int32_t reps, int16_t *j1,
+                                   double *ms);
+
 /* Kernel timing on the context's stream (for benchmarks and profiling).
  * enable = 1 brackets every launch of the dual kernel with a pair of HIP
  * events on the context's stream and accumulates the elapsed times; while it

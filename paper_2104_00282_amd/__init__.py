@@ -21,6 +21,7 @@ from ._capi import (RA_EDEVICE, RA_EINVAL, RA_ENOMEM, RA_ENOTCONV, RA_ENUMERIC, 
                     ra_problem_destroy, ra_solve, ra_solve_info, ra_solve_opts,
                     ra_solve_opts_default, ra_status_string, ra_set_kernel_timing,
                     ra_get_kernel_timing, ra_batch_solve, ra_stream_read_ms,
+                    ra_probe_first_vertex_ms,
                     ra_batch_set_shape, ra_batch_tuning)
 
 __all__ = [
@@ -28,7 +29,7 @@ __all__ = [
     "ra_last_error", "ra_problem_create", "ra_problem_destroy", "ra_dual_eval",
     "ra_solve_opts_default", "ra_solve", "ra_get_allocation", "ra_solve_opts", "ra_solve_info",
     "ra_set_kernel_timing", "ra_get_kernel_timing", "ra_batch_solve", "batch_solve", "MLP",
-    "ra_stream_read_ms", "ra_batch_set_shape", "ra_batch_tuning",
+    "ra_stream_read_ms", "ra_probe_first_vertex_ms", "ra_batch_set_shape", "ra_batch_tuning",
 ]
 
 

@@ -74,6 +74,8 @@ PROTOTYPES = {
     "ra_problem_set_demands": (_st, [_vp, _vp, _vp]),
     "ra_problem_set_demand_vectors": (_st, [_vp, _vp, _vp]),
     "ra_stream_read_ms": (_st, [_vp, _vp, _i64, _i32, ctypes.POINTER(_d)]),
+    "ra_probe_first_vertex_ms": (_st, [_vp, _vp, _i64, ctypes.POINTER(_d), _i32, _i32, _vp,
+                                       ctypes.POINTER(_d)]),
     "ra_mlp_create": (_st, [_vp, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "ra_mlp_destroy": (_st, [_vp]),
     "ra_mlp_num_params": (_st, [_vp, ctypes.POINTER(_i64)]),
@@ -199,6 +201,19 @@ def ra_stream_read_ms(ctx, ptr, nbytes, reps=20):
     """Mean ms of one plain streaming read of nbytes at device address ptr."""
     ms = ctypes.c_double()
     st = lib().ra_stream_read_ms(ctx, ptr, nbytes, reps, ctypes.byref(ms))
+    if st != RA_OK:
+        raise RAError(st, ra_last_error(ctx))
+    return ms.value
+
+
+def ra_probe_first_vertex_ms(ctx, T_ptr, n, p, lanes_per_job, reps, j1_ptr):
+    """Mean ms of one first-vertex scan pass over an n x 64 FP32 matrix with
+    lanes_per_job lanes per job; the vertices go to the int16 device array
+    at j1_ptr."""
+    pa = (_d * 64)(*[float(v) for v in p])
+    ms = ctypes.c_double()
+    st = lib().ra_probe_first_vertex_ms(ctx, T_ptr, n, pa,
+                                        lanes_per_job, reps, j1_ptr, ctypes.byref(ms))
     if st != RA_OK:
         raise RAError(st, ra_last_error(ctx))
     return ms.value

@@ -266,3 +266,33 @@ def test_alpha_fair_exponents_near_one_and_zero(ctx, torch):
         assert np.isfinite(out["g"]) and np.isfinite(out["lower_bound"])
         compare_dual(I, p, out, 1e-5)
     pr.close()
+
+
+def test_first_vertex_probe_mappings_agree_with_oracle(ctx, torch):
+    """The first-vertex scan probe (one lane per job, or 2-16 lanes per job
+    joined by a shuffle argmax) gives every job the oracle's first vertex
+    wherever it is clear of a near-tie, and all mappings agree exactly;
+    several tiles per wave (n = 64 x 4 x 2 x CUs x 2 + 64 x 3)."""
+    import oracle
+    import paper_2104_00282_amd as ra
+    from gpu_util import check_first_vertex
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 64 * (4 * 2 * cus * 2 + 3)
+    I = synth.random_small(n, 64, seed=4100, dtype=np.float32)
+    T = torch.from_numpy(np.ascontiguousarray(I.T)).cuda()
+    p = round_prices(0.2 + np.random.default_rng(4101).random(64) * 2, np.float32)
+    ref = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p, per_job=True)
+    first = None
+    for G in (1, 2, 4, 8, 16):
+        j1 = torch.full((n,), -7, dtype=torch.int16, device="cuda")
+        ms = ra.ra_probe_first_vertex_ms(ctx.handle, T.data_ptr(), n, p, G, 1, j1.data_ptr())
+        assert ms > 0.0
+        got = j1.cpu().numpy().astype(np.int64)
+        check_first_vertex(I.T, p, got, ref.jobs["j1"], ref.jobs["margin1"])
+        if first is None:
+            first = got
+        assert np.array_equal(got, first), G
+    with pytest.raises(ra.RAError):
+        ra.ra_probe_first_vertex_ms(ctx.handle, T.data_ptr(), n - 1, p, 1, 1, j1.data_ptr())
+    with pytest.raises(ra.RAError):
+        ra.ra_probe_first_vertex_ms(ctx.handle, T.data_ptr(), n, p, 3, 1, j1.data_ptr())
