@@ -1872,15 +1872,22 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     }
     const int grid = ctx->cus * bpc;
 
-    // the groups: problems by size, dealt 0 1 1 0 0 1 ... so that both
-    // groups get about half of the work; each group's members ascending
+    // the groups: problems by their work in a round (jobs times the tuned
+    // cost per job of their m class, else 4 m + 8 bytes per job), dealt
+    // 0 1 1 0 0 1 ... so that both groups get about half of it; each
+    // group's members ascending
     std::vector<int> members[2];
     {
+        std::vector<double> work(B);
+        for (int b = 0; b < B; ++b) {
+            const int c = ra::batch_class(P[b]->m);
+            work[b] = (double)P[b]->n *
+                      (tuned.cost[c] > 0.0 ? tuned.cost[c] : (double)(4 * P[b]->m + 8));
+        }
         std::vector<int> order(B);
         for (int b = 0; b < B; ++b) order[b] = b;
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-            return P[x]->n * (int64_t)P[x]->m > P[y]->n * (int64_t)P[y]->m;
-        });
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return work[x] > work[y]; });
         for (int k = 0; k < B; ++k) members[NG == 2 ? ((k + 1) >> 1) & 1 : 0].push_back(order[k]);
         for (int g = 0; g < NG; ++g) std::sort(members[g].begin(), members[g].end());
     }
