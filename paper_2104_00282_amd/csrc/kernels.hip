@@ -984,28 +984,31 @@ __global__ void __launch_bounds__(256, DV ? 1 : 2) k_dual_vec(
 // vectorised classes).  DV: per-job demand vectors dvec (n x m, like T), read
 // the same way; job i is solved at the prices d_i * p and adds d_ij x_ij.
 // ------------------------------------------------------------------------
-template <typename F, bool DV>
-__global__ void __launch_bounds__(256) k_dual_gen(
-    const F* __restrict__ T, const V2<F>* __restrict__ prm, int64_t n, int m,
-    const PriceBlock<F>* __restrict__ pb, F eps, double* __restrict__ partial,
+// One block's share of a generic pass (WPB waves per block, grid-stride over
+// 64-job tiles, one lane per job reading its row from global memory): each
+// wave's sums of r, of v and, with prev, of u(t~) and u(t) - u(t~) are left
+// in red[wave][0..m-1], red[wave][m], [m + 1], [m + 2], for the caller to
+// combine.  Prices P, IP at the new point and, with prev, Q, IQ with the
+// column scales S, SC of the point to certify.  Every thread of the block
+// must call it.
+template <typename F, bool DV, int WPB>
+__device__ __forceinline__ void gen_block_pass(
+    const F* __restrict__ T, const V2<F>* __restrict__ prm, int64_t n, int m, const F* P,
+    const F* IP, const F* Q, const F* IQ, const F* S, const F* SC, bool prev, F eps,
     int* __restrict__ jpair, V2<F>* __restrict__ xpair, V2<F>* __restrict__ tpair,
-    int16_t* __restrict__ j1out, const F* __restrict__ dem, const F* __restrict__ dvec)
+    int16_t* __restrict__ j1out, const F* __restrict__ dem, const F* __restrict__ dvec,
+    F (*hist)[256], double (*red)[259])
 {
     constexpr int TR = 64;
-    __shared__ F hist[4][256];
-    __shared__ double red[4][259];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const F* __restrict__ P = pb->p;
-    const F* __restrict__ IP = pb->invp;
-    const bool prev = pb->has_prev != 0;
     for (int j = lane; j < m; j += 64) hist[wv][j] = F(0);
     __syncthreads();
     // some price zero (wave-uniform): see scan_first
     bool zp = false, zq = false;
     for (int j = lane; j < m; j += 64) {
         zp |= P[j] == F(0);
-        zq |= prev && pb->q[j] == F(0);
+        zq |= prev && Q[j] == F(0);
     }
     const bool freep = __ballot(zp) != 0ull;
     const bool freeq = __ballot(zq) != 0ull;
@@ -1013,8 +1016,8 @@ __global__ void __launch_bounds__(256) k_dual_gen(
     double racc[4] = {0.0, 0.0, 0.0, 0.0};
     double vacc = 0.0, uacc = 0.0, duacc = 0.0;
     const int64_t ntiles = (n + TR - 1) / TR;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t ti = (int64_t)blockIdx.x * 4 + wv; ti < ntiles; ti += nw) {
+    const int64_t nw = (int64_t)gridDim.x * WPB;
+    for (int64_t ti = (int64_t)blockIdx.x * WPB + wv; ti < ntiles; ti += nw) {
         const int64_t i = ti * TR + lane;
         if (i < n) {
             GlobalRow<F> row{T + i * m};
@@ -1039,10 +1042,9 @@ __global__ void __launch_bounds__(256) k_dual_gen(
             vacc += (double)J.v * (double)dj;
             if (prev) {  // lower bound of the previous prices, same row
                 Job<F> K;
-                solve(pb->q, pb->invq, freeq, K);
+                solve(Q, IQ, freeq, K);
                 F u, loss;
-                scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, pb->s, pb->sc,
-                               u, loss);
+                scaled_utility(caplin, wc.x, wc.y, eps, K.jlo, K.jhi, K.tlo, K.thi, S, SC, u, loss);
                 uacc += (double)u * (double)dj;
                 duacc += (double)loss * (double)dj;
             }
@@ -1076,11 +1078,83 @@ __global__ void __launch_bounds__(256) k_dual_gen(
         red[wv][m + 2] = duacc;
     }
     __syncthreads();
+}
+
+template <typename F, bool DV>
+__global__ void __launch_bounds__(256) k_dual_gen(
+    const F* __restrict__ T, const V2<F>* __restrict__ prm, int64_t n, int m,
+    const PriceBlock<F>* __restrict__ pb, F eps, double* __restrict__ partial,
+    int* __restrict__ jpair, V2<F>* __restrict__ xpair, V2<F>* __restrict__ tpair,
+    int16_t* __restrict__ j1out, const F* __restrict__ dem, const F* __restrict__ dvec)
+{
+    __shared__ F hist[4][256];
+    __shared__ double red[4][259];
+    gen_block_pass<F, DV, 4>(T, prm, n, m, pb->p, pb->invp, pb->q, pb->invq, pb->s, pb->sc,
+                          pb->has_prev != 0, eps, jpair, xpair, tpair, j1out, dem, dvec, hist,
+                          red);
     const int nc = m + 3;
     for (int t = threadIdx.x; t < nc; t += 256) {
         const double s = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
         partial[(int64_t)blockIdx.x * nc + t] = s;
     }
+}
+
+// A generic solver pass of a small problem (n <= SMALL_MAX_N jobs, m <=
+// SMALL_MAX_M, no demand vectors) as one launch of at most four blocks (one
+// 64-job tile per wave): the prices come as a kernel argument, each block
+// leaves its sums in partial[block], and the block that takes the last
+// ticket adds them up in block order and writes the columns of the
+// reduction (r, sum v, sum u(t~), sum of the loss) straight into pinned host
+// memory, with the completion flag after them.  One launch per pass instead
+// of a price copy, the dual kernel and the column reduction.
+template <typename F>
+__global__ void __launch_bounds__(256) k_dual_small(const F* __restrict__ T,
+                                                    const V2<F>* __restrict__ prm, int64_t n,
+                                                    int m, const SmallPrices<F> sp, F eps,
+                                                    const F* __restrict__ dem,
+                                                    double* __restrict__ partial,
+                                                    unsigned* __restrict__ ticket,
+                                                    double* __restrict__ out,
+                                                    unsigned* __restrict__ flag)
+{
+    __shared__ F hist[4][256];
+    __shared__ double red[4][259];
+    __shared__ F pt[6][SMALL_MAX_M];
+    __shared__ bool last;
+    for (int t = threadIdx.x; t < m; t += 256) {
+        pt[0][t] = sp.p[t];
+        pt[1][t] = sp.invp[t];
+        pt[2][t] = sp.q[t];
+        pt[3][t] = sp.invq[t];
+        pt[4][t] = sp.s[t];
+        pt[5][t] = sp.sc[t];
+    }
+    __syncthreads();
+    gen_block_pass<F, false, 4>(T, prm, n, m, pt[0], pt[1], pt[2], pt[3], pt[4], pt[5],
+                                sp.has_prev != 0, eps, nullptr, nullptr, nullptr, nullptr, dem,
+                                nullptr, hist, red);
+    const int nc = m + 3;
+    for (int t = threadIdx.x; t < nc; t += 256) {
+        partial[(int64_t)blockIdx.x * nc + t] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+        __threadfence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        last = atomicAdd(ticket, 1u) == gridDim.x - 1u;
+        if (last) atomicExch(ticket, 0u);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();  // every block's sums are visible past this point
+    for (int t = threadIdx.x; t < nc; t += 256) {
+        double s = partial[t];
+        for (int b = 1; b < (int)gridDim.x; ++b) s += partial[(int64_t)b * nc + t];
+        out[t] = s;
+        __threadfence_system();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ------------------------------------------------------------------------
@@ -1847,6 +1921,42 @@ hipError_t launch_dual_dev(int m, int grid, hipStream_t st, const void* T, const
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t launch_small_t(hipStream_t st, const void* T, const void* prm, int64_t n, int m,
+                                 const void* host_prices, double eps, const void* dem,
+                                 double* partial, unsigned* ticket, double* out, unsigned* flag)
+{
+    const auto* b = static_cast<const PriceBlock<F>*>(host_prices);
+    SmallPrices<F> sp;
+    for (int j = 0; j < SMALL_MAX_M; ++j) {
+        const bool in = j < m;
+        sp.p[j] = in ? b->p[j] : F(0);
+        sp.invp[j] = in ? b->invp[j] : F(0);
+        sp.q[j] = in ? b->q[j] : F(0);
+        sp.invq[j] = in ? b->invq[j] : F(0);
+        sp.s[j] = in ? b->s[j] : F(0);
+        sp.sc[j] = in ? b->sc[j] : F(0);
+    }
+    sp.has_prev = b->has_prev;
+    const int grid = (int)(((n + 63) / 64 + 3) / 4);
+    k_dual_small<F><<<grid, 256, 0, st>>>(static_cast<const F*>(T),
+                                          static_cast<const V2<F>*>(prm), n, m, sp, (F)eps,
+                                          static_cast<const F*>(dem), partial, ticket, out, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_dual_small(int dtype, hipStream_t st, const void* T, const void* prm,
+                             int64_t n, int m, const void* host_prices, double eps,
+                             const void* dem, double* partial, unsigned* ticket, double* out,
+                             unsigned* flag)
+{
+    if (n < 1 || n > SMALL_MAX_N || m < 1 || m > SMALL_MAX_M) return hipErrorInvalidValue;
+    return dtype == 0 ? launch_small_t<float>(st, T, prm, n, m, host_prices, eps, dem, partial,
+                                              ticket, out, flag)
+                      : launch_small_t<double>(st, T, prm, n, m, host_prices, eps, dem, partial,
+                                               ticket, out, flag);
 }
 
 hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, const void* T,

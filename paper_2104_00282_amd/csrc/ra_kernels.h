@@ -30,6 +30,17 @@ struct PriceArgs {
     int has_prev;
 };
 
+// The prices of a small problem's generic solver pass (m <= SMALL_MAX_M),
+// passed by value to its one-block kernel (launch_dual_one).
+constexpr int SMALL_MAX_M = 64;
+constexpr int64_t SMALL_MAX_N = 1024;
+template <typename F>
+struct SmallPrices {
+    F p[SMALL_MAX_M], invp[SMALL_MAX_M], q[SMALL_MAX_M], invq[SMALL_MAX_M], s[SMALL_MAX_M],
+        sc[SMALL_MAX_M];
+    int has_prev;
+};
+
 // Columns of one row of dual-kernel block partials: r_j (m), then the sums of
 // net utilities, of scaled utilities U(X~) and of utility lost by scaling.
 inline int partial_cols(int m) { return m + 3; }
@@ -119,6 +130,19 @@ hipError_t launch_dual(int dtype, int m, bool vec_ok, int grid, hipStream_t st, 
 
 // True when launch_dual uses a vectorised kernel (prices as a kernel argument).
 bool dual_is_vec(int dtype, int m, bool vec_ok);
+
+// A generic solver pass of a small problem (n <= SMALL_MAX_N, m <=
+// SMALL_MAX_M, no demand vectors) as one launch of at most four blocks:
+// host_prices is the problem's host price block (PriceBlock of the dtype;
+// its first m entries are passed by value), dem the optional per-job
+// demands, partial ((n / 256 rounded up) x (m + 3) doubles) and ticket (zero
+// between launches) device scratch; the column sums r_j, sum v, sum u(t~),
+// sum of the loss go to out (m + 3 doubles of pinned host memory) before
+// *flag = 1.
+hipError_t launch_dual_small(int dtype, hipStream_t st, const void* T, const void* prm,
+                             int64_t n, int m, const void* host_prices, double eps,
+                             const void* dem, double* partial, unsigned* ticket, double* out,
+                             unsigned* flag);
 
 // Data-dependent starting prices: partial [grid][m] gets, per block, the sums
 // of u_i'(a_i^T x) a_ij with x = prices->p (the uniform share of R), each

@@ -283,9 +283,16 @@ ra_status run_pass(ra_problem* P, const std::vector<double>& p, const ra::Point*
     const double pR = fill_prices(P, p.data(), &p_eval);
     if (prev) fill_prev(P, prev->p, prev->r);
     __atomic_store_n(P->h_flag, 0u, __ATOMIC_RELEASE);
-    // a captured graph would keep the kernel arguments of its capture, so the
-    // vectorised kernels (prices as an argument) are launched directly
-    if (use_graph && !ctx->timing && !ra::dual_is_vec(P->dt, P->m, dual_vec(P))) {
+    const bool vec = ra::dual_is_vec(P->dt, P->m, dual_vec(P));
+    // a small problem on the generic kernels: one launch with the prices as
+    // its argument, its sums written straight to the host
+    if (!vec && !ctx->timing && P->n <= ra::SMALL_MAX_N && P->m <= ra::SMALL_MAX_M && !P->dvec) {
+        RA_HIP(ctx, ra::launch_dual_small(P->dt, ctx->stream, P->T, P->prm, P->n, P->m,
+                                          P->h_pblock, P->eps, P->dem, P->partial, P->ticket,
+                                          P->h_out, P->h_flag));
+    } else if (use_graph && !ctx->timing && !vec) {
+        // a captured graph would keep the kernel arguments of its capture, so
+        // the vectorised kernels (prices as an argument) are launched directly
         ra_status st = capture_graph(P);
         if (st != RA_OK) return st;
         RA_HIP(ctx, hipGraphLaunch(P->gexec, ctx->stream));
