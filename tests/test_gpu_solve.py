@@ -299,3 +299,39 @@ def test_mixed16_solve_to_target(ctx, torch):
     check_relative(info["g"], g, sg, 1e-5, "g")
     check_relative(info["U_lb"], U, su, 1e-5, "U(X~)")
     assert (g - U) / max(abs(g), abs(U)) <= target + 1e-6
+
+
+@pytest.mark.parametrize("n,m,dtype,demands,alpha", [
+    (1, 5, np.float32, False, False), (37, 7, np.float64, False, False),
+    (1000, 4, np.float64, True, False), (1024, 5, np.float32, False, True),
+    (700, 64, np.float64, False, True), (1025, 5, np.float32, True, False)])
+def test_small_generic_pass_matches_oracle(ctx, torch, n, m, dtype, demands, alpha):
+    """Solver passes of small problems on the generic kernels (n <= 1024,
+    m <= 64: one launch of at most four blocks, the last one by ticket
+    writing the sums; n = 1025 the usual kernel and column reduction): two
+    passes from p0, the second certifying it; g(p0) and U(X~(p0)) against the
+    oracle, with scalar demands and alpha-fair jobs on some cases."""
+    print("small generic pass n=%d m=%d" % (n, m), flush=True)
+    I = synth.random_small(n, m, seed=4400 + n + m, dtype=dtype)
+    if alpha:
+        rng = np.random.default_rng(4500 + m)
+        sel = rng.random(I.n) < 0.5
+        I.kind = np.where(sel, 2, I.kind).astype(np.uint8)
+        I.c = np.where(sel, rng.choice([0.0, 0.5, 2.0], I.n), I.c).astype(dtype)
+    prob = _problem(ctx, torch, I)
+    d = None
+    if demands:
+        d = (0.5 + 2.5 * np.random.default_rng(4600 + n).random(n)).astype(dtype)
+        prob.set_demands(torch.from_numpy(d).cuda())
+        d = d.astype(np.float64)
+    p0 = np.asarray(0.2 + np.random.default_rng(4700 + m).random(m) * 2, dtype=dtype)
+    p0 = p0.astype(np.float64)
+    p, info, _ = prob.solve(p0=p0, tol_rel=0.0, max_iter=50, max_evals=2)
+    assert np.array_equal(p, p0)
+    ref = oracle.dual_eval(I.T, I.w, I.c, I.kind, I.eps, I.R, p0, per_job=True, d=d)
+    U, _ = oracle.lower_bound(I.T, I.w, I.c, I.kind, I.eps, I.R, ref.r, ref.jobs)
+    tol = 1e-5 if dtype == np.float32 else 1e-9
+    scale = abs(float(p0 @ I.R)) + np.abs(ref.jobs["v"]).sum()
+    assert abs(info["g"] - ref.g) <= tol * scale, (info["g"], ref.g)
+    assert abs(info["U_lb"] - U) <= tol * (scale + abs(U)), (info["U_lb"], U)
+    prob.close()
