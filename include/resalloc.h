@@ -174,7 +174,7 @@ typedef struct {
                                 not improved by 0.1% within this many passes       */
     double init_step;        /* > 0: a step taken with an empty L-BFGS memory moves
                                 the largest price by this fraction of max_j p_j;
-                                0 = the default (0.1, or 0.02 from a learned start);
+                                0 = the default (0.1, or 0.005 from a learned start);
                                 must be finite, 0 <= init_step <= 10               */
     double tol_abs;          /* > 0: also stop when g - U(X~) <= tol_abs (Algorithm 2's
                                 absolute test; the paper suggests 1e-3 n)          */
@@ -411,7 +411,7 @@ ra_status ra_mlp_load(ra_ctx *ctx, const char *path, ra_mlp **out);
 
 /* Price discovery from a learned starting point: features, network forward,
  * p0 = exp(predicted log-prices), then the loop of ra_solve, with its
- * empty-memory steps sized by opts->init_step (default 0.02: a prediction is
+ * empty-memory steps sized by opts->init_step (default 0.005: a prediction is
  * expected within a few percent).  If after `fallback_window` certificates
  * the certified relative gap has not fallen below that of the starting
  * point (or any value is non-finite), the warm

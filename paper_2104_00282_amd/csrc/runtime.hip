@@ -1067,7 +1067,7 @@ ra_status ra_solve_learned(ra_ctx* ctx, const ra_problem* prob, ra_mlp* mlp,
     // a predicted start is expected within a few percent of p*: the first
     // step is kept to that scale so that it does not undo the prediction
     ra_solve_opts ow = o;
-    if (ow.init_step == 0.0) ow.init_step = 0.02;
+    if (ow.init_step == 0.0) ow.init_step = 0.005;
     if (o.warm_stall_restarts >= 0) ow.stall_restarts = o.warm_stall_restarts;
     if (o.warm_stall_evals > 0) ow.stall_evals = o.warm_stall_evals;
     ra::PriceLoop W(m, P->n, P->R.data(), ow, warm_ok ? p0.data() : std::vector<double>(m, 1.0).data());

@@ -142,10 +142,10 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
         if "floor_any" in levels:
             _, rp, _ = batch_solve(probs, tol_rel=0.0, max_iter=floor_iters,
                                    stall_evals=ref_stall_evals, paper_init=True)
-            # the learned solve's empty-memory step is 2 % of max p
+            # the learned solve's empty-memory step is 0.5 % of max p
             preds = [pr.predict_prices(net) for pr in probs]
             _, rw, _ = batch_solve(probs, p0=preds, tol_rel=0.0, max_iter=floor_iters,
-                                   stall_evals=ref_stall_evals, init_step=0.02)
+                                   stall_evals=ref_stall_evals, init_step=0.005)
             refs += [rp, rw]
         for k, (pr, rf) in enumerate(zip(probs, ref)):
             pr.solve(max_iter=0)  # capture the evaluation graph outside the timings
@@ -169,7 +169,7 @@ def evaluate(ctx, net, count, n, m, seed0, const_net=None, group=50, floor_iters
                 if near_sigma > 0:
                     z = np.random.default_rng(seed0 + g0 + k).standard_normal(m)
                     arms["near"] = pr.solve(p0=np.asarray(pref[k]) * np.exp(near_sigma * z),
-                                            init_step=0.02, **kw)[1]
+                                            init_step=0.005, **kw)[1]
                 if const_net is not None:
                     arms["const"] = pr.solve_learned(const_net, **lw, **kw)[1]
                 arms["target"] = tol
