@@ -828,6 +828,51 @@ def bench_scan_forms(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_predict(args):
+    """Cost of one learned prediction (features, the one-row forward, the
+    predicted prices on the host) at n = 1e6, m = 16 with a 144-256-256-16
+    network, against one cold solver pass of the same instance: host-timed
+    medians of 200 calls after 20 warm-up calls."""
+    import torch
+    import synth
+    import paper_2104_00282_amd as ra
+
+    n, m = 1_000_000, 16
+    ctx = ra.Context(0)
+    T, w, c, kind, R = synth.warmstart_device(n, m, seed=synth_seed(300000))
+    pr = ra.Problem(ctx, T, w, c, kind, R, 1e-3, validate=False)
+    net = ra.MLP(ctx, 8 * m + 16, 256, m, seed=3)
+
+    def med_us(fn, reps, per=1):
+        for _ in range(20):
+            fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append((time.perf_counter() - t0) / per)
+        return float(np.median(ts) * 1e6)
+
+    pred = med_us(lambda: pr.predict_prices(net), 200)
+    log("predict_prices: %.1f us" % pred)
+
+    def feats():
+        pr.features()
+        torch.cuda.synchronize()
+
+    feat = med_us(feats, 200)
+    pr.solve(max_iter=0)
+    one_pass = med_us(lambda: pr.solve(tol_rel=0.0, max_evals=20), 50, per=20)
+    res = {"metric": "learned prediction cost (features + one-row forward, host-timed)",
+           "n": n, "m": m, "network": [8 * m + 16, 256, 256, m],
+           "predict_us": pred, "features_us": feat, "solver_pass_us": one_pass,
+           "predict_in_passes": pred / one_pass}
+    net.close()
+    pr.close()
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def synth_seed(offset):
     import synth
     return synth.BASE_SEED + offset
@@ -879,7 +924,7 @@ def main():
     ap.add_argument("--workload", choices=["roofline", "batched", "warmstart", "solves",
                                            "batch-rounds", "e1", "demand-vectors", "demands",
                                            "alpha-fair", "dual-evals", "scale", "pass-curve",
-                                           "scan-forms"],
+                                           "scan-forms", "predict"],
                     default="roofline",
                     help="roofline: the default step benchmark; batched: time to each "
                          "instance's gap target, batched solver vs a per-instance loop; "
@@ -913,7 +958,7 @@ def main():
         return
     if args.workload in ("batched", "warmstart", "solves", "batch-rounds", "e1",
                          "demand-vectors", "demands", "alpha-fair", "dual-evals", "scale",
-                         "pass-curve", "scan-forms"):
+                         "pass-curve", "scan-forms", "predict"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
@@ -922,7 +967,7 @@ def main():
          "e1": bench_e1, "demand-vectors": bench_extension, "demands": bench_extension,
          "alpha-fair": bench_extension, "dual-evals": bench_dual_evals,
          "scale": bench_scale, "pass-curve": bench_pass_curve,
-         "scan-forms": bench_scan_forms}[args.workload](args)
+         "scan-forms": bench_scan_forms, "predict": bench_predict}[args.workload](args)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "

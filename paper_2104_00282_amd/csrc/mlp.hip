@@ -37,6 +37,8 @@ struct ra_mlp {
     double* dloss = nullptr;
     double* hloss = nullptr;
     float* feat = nullptr;    // device scratch for one feature row and one output row
+    float* hy = nullptr;      // pinned host: one predicted output row (O floats)
+    unsigned* hflag = nullptr;  // pinned host: completion flag of the one-row forward
 };
 
 namespace {
@@ -422,7 +424,7 @@ __global__ void __launch_bounds__(1024) k_forward1(const float* __restrict__ P, 
                                                    int64_t oW3, int64_t ob3,
                                                    const float* __restrict__ norm, int D, int H,
                                                    int O, const float* __restrict__ x,
-                                                   float* __restrict__ y)
+                                                   float* __restrict__ y, unsigned* flag)
 {
     extern __shared__ __attribute__((aligned(16))) float fsh[];
     float* xs = fsh;
@@ -467,7 +469,15 @@ __global__ void __launch_bounds__(1024) k_forward1(const float* __restrict__ P, 
     layer(P + oW2, P + ob2, h1, H, H, h2, true);
     layer(P + oW3, P + ob3, h2, H, O, xs, false);  // xs is free again
     const float* ym = norm + 2 * D;
-    for (int k = tid; k < O; k += blockDim.x) y[k] = xs[k] * ym[O + k] + ym[k];
+    // wave 0 writes the outputs; with a flag, y is pinned host memory, made
+    // visible (one wave's system fence) before the flag is raised
+    if (tid < 64) {
+        for (int k = tid; k < O; k += 64) y[k] = xs[k] * ym[O + k] + ym[k];
+        if (flag) {
+            __threadfence_system();
+            if (tid == 0) __hip_atomic_store(flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 int grid_for(int64_t total) { return (int)std::min<int64_t>(4096, (total + 255) / 256 + 1); }
@@ -596,22 +606,26 @@ ra_status predict_prices(ra_mlp* N, ra_problem* P, std::vector<double>& p0)
     float* Y = N->feat + N->D;
     const size_t lds = sizeof(float) * ((size_t)N->D + 2 * (size_t)N->H);
     if (N->O <= N->D && lds <= 48 * 1024) {
+        // the one-block forward writes the log-prices to pinned host memory
+        // and raises a flag there, which the host polls
+        __atomic_store_n(N->hflag, 0u, __ATOMIC_RELEASE);
         k_forward1<<<1, 1024, lds, ctx->stream>>>(N->params, N->oW1, N->ob1, N->oW2, N->ob2,
                                                   N->oW3, N->ob3, N->norm, N->D, N->H, N->O,
-                                                  N->feat, Y);
+                                                  N->feat, N->hy, N->hflag);
         RA_HIP(ctx, hipGetLastError());
+        s = wait_flag(ctx, N->hflag);
+        if (s != RA_OK) return s;
     } else {
         s = forward_std(N, 1, N->feat);
         if (s != RA_OK) return s;
         const float* ym = N->norm + 2 * N->D;
         k_destandardize<<<1, 256, 0, ctx->stream>>>(N->Ys, ym, ym + N->O, N->O, N->O, Y);
+        RA_HIP(ctx, hipMemcpyAsync(N->hy, Y, sizeof(float) * N->O, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     }
-    std::vector<float> y(N->O);
-    RA_HIP(ctx, hipMemcpyAsync(y.data(), Y, sizeof(float) * N->O, hipMemcpyDeviceToHost,
-                               ctx->stream));
-    RA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     p0.resize(N->O);
-    for (int j = 0; j < N->O; ++j) p0[j] = std::exp((double)y[j]);
+    for (int j = 0; j < N->O; ++j) p0[j] = std::exp((double)N->hy[j]);
     return RA_OK;
 }
 
@@ -674,6 +688,11 @@ ra_status ra_mlp_create(ra_ctx* ctx, int32_t in_dim, int32_t hidden, int32_t out
     if ((e = hipMalloc(&N->feat, sizeof(float) * (D + O))) != hipSuccess) return bad(e);
     if ((e = hipHostMalloc((void**)&N->hloss, sizeof(double), hipHostMallocDefault)) != hipSuccess)
         return bad(e);
+    if ((e = hipHostMalloc((void**)&N->hy, sizeof(float) * O, hipHostMallocCoherent)) != hipSuccess)
+        return bad(e);
+    if ((e = hipHostMalloc((void**)&N->hflag, sizeof(unsigned), hipHostMallocCoherent)) !=
+        hipSuccess)
+        return bad(e);
     std::vector<float> host(N->np, 0.f);
     uint64_t s = seed;
     auto fill = [&](int64_t off, int64_t rows, int64_t fan_in) {
@@ -720,6 +739,8 @@ ra_status ra_mlp_destroy(ra_mlp* N)
     (void)hipFree(N->dA);
     (void)hipFree(N->dB);
     if (N->hloss) (void)hipHostFree(N->hloss);
+    if (N->hy) (void)hipHostFree(N->hy);
+    if (N->hflag) (void)hipHostFree(N->hflag);
     delete N;
     return RA_OK;
 }

@@ -107,6 +107,10 @@ inline ra_status fail(ra_ctx* ctx, ra_status st, const char* fmt, ...)
                         #call, hipGetErrorString(e_));                                      \
     } while (0)
 
+// Spin until a kernel has set the pinned completion flag to 1 (runtime.hip);
+// a stream that ends or fails without it gives RA_EDEVICE.
+ra_status wait_flag(ra_ctx* ctx, unsigned* flag);
+
 // Learned warm start (mlp.hip)
 ra_status features_into(ra_problem* P, float* feat);
 ra_status predict_prices(ra_mlp* N, ra_problem* P, std::vector<double>& p0);

@@ -40,9 +40,34 @@ constexpr int NOALLOC_PARTIAL = 1 << 18;                  // doubles (2 MiB)
 constexpr int NOALLOC_OUT = RA_MAX_RESOURCES + 3;         // one row of column sums
 static __device__ __align__(256) double scratch[NOALLOC_PARTIAL + NOALLOC_OUT];
 
+namespace ra {
+
+// Wait for the completion flag of a signalled pass.  The stream is queried
+// now and then, so that a failed or finished stream without the flag ends
+// the wait with an error instead of spinning.
+ra_status wait_flag(ra_ctx* ctx, unsigned* flag)
+{
+    for (uint64_t k = 1;; ++k) {
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
+        if ((k & 4095) == 0) {
+            const hipError_t e = hipStreamQuery(ctx->stream);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
+                return fail(ctx, RA_EDEVICE, "evaluation finished without its completion flag");
+            }
+            if (e != hipErrorNotReady)
+                return fail(ctx, RA_EDEVICE, "evaluation failed: %s", hipGetErrorString(e));
+        }
+        __builtin_ia32_pause();
+    }
+}
+
+}  // namespace ra
+
 namespace {
 
 using ra::fail;
+using ra::wait_flag;
 
 // The device address of `scratch` on each device, found once per device
 // with that device current (the host-side name of the array is not a device
@@ -249,26 +274,6 @@ ra_status init_prices(ra_problem* P, double* p)
             return fail(ctx, RA_ENUMERIC, "initial price %d is %g", j, p[j]);
     }
     return RA_OK;
-}
-
-// Wait for the completion flag of a signalled pass.  The stream is queried
-// now and then, so that a failed or finished stream without the flag ends
-// the wait with an error instead of spinning.
-ra_status wait_flag(ra_ctx* ctx, unsigned* flag)
-{
-    for (uint64_t k = 1;; ++k) {
-        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
-        if ((k & 4095) == 0) {
-            const hipError_t e = hipStreamQuery(ctx->stream);
-            if (e == hipSuccess) {
-                if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == 1u) return RA_OK;
-                return fail(ctx, RA_EDEVICE, "evaluation finished without its completion flag");
-            }
-            if (e != hipErrorNotReady)
-                return fail(ctx, RA_EDEVICE, "evaluation failed: %s", hipGetErrorString(e));
-        }
-        __builtin_ia32_pause();
-    }
 }
 
 // One pass over T at p: dual value and usage at p (p_eval = p as rounded for
@@ -1918,7 +1923,7 @@ extern "C" ra_status ra_batch_solve(ra_ctx* ctx, int32_t B, ra_problem* const* p
     // reported for the first such problem after all have been visited
     auto take_round = [&](int g) -> ra_status {
         BatchWs& wg = *wss[g];
-        ra_status s = wait_flag(ctx, wg.hflag);
+        ra_status s = ra::wait_flag(ctx, wg.hflag);
         if (s != RA_OK) return s;
         const std::vector<int>& A = gact[g];
         const int nA = (int)A.size();
