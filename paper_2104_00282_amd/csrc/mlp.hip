@@ -201,30 +201,28 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 // thread of many small blocks reads one sampled row (all m entries, so the
 // scattered row reads are spread over many compute units) and its packed
 // utility, writes the 32-bit key (kind << 31) | bits(value) of every entry
-// to keys[j][k] (values are >= 0, so key order is (kind, value) order), and
-// each block writes its FP64 column sums, its count of log jobs and its
-// weight-histogram counts.  k_feat_select, block j < m: column j's keys
-// from memory into LDS; the nearest-rank quantiles of each kind are the
-// keys of given global rank in that order, found by a radix select (4
+// to keys[j][k] (values are >= 0, so key order is (kind, value) order and
+// the low 31 bits are the value), and each block writes its count of log
+// jobs and its weight-histogram counts.  k_feat_select, block j < m: column
+// j's keys from memory into LDS; the nearest-rank quantiles of each kind are
+// the keys of given global rank in that order, found by a radix select (4
 // passes of 8 bits, all six ranks at once) instead of a full sort; the
-// column's partial sums in block order give its mean.  Block m: the weight
-// histograms from the block counts.
+// column's mean is the FP64 sum of the values the keys hold (each thread its
+// keys in order, then waves and the block in a fixed order).  Block m: the
+// weight histograms from the block counts.
 constexpr int FEAT_GATHER_THREADS = 64;
 constexpr int FEAT_GATHER_BLOCKS = FEAT_SAMPLE / FEAT_GATHER_THREADS;
 
 // Layout of the features scratch (ctx->feat_ws): keys [64][FEAT_SAMPLE],
-// then per gather block m FP64 column sums (stride 64), one log-job count
-// and 16 histogram counts.
+// then per gather block one log-job count and 16 histogram counts.
 constexpr size_t FEAT_KEYS_BYTES = sizeof(unsigned) * 64 * FEAT_SAMPLE;
-constexpr size_t FEAT_SUMS_BYTES = sizeof(double) * 64 * FEAT_GATHER_BLOCKS;
 constexpr size_t FEAT_CNT_BYTES = sizeof(int) * 17 * FEAT_GATHER_BLOCKS;
-constexpr size_t FEAT_WS_BYTES = FEAT_KEYS_BYTES + FEAT_SUMS_BYTES + FEAT_CNT_BYTES;
+constexpr size_t FEAT_WS_BYTES = FEAT_KEYS_BYTES + FEAT_CNT_BYTES;
 
 __global__ void __launch_bounds__(FEAT_GATHER_THREADS) k_feat_gather(
     const float* __restrict__ T, const float2* __restrict__ prm, int64_t n, int m,
-    unsigned* __restrict__ keys, double* __restrict__ sums, int* __restrict__ cnts)
+    unsigned* __restrict__ keys, int* __restrict__ cnts)
 {
-    __shared__ double cs[64][FEAT_GATHER_THREADS / 64 + 1];
     __shared__ int hc[17];
     const int S = (int)(n < FEAT_SAMPLE ? n : FEAT_SAMPLE);
     const int tid = threadIdx.x;
@@ -247,23 +245,12 @@ __global__ void __launch_bounds__(FEAT_GATHER_THREADS) k_feat_gather(
         // -0 and +0 share a key
         const unsigned bits = v == 0.f ? 0u : __float_as_uint(v);
         if (on) keys[(int64_t)j * FEAT_SAMPLE + k] = (kind << 31) | (bits & 0x7fffffffu);
-        // the block's column sum, lanes in order (wave sum by butterfly)
-        double s = (double)v;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if ((tid & 63) == 0) cs[j][tid >> 6] = s;
     }
     __syncthreads();
-    if (tid < m) {
-        double s = 0.0;
-        for (int w = 0; w < FEAT_GATHER_THREADS / 64; ++w) s += cs[tid][w];
-        sums[(int64_t)blockIdx.x * 64 + tid] = s;
-    }
     if (tid < 17) cnts[blockIdx.x * 17 + tid] = hc[tid];
 }
 
 __global__ void __launch_bounds__(1024) k_feat_select(const unsigned* __restrict__ keys,
-                                                      const double* __restrict__ sums,
                                                       const int* __restrict__ cnts, int64_t n,
                                                       int m, const double* __restrict__ R,
                                                       float* __restrict__ feat)
@@ -272,7 +259,7 @@ __global__ void __launch_bounds__(1024) k_feat_select(const unsigned* __restrict
     __shared__ unsigned hist[2][6][256];
     __shared__ unsigned tpre[6], trank[6];
     __shared__ int tvalid[6], n0s;
-    __shared__ double colsum;
+    __shared__ double wsum[16];
     const int S = (int)(n < FEAT_SAMPLE ? n : FEAT_SAMPLE);
     const int nb = (S + FEAT_GATHER_THREADS - 1) / FEAT_GATHER_THREADS;
     const int tid = threadIdx.x;
@@ -298,30 +285,25 @@ __global__ void __launch_bounds__(1024) k_feat_select(const unsigned* __restrict
             const int k = tid + 1024 * u;
             v[u] = k < S ? keys[(int64_t)j * FEAT_SAMPLE + k] : 0u;
         }
+        double cs = 0.0;
 #pragma unroll
         for (int u = 0; u < FEAT_SAMPLE / 1024; ++u) {
             const int k = tid + 1024 * u;
             if (k < S) key[k] = v[u];
-        }
-    }
-    // wave 0: the number of log jobs and the column sum over the gather
-    // blocks (lanes stride over the blocks, then a butterfly: a fixed order)
-    if (wv == 0) {
-        int c = 0;
-        double cs = 0.0;
-        for (int b = lane; b < nb; b += 64) {
-            c += cnts[b * 17 + 16];
-            cs += sums[(int64_t)b * 64 + j];
+            cs += (double)__uint_as_float(v[u] & 0x7fffffffu);  // 0 past S
         }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            c += __shfl_xor(c, off);
-            cs += __shfl_xor(cs, off);
-        }
-        if (lane == 0) {
-            n0s = c;
-            colsum = cs;
-        }
+        for (int off = 32; off > 0; off >>= 1) cs += __shfl_xor(cs, off);
+        if (lane == 0) wsum[wv] = cs;
+    }
+    // wave 0: the number of log jobs (lanes stride over the gather blocks,
+    // then a butterfly)
+    if (wv == 0) {
+        int c = 0;
+        for (int b = lane; b < nb; b += 64) c += cnts[b * 17 + 16];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        if (lane == 0) n0s = c;
     }
     __syncthreads();
     if (tid == 0) {
@@ -407,6 +389,8 @@ __global__ void __launch_bounds__(1024) k_feat_select(const unsigned* __restrict
         for (int t = 0; t < 6; ++t)
             feat[8 * j + t] = tvalid[t] ? __uint_as_float(tpre[t] & 0x7fffffffu) : 0.f;
         feat[8 * j + 6] = (float)(R[j] / (double)n);
+        double colsum = 0.0;
+        for (int w = 0; w < 16; ++w) colsum += wsum[w];
         const double mean = colsum / (double)S;
         feat[8 * j + 7] = (float)log(mean > 1e-30 ? mean : 1e-30);
     }
@@ -583,14 +567,13 @@ ra_status features_into(ra_problem* P, float* feat)
     if (!ctx->feat_ws) RA_HIP(ctx, hipMalloc(&ctx->feat_ws, FEAT_WS_BYTES));
     char* ws = static_cast<char*>(ctx->feat_ws);
     unsigned* keys = reinterpret_cast<unsigned*>(ws);
-    double* sums = reinterpret_cast<double*>(ws + FEAT_KEYS_BYTES);
-    int* cnts = reinterpret_cast<int*>(ws + FEAT_KEYS_BYTES + FEAT_SUMS_BYTES);
+    int* cnts = reinterpret_cast<int*>(ws + FEAT_KEYS_BYTES);
     const int S = (int)std::min<int64_t>(P->n, FEAT_SAMPLE);
     const int nb = (S + FEAT_GATHER_THREADS - 1) / FEAT_GATHER_THREADS;
     k_feat_gather<<<nb, FEAT_GATHER_THREADS, 0, ctx->stream>>>(
         static_cast<const float*>(P->T), static_cast<const float2*>(P->prm), P->n, P->m, keys,
-        sums, cnts);
-    k_feat_select<<<P->m + 1, 1024, 0, ctx->stream>>>(keys, sums, cnts, P->n, P->m, P->Rdev,
+        cnts);
+    k_feat_select<<<P->m + 1, 1024, 0, ctx->stream>>>(keys, cnts, P->n, P->m, P->Rdev,
                                                       feat);
     RA_HIP(ctx, hipGetLastError());
     return RA_OK;
