@@ -85,10 +85,12 @@ def test_forward_and_gradients_match_fp64(ctx, torch, D, H, O, B):
     net.close()
 
 
-@pytest.mark.parametrize("H", [256, 33])
+@pytest.mark.parametrize("H", [256, 33, 6200])
 def test_predicted_prices_match_fp64(ctx, torch, H):
-    """ra_predict_prices (features, then the single-row forward kernel) against
-    the FP64 network on the same feature row."""
+    """ra_predict_prices (features, then the single-row forward kernel, or for a
+    network whose activations do not fit its LDS budget, H = 6200, the batched
+    forward and a copy to the host) against the FP64 network on the same
+    feature row."""
     m = 16
     D = 8 * m + 16
     I = synth.warmstart_instance(50000, m=m, seed=777)
@@ -98,7 +100,9 @@ def test_predicted_prices_match_fp64(ctx, torch, H):
     p = pr.predict_prices(net)
     yref, _ = om.forward(params.astype(np.float64), D, H, m, norm, f[None, :])
     assert np.all(p > 0)
-    assert np.allclose(np.log(p), yref[0], rtol=1e-5, atol=1e-5 * np.abs(yref).max())
+    # FP32 dot products of length H: the rounding of a sum grows like sqrt(H)
+    tol = 1e-5 * max(1.0, np.sqrt(H / 256.0))
+    assert np.allclose(np.log(p), yref[0], rtol=tol, atol=tol * np.abs(yref).max())
     # the batched forward path gives the same outputs
     yb = net.forward(torch.from_numpy(f[None, :]).cuda()).cpu().numpy()[0]
     assert np.allclose(yb, np.log(p), rtol=1e-5, atol=1e-5 * np.abs(yref).max())
