@@ -428,8 +428,10 @@ ra_status ra_solve_learned(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp,
 /* The starting prices ra_solve_learned would use: p_out[j] = exp(y_j), y the
  * network's de-standardised output on the problem's features (ra_features).
  * p_out: host, m doubles.  Same requirements as ra_solve_learned; blocks
- * until the prices are on the host.  Errors: RA_EINVAL, RA_EUNSUPPORTED,
- * RA_EDEVICE. */
+ * until the prices are on the host (the network's forward writes them to
+ * pinned host memory the network owns and raises a flag there, so calls
+ * with one network must not overlap; ra_solve_learned uses the same path).
+ * Errors: RA_EINVAL, RA_EUNSUPPORTED, RA_EDEVICE. */
 ra_status ra_predict_prices(ra_ctx *ctx, const ra_problem *prob, ra_mlp *mlp, double *p_out);
 
 /* Measurement aid: the mean time (ms) of one plain streaming read of `bytes`
