@@ -229,6 +229,19 @@ def warmstart_run(args):
                        warm_stall_restarts=args.warm_stall_restarts,
                        warm_stall_evals=args.warm_stall_evals, near_sigma=0.03, log=log)
     s = ws.summarize(rows)
+    # the prediction's own cost (inside every learned solve's time): host-timed
+    # median of 50 calls on one evaluation-size instance
+    import synth
+    T, w, c, kind, R = synth.warmstart_device(args.eval_n, m, seed=synth_seed(200000))
+    pr = ra.Problem(ctx, T, w, c, kind, R, 1e-3, validate=False)
+    for _ in range(10):
+        pr.predict_prices(net)
+    pts = []
+    for _ in range(50):
+        t1 = time.perf_counter()
+        pr.predict_prices(net)
+        pts.append(time.perf_counter() - t1)
+    pr.close()
     out = {
         "metric": "time to a 1e-4 relative gap, learned warm start vs cold start (also 1e-3 and "
                   "max(1e-6, 1.5 floor) in summary)",
@@ -262,6 +275,7 @@ def warmstart_run(args):
                        args.stall_evals),
         },
         "summary": s,
+        "prediction_us": float(np.median(pts) * 1e6),
         "training": dict(tinfo, data_seconds=t_data,
                          train_gap_median=float(np.median(gaps))),
     }
@@ -277,13 +291,14 @@ def bench_warmstart(args):
 
 
 def warmstart_digest(res):
-    """The learned-start figures the default benchmark line carries: per gap
-    level, warm-vs-cold speedup in total time, instances reaching the target
-    per arm, median passes, fallback rate."""
+    """The learned-start figures the default benchmark line carries: the
+    prediction's cost and, per gap level, warm-vs-cold speedup in total time,
+    instances reaching the target per arm, median passes, fallback rate."""
     s = res["summary"]
     out = {"workload": res["config"]["workload"], "stop": res["config"]["stop"],
            "fallback": res["config"]["fallback"],
-           "floor_median": s["floor_median"], "floor_any_median": s.get("floor_any_median")}
+           "floor_median": s["floor_median"], "floor_any_median": s.get("floor_any_median"),
+           "prediction_us": res.get("prediction_us")}
     for lv in ("0.001", "0.0001", "floor", "floor_any"):
         L = s[lv]
         out["to_" + lv] = {
